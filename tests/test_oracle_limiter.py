@@ -1,0 +1,138 @@
+"""Pins of the oracle's limiter (Sec. 3.3, Eq. (9)-(11)) against mathematics it must satisfy."""
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as L
+
+from workloads import gen
+
+
+def onestep_cfg(orc, order_p=3, gamma=1.2, q=50.0):
+    case, _ = gen.case_c2(E=16, order_p=order_p, length=16.0, shock_x=4.0, n_pe=2, k_pre=1.0)
+    case["physics"]["gamma"] = gamma
+    case["physics"]["q_heat"] = q
+    return orc.Config(case)
+
+
+@pytest.mark.parametrize("np_", [1, 2, 3, 4])
+def test_beta_matrix_against_polynomial_integration(orc, np_):
+    """Eq. (10) mapped to xi: B_ab = sum_s 2^(2s-1) int P_a^(s) P_b^(s); integrate with numpy."""
+    M = np_ + 1
+    B = np.zeros(M * M)
+    orc.lib().or_beta_matrix(np_, orc._dptr(B))
+    B = B.reshape(M, M)
+    ref = np.zeros((M, M))
+    for a in range(M):
+        for b in range(M):
+            for s in range(1, np_ + 1):
+                pa = L.legder(np.eye(M)[a], s)
+                pb = L.legder(np.eye(M)[b], s)
+                prod = L.legmul(pa, pb)
+                anti = L.legint(prod)
+                ref[a, b] += 2.0 ** (2 * s - 1) * (L.legval(1.0, anti) - L.legval(-1.0, anti))
+    np.testing.assert_allclose(B, ref, rtol=1e-13, atol=1e-15 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("np_", [1, 2, 3, 4])
+@pytest.mark.parametrize("side", [-1, 1])
+def test_translation_matrix(orc, np_, side):
+    """The neighbour polynomial re-expanded in the cell: evaluate both forms at random points."""
+    M = np_ + 1
+    T = np.zeros(M * M)
+    orc.lib().or_translation(np_, side, orc._dptr(T))
+    T = T.reshape(M, M)
+    rng = np.random.default_rng(3)
+    c = rng.normal(size=M)
+    xi = rng.uniform(-1, 1, size=7)
+    direct = L.legval(xi - 2.0 * side, c)
+    moved = L.legval(xi, T @ c)
+    np.testing.assert_allclose(moved, direct, rtol=1e-12, atol=1e-12)
+
+
+def flux_jacobian_fd(orc, cfg, w, h=1e-6):
+    V = len(w)
+    A = np.zeros((V, V))
+    for j in range(V):
+        dw = np.zeros(V)
+        dw[j] = h * max(1.0, abs(w[j]))
+        fp = orc.call_vec("or_conv_flux", cfg, w + dw, nout=V)
+        fm = orc.call_vec("or_conv_flux", cfg, w - dw, nout=V)
+        A[:, j] = (fp - fm) / (2 * dw[j])
+    return A
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_eigenvectors_diagonalise_the_flux_jacobian(orc, seed):
+    """L A R = diag(u-a, u, u, u, u+a) with A from finite differences of f^c; L R = I."""
+    cfg = onestep_cfg(orc)
+    rng = np.random.default_rng(seed)
+    rho, u, p, yr = rng.uniform(0.5, 8), rng.uniform(-3, 6), rng.uniform(0.5, 40), rng.uniform(0, 1)
+    w = np.array(gen.onestep_conserved(np.array(rho), np.array(u), np.array(p), np.array(yr),
+                                       {"gamma": 1.2, "q_heat": 50.0}), dtype=float)
+    V = 5
+    Lm = np.zeros(V * V)
+    Rm = np.zeros(V * V)
+    rc = orc.lib().or_char_matrices(cfg.ref(), orc._dptr(w), orc._dptr(Lm), orc._dptr(Rm))
+    assert rc == 0
+    Lm, Rm = Lm.reshape(V, V), Rm.reshape(V, V)
+    np.testing.assert_allclose(Lm @ Rm, np.eye(V), atol=1e-12)
+    A = flux_jacobian_fd(orc, cfg, w)
+    a = np.sqrt(1.2 * p / rho)
+    lam = np.diag([u - a, u, u, u, u + a])
+    scale = abs(u) + a
+    np.testing.assert_allclose(Lm @ A @ Rm, lam, atol=1e-6 * scale)
+
+
+def run_limiter_once(orc, case, w0):
+    """Run one step with dt = 0 so only the limiter acts (three times, once per stage)."""
+    case = dict(case)
+    case["disc"] = dict(case["disc"], dt=0.0)
+    s = orc.OracleSolver(case, w0, 4)
+    s.step(1)
+    return s.state(), s.flags(), s.total_flags()
+
+
+def test_limiter_preserves_means_and_flags_the_jump(orc):
+    case, w0 = gen.case_c2(E=64, order_p=3, length=8.0, shock_x=4.0, n_pe=4, k_pre=0.0, mode="sync")
+    rng = np.random.default_rng(1)
+    w0 = w0 * (1 + 0.01 * rng.uniform(size=w0.shape) * (np.arange(4) > 0))  # some wiggles
+    w0 = gen._fix_density_modes(w0)
+    w, flags, total = run_limiter_once(orc, case, w0)
+    assert flags[31] or flags[32], "cells next to the jump must be troubled"
+    assert total > 0
+    np.testing.assert_allclose(w[:, :, 0], w0[:, :, 0], rtol=1e-13, atol=1e-13)
+    # sum_i rho Y_i = rho survives the characteristic limiting, mode by mode
+    np.testing.assert_allclose(w[:, 3:, :].sum(1), w[:, 0, :], rtol=1e-12, atol=1e-12)
+
+
+def test_limiter_is_identity_on_smooth_data(orc):
+    case, w0 = gen.case_c0(E=64, order_p=3)
+    case["disc"]["limiter"] = 1
+    case["disc"]["bc"] = "periodic"
+    case["async"]["mode"] = "sync"
+    w, flags, total = run_limiter_once(orc, case, w0)
+    assert total == 0
+    np.testing.assert_allclose(w, w0, rtol=4e-16, atol=4e-16 * np.abs(w0).max())  # dt = 0: RK weights only
+
+
+def test_weno_reproduces_a_global_polynomial(orc):
+    """If the three stencil polynomials are one global polynomial, the WENO result is that polynomial."""
+    E, np_ = 12, 3
+    case, _ = gen.case_c0(E=E, order_p=np_)
+    case["disc"].update(limiter=1, bc="periodic", x_right=float(E))
+    case["async"]["mode"] = "sync"
+    phys = case["physics"]
+
+    def fn(x):
+        rho = 2.0 + 0.01 * x + 0.002 * x**2
+        return gen.onestep_conserved(rho, 0.5, 1.0 + 0.001 * x**3 / 100.0, 0.7, phys)
+
+    w0 = gen._fix_density_modes(gen.project(fn, E, np_, 0.0, float(E)))
+    # force every interior cell to be limited: use the WENO routine on each stencil directly
+    cfg = orc.Config(case)
+    V, M = 5, np_ + 1
+    for e in range(1, E - 1):
+        out = np.zeros(V * M)
+        args = [np.ascontiguousarray(w0[e + d]) for d in (-1, 0, 1)]
+        rc = orc.lib().or_weno_cell(cfg.ref(), *[orc._dptr(a) for a in args], orc._dptr(out))
+        assert rc == 0
+        np.testing.assert_allclose(out.reshape(V, M), w0[e], rtol=1e-11, atol=1e-11)
