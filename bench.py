@@ -1,0 +1,206 @@
+"""Benchmark of one ADG time step (three SSP-RK3 stages, every hot-path step) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c2]
+
+A "step" is one full SSP-RK3 time step: three fused stage launches (DG right-hand
+side, chemistry, AT fluxes at PE interfaces, RK update, history publish) plus,
+for the limited workload, the KXRCF/AT-WENO limiter after every stage.  The
+metric counts scalar DOF updates (E (N_p+1) (3+N_s) per stage) per second, with
+the inputs resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  The roofline object refers to the dominant kernel (the
+stage kernel): its average launch duration is measured with HIP events that the
+library records on the solver's stream around every launch (adg_profile).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s per RK stage (plain vs batched mixed); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def workload(name: str):
+    from workloads import gen
+
+    if name == "c0":
+        case, w0 = gen.case_c0()
+    elif name == "c1":
+        case, w0 = gen.case_c1()
+    elif name == "c2":
+        case, w0 = gen.case_c2()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return case, w0
+
+
+def euler_stage_bytes(case) -> float:
+    """Algorithmic HBM bytes of one stage launch, averaged over the three stages:
+    stage 1 reads w^n and writes w^(1) (16 B/DOF); stages 2 and 3 read w^n and
+    w^(s) and write w^(s+1) (24 B/DOF)."""
+    from workloads import gen
+
+    return gen.dof(case) * 8.0 * (2 + 3 + 3) / 3.0
+
+
+def detailed_stage_flops(case) -> float:
+    """Algorithmic FP64 operations of one detailed-chemistry stage launch (count of
+    +, -, *, / and one per exp/log/pow), from the formulas evaluated per element:
+
+      per quadrature node (Q = N_p+1 per element) and per face trace (2 per element):
+        temperature Newton, 4 iterations x Ns x (cp, h polynomials: 20)       = 80 Ns
+        primitives, pressure, sound speed                                      = 10 + 4 Ns
+        diffusive flux (gradients, transport law, heat flux)                   = 30 + 8 Ns
+        convective flux                                                        = 4 + Ns
+      per quadrature node only (chemistry):
+        Gibbs energies 14 Ns, rates 21 reactions x (2 exp + 12)                = 14 Ns + 14 Nr
+        species production 2 Nr Ns
+      per element: modal->nodal interpolation 2 M (Q+2) V, LDG gradient 4 M M V,
+        nodal->modal projection 2 M Q (V + Ns), lift + RK 8 M V
+      per face: Rusanov 6 V + 8, central diffusive average 2 V
+    """
+    d = case["disc"]
+    E, M = d["n_elem"], d["order_p"] + 1
+    Q = M
+    ns = case["physics"]["n_species"]
+    nr = case["physics"]["mech"]["n_reactions"]
+    V = 3 + ns
+    point = 80 * ns + (10 + 4 * ns) + (30 + 8 * ns) + (4 + ns)
+    chem = 14 * ns + 14 * nr + 2 * nr * ns
+    elem = 2 * M * (Q + 2) * V + 4 * M * M * V + 2 * M * Q * (V + ns) + 8 * M * V
+    face = 6 * V + 8 + 2 * V
+    return float(E * ((Q + 2) * point + Q * chem + elem + face))
+
+
+def src_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2501_01747_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name: str, kernel_src: list[str]):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None when
+    missing or taken on a different version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"kernel_src_sha:\s*([0-9a-f]+)", txt)
+    if not m or not h or h.group(1) != src_hash(kernel_src):
+        return None
+    return float(m.group(1))
+
+
+def cpu_baseline(case, w0, budget_s: float = 12.0):
+    """The oracle as it stands, single thread, on the same workload from the same
+    initial state: as many whole time steps as fit in about `budget_s`."""
+    from oracle import oracle
+    from workloads import gen
+
+    oracle.build(force=not os.path.exists(oracle._LIB_PATH))
+    cap = 100000
+    s = oracle.OracleSolver(case, w0, cap)
+    t0 = time.perf_counter()
+    steps = 0
+    chunk = 1
+    while True:
+        s.step(chunk)
+        steps += chunk
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps + chunk * 2 > cap:
+            break
+        if el < budget_s / 8:
+            chunk *= 2
+    s.close()
+    rate = gen.dof(case) * 3 * steps / el
+    return {"value": rate, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} time steps of the same workload from the same initial state "
+                      f"({el:.1f} s, single thread, gcc -O2)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--graph", type=int, default=10, help="time steps per captured HIP graph (0 = plain launches)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    torch.cuda.set_device(0)
+    case, w0 = workload(args.workload)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    if args.graph:
+        s.set_graph(args.graph)
+    s.step(args.warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.sync()
+    dof = gen.dof(case)
+    value = dof * 3 * args.steps / el
+    ms_per_step = el * 1e3 / args.steps
+
+    # dominant kernel: the stage kernel, timed per launch with HIP events on the solver's stream
+    prof = s.profile(max(10, min(args.steps, 50)))
+    stage_ms = prof["stage"][0]
+    detailed = case["physics"]["model"] == "detailed"
+    kernel_src = ["adg_ns.hip", "adg_ns.hpp"] if detailed else ["adg_euler.hip", "adg_device.hpp"]
+    if detailed:
+        flops = detailed_stage_flops(case)
+        achieved = flops / (stage_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": read_traffic(args.workload, kernel_src),
+                "kernel": "ns_stage_kernel", "launch_ms": stage_ms, "flops_per_launch": flops}
+    else:
+        nbytes = euler_stage_bytes(case)
+        achieved = nbytes / (stage_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(args.workload, kernel_src),
+                "kernel": "euler_stage_kernel", "launch_ms": stage_ms, "bytes_per_launch": nbytes}
+    d = case["disc"]
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": case["name"], "n_elem": d["n_elem"], "order_p": d["order_p"],
+                   "n_vars": 3 + case["physics"]["n_species"], "n_pe": case["async"]["n_pe"],
+                   "delays": case["async"]["mode"], "dof": dof, "graph_steps": args.graph},
+        "roofline": roof,
+        "kernel_ms": {k: v[0] for k, v in prof.items()},
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, w0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

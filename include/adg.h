@@ -1,0 +1,178 @@
+/*
+ * adg.h — C ABI of the MI355X (gfx950) asynchronous discontinuous Galerkin solver.
+ *
+ * The solver advances the 1D compressible reacting-flow equations of
+ * Arumugam & Aditya, "An asynchronous discontinuous Galerkin method for
+ * combustion simulations" (arXiv 2501.01747):
+ *   dw/dt + df^c/dx = df^d/dx + s                       Sec. 2, Eq. (1)-(3)
+ * with a Legendre-modal DG discretisation (Sec. 3.1, Eq. (4)-(6)), local
+ * Lax-Friedrichs or HLLC fluxes, LDG diffusion, three-stage SSP Runge-Kutta
+ * time stepping, and the asynchronous machinery of Sec. 3.2-4: the domain is
+ * split into emulated processing elements (PEs); at PE interfaces the flux is
+ * the asynchrony-tolerant (AT) flux of Eq. (7) built from the synchronous
+ * fluxes of past time levels with the weights of Eq. (8); delays follow the
+ * CAA (Sec. 4.1) or SAA (Sec. 4.2) model.  The optional limiter is the
+ * KXRCF-indicated characteristic WENO of Eq. (9)-(10) with the AT neighbour
+ * data of Eq. (11) across delayed PE interfaces.
+ *
+ * Conventions of the whole ABI
+ *   * Every call returns adg_status (0 = ADG_OK, negative = error); nothing
+ *     aborts or throws across the ABI.  adg_last_error() gives a message.
+ *   * State arrays exchanged with the caller are FP64 modal coefficients in the
+ *     layout w[e][v][j]: element e (0..E-1), conserved variable v
+ *     (rho, rho u, rho E, rho Y_1 .. rho Y_Ns; V = 3 + Ns), Legendre mode j
+ *     (0..N_p, basis normalised with P_j(1) = 1).
+ *   * The library allocates no device memory.  The caller passes one device
+ *     workspace of adg_workspace_bytes() bytes (e.g. a torch tensor); it must
+ *     stay alive and unmodified until adg_destroy().  All kernels run on the
+ *     caller's HIP stream (hipStream_t passed as void*).
+ *   * Errors detected on the device (non-physical state: rho <= 0, p <= 0,
+ *     non-finite, Newton failure for the temperature) are latched in a device
+ *     flag and reported as ADG_ERR_STATE by the next synchronising call
+ *     (adg_get_state, adg_sync).
+ *   * Calls on one solver must not overlap; different solvers are independent.
+ */
+#ifndef ADG_H
+#define ADG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t adg_status;
+#define ADG_OK 0
+#define ADG_ERR_ARG (-1)         /* inconsistent or unsupported argument values */
+#define ADG_ERR_NOMEM (-2)       /* workspace too small */
+#define ADG_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define ADG_ERR_STATE (-4)       /* non-physical state detected on the device */
+#define ADG_ERR_UNSUPPORTED (-5) /* valid but not implemented combination */
+
+enum { ADG_ONESTEP = 0, ADG_DETAILED = 1 };
+enum { ADG_PERIODIC = 0, ADG_TRANSMISSIVE = 1 };
+enum { ADG_RUSANOV = 0, ADG_HLLC = 1 };
+enum { ADG_SYNC = 0, ADG_CAA = 1, ADG_SAA = 2, ADG_SCHEDULE = 3 };
+enum { ADG_HOST = 0, ADG_DEVICE = 1 };
+
+/* Detailed reaction mechanism (Sec. 2: mass-action kinetics with species
+   molecular weights W_i and molar production rates omega_i).  Reversible
+   reactions: k_f = A T^b exp(-Ea/(Ru T)), k_r = k_f / K_c with
+   K_c = exp(-Delta G/(Ru T)) (p_ref/(Ru T))^(sum nu).  Thermo: NASA
+   7-coefficient polynomials, one temperature range.  Transport: viscosity
+   mu = mu_ref (T/T_ref)^mu_exp, conductivity k = mu cp/Pr, unit Lewis number.
+   All arrays are read during adg_create only. */
+typedef struct adg_mechanism {
+  int32_t n_species, n_reactions;
+  const double *W;        /* [Ns] kg/mol */
+  const double *nasa7;    /* [Ns][7] */
+  const int32_t *nu_f;    /* [Nr][Ns] reactant coefficients (0, 1 or 2) */
+  const int32_t *nu_r;    /* [Nr][Ns] product coefficients */
+  const double *A, *b, *Ea; /* [Nr] SI units, Ea in J/mol */
+  double Ru, p_ref;       /* J/(mol K), Pa */
+  double mu_ref, T_ref, mu_exp, prandtl;
+  double T_guess;         /* start of the Newton iteration for T(e) */
+} adg_mechanism;
+
+/* Governing equations, Sec. 2. */
+typedef struct {
+  int32_t model;          /* ADG_ONESTEP: nondimensional reactive Euler (R = 1), species (R, P),
+                                rho E = rho u^2/2 + p/(gamma-1) + q_heat rho Y_R,
+                                source W omega = -+ k_pre rho Y_R exp(-e_act/T), T = p/rho.
+                             ADG_DETAILED: mixture of Ns thermally perfect species with the
+                                mechanism `mech`; viscous = 1 adds the Navier-Stokes terms. */
+  int32_t n_species;      /* Ns (2 for ADG_ONESTEP, 9 for ADG_DETAILED in this build) */
+  int32_t viscous;
+  double gamma, q_heat, e_act, k_pre;
+  const adg_mechanism *mech;
+} adg_physics;
+
+/* Discretisation, Sec. 3.1. */
+typedef struct {
+  int32_t order_p;        /* N_p, polynomial degree: 1..4 */
+  int32_t n_quad;         /* Gauss-Legendre points per element: 0 = N_p + 1 (only value supported) */
+  int32_t n_elem;         /* N_E >= 1 */
+  double x_left, x_right;
+  int32_t bc;             /* ADG_PERIODIC | ADG_TRANSMISSIVE (ghost trace = interior trace) */
+  int32_t flux;           /* ADG_RUSANOV | ADG_HLLC (HLLC with ADG_ONESTEP only) */
+  int32_t limiter;        /* 1 = KXRCF + characteristic (AT-)WENO after every stage (ADG_ONESTEP) */
+  double weno_gamma[3];   /* linear weights of Eq. (10) */
+  double weno_eps;        /* epsilon of Eq. (10) */
+  double dt;              /* fixed time step (> 0); the AT weights of Eq. (8) assume it constant */
+} adg_discretization;
+
+/* Emulated PEs and delay model, Sec. 3.2 and 4. */
+typedef struct {
+  int32_t n_pe;           /* P, 1 <= P <= N_E */
+  const int32_t *pe_offsets; /* [P+1] first element of each PE (host), or NULL = floor(p E / P) */
+  int32_t mode;           /* ADG_SYNC | ADG_CAA (k = n mod L) | ADG_SAA | ADG_SCHEDULE */
+  int32_t L;              /* number of admissible delays, k in {0 .. L-1}; 1 <= L <= 8 */
+  const double *pmf;      /* [L] SAA probabilities (host); must sum to 1 within 1e-12 */
+  uint64_t seed;          /* SAA: counter-based SplitMix64 draw per (step, interface) */
+  const int8_t *schedule; /* ADG_SCHEDULE: [schedule_steps][n_if] delays (host), period schedule_steps */
+  int32_t schedule_steps;
+  int32_t at_order;       /* q, number of levels in Eq. (7): 0 = N_p + 1; 1..6 */
+} adg_async;
+
+typedef struct adg_solver adg_solver;
+
+/* Device workspace needed for a problem (0 on invalid arguments). */
+size_t adg_workspace_bytes(const adg_physics *phys, const adg_discretization *disc, const adg_async *as);
+
+/* Validates the problem, lays out the workspace (256-byte aligned pointer
+   required), uploads constant tables and the mechanism, and returns a solver.
+   PE interfaces: the faces at pe_offsets[1..P-1], plus the periodic wrap face
+   (interface 0) when bc is periodic, so n_if = P (periodic) or P-1.
+   The state is undefined until adg_set_state(). */
+adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, const adg_async *as,
+                      void *device_workspace, size_t workspace_bytes, void *hip_stream,
+                      adg_solver **out);
+
+/* Replace the state by w ([E][V][M] FP64, `count` = E*V*M doubles) on the host
+   (where = ADG_HOST; synchronous copy) or on the device (ADG_DEVICE; enqueued).
+   Resets the step counter to 0, clears the history of past levels and the
+   device error flag. */
+adg_status adg_set_state(adg_solver *s, const double *w, int64_t count, int32_t where);
+
+/* Enqueue n_steps full SSP-RK3 time steps on the stream (asynchronous). */
+adg_status adg_step(adg_solver *s, int32_t n_steps);
+
+/* Copy the current state out ([E][V][M]).  Synchronises the stream and
+   returns ADG_ERR_STATE if the device latched a non-physical state. */
+adg_status adg_get_state(adg_solver *s, double *w, int64_t count, int32_t where);
+
+/* Synchronise the stream and report the device error flag. */
+adg_status adg_sync(adg_solver *s);
+
+/* Troubled-cell flags (int8 [E], host) of the last limited stage, and the
+   number of troubled cells summed over all limited stages since set_state. */
+adg_status adg_get_flags(adg_solver *s, int8_t *flags, int64_t *total);
+
+/* Number of completed time steps since adg_set_state (synchronises). */
+int64_t adg_step_count(adg_solver *s);
+
+/* Number of PE interfaces. */
+int32_t adg_n_interfaces(const adg_solver *s);
+
+/* Enqueue n_steps steps like adg_step and time every kernel launch with HIP
+   events on the solver's stream.  ms_out[i] receives the mean duration in ms
+   of kernel class i and launches_out[i] the launch count; n_classes is the
+   array length (classes: 0 stage kernel, 1 limiter, 2 limiter scatter,
+   3 step counter).  Synchronises. */
+adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *launches_out, int32_t n_classes);
+
+/* Use a captured HIP graph of `steps_per_graph` time steps for adg_step
+   (0 = plain launches, the default).  Takes effect at the next adg_step. */
+adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph);
+
+/* Release the solver (the caller's workspace is not freed). */
+void adg_destroy(adg_solver *s);
+
+const char *adg_last_error(const adg_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADG_H */

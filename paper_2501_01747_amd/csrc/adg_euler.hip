@@ -1,0 +1,506 @@
+// Fused SSP-RK3 stage kernel for the one-step reactive Euler model and the
+// KXRCF + characteristic (AT-)WENO limiter.
+//
+// Stage kernel (Sec. 3.1 Eq. (5), Sec. 3.2 Eq. (7)): one thread per element,
+// 256 elements per workgroup.  Each thread loads its element's modal DoFs from
+// the component planes (coalesced), forms both face traces, and publishes them
+// in LDS; the two tile-edge threads also load the neighbouring element of the
+// tile.  One numerical flux per face is computed from LDS; at PE-interface
+// faces the synchronous flux of this level is written to the history ring and
+// replaced by the AT combination of past levels.  The volume integral, the
+// source projection, the lift and the RK combination then run in registers and
+// the output is stored once.  HBM traffic per stage: read w^(s) (+ w^n for
+// stages 2 and 3), write w^(s+1).
+#include "adg_device.hpp"
+
+namespace adg {
+
+template <int M>
+__device__ __forceinline__ void traces(const double (&u)[5][M], double *wl, double *wr) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double sm = 0.0, sp = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      sp += u[v][j];
+      sm += (j & 1) ? -u[v][j] : u[v][j];
+    }
+    wl[v] = sm;
+    wr[v] = sp;
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void load_elem(const double *__restrict__ w, int E, int e, double (&u)[5][M]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int j = 0; j < M; ++j) u[v][j] = w[(size_t)(v * M + j) * E + e];
+}
+
+// Numerical flux at face f from its two traces; at PE interfaces the AT flux.
+template <int FLUX>
+__device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int f, const double *wm,
+                                          const double *wp, double *F) {
+  bool ok = numflux1<FLUX>(a.ph, wm, wp, F);
+  const int i = a.face_if[f];
+  if (i >= 0) {
+    double *rec = ring_rec(a.ring, n, a.stage, a.dl.nif, i) + a.ring.off_F;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) rec[v] = F[v];
+    const int k = eff_delay(a.dl, n, i);
+    if (k > 0) {
+      double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < a.dl.q; ++j) {
+        const double c = at_weight(a.dl.q, k, j);
+        const double *h = ring_rec(a.ring, n - k - j, a.stage, a.dl.nif, i) + a.ring.off_F;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] += c * h[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[v] = acc[v];
+    }
+  }
+  return ok;
+}
+
+template <int M, int FLUX>
+__global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
+  constexpr int V = 5, Q = M;
+  __shared__ double sR[kEulerBlock + 1][V];  // right trace of the element left of face t
+  __shared__ double sL[kEulerBlock + 1][V];  // left trace of the element right of face t
+  __shared__ double sF[kEulerBlock + 1][V];  // numerical flux at face e0 + t
+  const int t = threadIdx.x;
+  const int E = a.E;
+  const int e0 = blockIdx.x * kEulerBlock;
+  const int nloc = min(kEulerBlock, E - e0);
+  const bool act = t < nloc;
+  const int e = e0 + t;
+  const long long n = *a.step;
+  bool ok = true;
+
+  double u[V][M];
+  double wl[V], wr[V];
+  if (act) {
+    load_elem<M>(a.ws, E, e, u);
+    traces<M>(u, wl, wr);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      sR[t + 1][v] = wr[v];
+      sL[t][v] = wl[v];
+    }
+  }
+  if (t == 0) {
+    if (e0 == 0 && !a.periodic) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) sR[0][v] = wl[v];   // ghost = interior trace
+    } else {
+      double nb[V][M], tl[V], tr[V];
+      load_elem<M>(a.ws, E, e0 == 0 ? E - 1 : e0 - 1, nb);
+      traces<M>(nb, tl, tr);
+#pragma unroll
+      for (int v = 0; v < V; ++v) sR[0][v] = tr[v];
+    }
+  }
+  if (t == nloc - 1) {
+    if (e == E - 1 && !a.periodic) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) sL[nloc][v] = wr[v];
+    } else {
+      double nb[V][M], tl[V], tr[V];
+      load_elem<M>(a.ws, E, e == E - 1 ? 0 : e + 1, nb);
+      traces<M>(nb, tl, tr);
+#pragma unroll
+      for (int v = 0; v < V; ++v) sL[nloc][v] = tl[v];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    double F[V];
+    ok = face_flux<FLUX>(a, n, e, sR[t], sL[t], F) && ok;
+#pragma unroll
+    for (int v = 0; v < V; ++v) sF[t][v] = F[v];
+    if (t == nloc - 1) {
+      ok = face_flux<FLUX>(a, n, e + 1, sR[nloc], sL[nloc], F) && ok;
+#pragma unroll
+      for (int v = 0; v < V; ++v) sF[nloc][v] = F[v];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    double vol[V][M], srcR[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      srcR[j] = 0.0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) vol[v][j] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double wq[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc += u[v][j] * a.tb.B[q][j];
+        wq[v] = acc;
+      }
+      Prim1 pr;
+      ok = prim1(a.ph, wq, pr) && ok;
+      double f[V];
+      flux1(wq, pr, f);
+      const double rate = a.ph.k_pre * wq[3] * exp(-a.ph.e_act / pr.T);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const double g = a.tb.WG[q][j];
+#pragma unroll
+        for (int v = 0; v < V; ++v) vol[v][j] += g * f[v];
+        srcR[j] += a.tb.WB[q][j] * (-rate);
+      }
+    }
+    const double *Fl = sF[t], *Fr = sF[t + 1];
+    double out[V][M];
+    const bool st_last = a.stage == 2;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const double half2j1 = 0.5 * (2 * j + 1);
+        const double b = vol[v][j] + (-Fr[v] + ((j & 1) ? -Fl[v] : Fl[v]));
+        double s = 0.0;
+        if (v == 3) s = srcR[j];
+        if (v == 4) s = -srcR[j];
+        const double L = a.two_over_dx * (half2j1 * b) + half2j1 * s;
+        const double y = u[v][j] + a.dt * L;
+        double o;
+        if (a.stage == 0) {
+          o = y;
+        } else {
+          const double wn = a.w0[(size_t)(v * M + j) * E + e];
+          o = st_last ? (1.0 / 3.0) * wn + (2.0 / 3.0) * y : 0.75 * wn + 0.25 * y;
+        }
+        out[v][j] = o;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int j = 0; j < M; ++j) a.wout[(size_t)(v * M + j) * E + e] = out[v][j];
+    if (a.store_U) {
+      const int il = a.face_if[e], ir = a.face_if[e + 1];
+      if (il >= 0) {  // this element is right of interface il
+        double *rec = ring_rec(a.ring, n, a.stage, a.dl.nif, il) + a.ring.off_U + V * M;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int j = 0; j < M; ++j) rec[v * M + j] = out[v][j];
+      }
+      if (ir >= 0) {  // left of interface ir
+        double *rec = ring_rec(a.ring, n, a.stage, a.dl.nif, ir) + a.ring.off_U;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int j = 0; j < M; ++j) rec[v * M + j] = out[v][j];
+      }
+    }
+  }
+  if (!ok) atomicOr(a.err, (int)kErrState);
+}
+
+// ------------------------------------------------------------------- limiter
+
+// Characteristic left eigenvectors at the mean state (one-step model) and
+// R = L^-1 by Gauss-Jordan with partial pivoting.  Rows of L:
+//   (dp - rho a du)/(2a^2), drho - dp/a^2, d(rho Y_R) - Y_R drho,
+//   d(rho Y_R + rho Y_P - rho), (dp + rho a du)/(2a^2).
+__device__ bool char_matrices(const OneStep &ph, const double *wb, double (&Lm)[5][5], double (&Rm)[5][5]) {
+  Prim1 pr;
+  bool ok = prim1(ph, wb, pr);
+  const double rho = pr.rho, u = pr.u, a = pr.a, g1 = ph.gamma - 1.0;
+  const double dp[5] = {g1 * 0.5 * u * u, -g1 * u, g1, -g1 * ph.q_heat, 0.0};
+  const double du[5] = {-u / rho, 1.0 / rho, 0.0, 0.0, 0.0};
+  const double a2 = a * a;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double drho = c == 0 ? 1.0 : 0.0;
+    Lm[0][c] = (dp[c] - rho * a * du[c]) / (2.0 * a2);
+    Lm[1][c] = drho - dp[c] / a2;
+    Lm[4][c] = (dp[c] + rho * a * du[c]) / (2.0 * a2);
+  }
+  const double Y0 = wb[3] / rho;
+  Lm[2][0] = -Y0; Lm[2][1] = 0.0; Lm[2][2] = 0.0; Lm[2][3] = 1.0; Lm[2][4] = 0.0;
+  Lm[3][0] = -1.0; Lm[3][1] = 0.0; Lm[3][2] = 0.0; Lm[3][3] = 1.0; Lm[3][4] = 1.0;
+  double A[5][5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      A[r][c] = Lm[r][c];
+      Rm[r][c] = r == c ? 1.0 : 0.0;
+    }
+  for (int col = 0; col < 5; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 5; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (A[piv][col] == 0.0) return false;
+    if (piv != col)
+      for (int c = 0; c < 5; ++c) {
+        double x = A[col][c]; A[col][c] = A[piv][c]; A[piv][c] = x;
+        x = Rm[col][c]; Rm[col][c] = Rm[piv][c]; Rm[piv][c] = x;
+      }
+    const double p = A[col][col];
+    for (int c = 0; c < 5; ++c) { A[col][c] /= p; Rm[col][c] /= p; }
+    for (int r = 0; r < 5; ++r) {
+      if (r == col) continue;
+      const double f = A[r][col];
+      if (f == 0.0) continue;
+      for (int c = 0; c < 5; ++c) { A[r][c] -= f * A[col][c]; Rm[r][c] -= f * Rm[col][c]; }
+    }
+  }
+  return ok;
+}
+
+// Modal data of a neighbour: loaded from the unlimited stage output, the
+// AT combination of Eq. (11) from the history ring, or the constant ghost.
+template <int M>
+__device__ void neighbour_modes(const LimiterArgs &a, long long n, int e, int side, const double (&u)[5][M],
+                                double (&nb)[5][M]) {
+  const int E = a.E;
+  const bool ghost = !a.periodic && (side == 0 ? e == 0 : e == E - 1);
+  if (ghost) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int j = 0; j < M; ++j) nb[v][j] = j == 0 ? u[v][0] : 0.0;
+    return;
+  }
+  const int face = side == 0 ? e : e + 1;
+  const int i = a.face_if[face];
+  const int k = i >= 0 ? eff_delay(a.dl, n, i) : 0;
+  if (k > 0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int j = 0; j < M; ++j) nb[v][j] = 0.0;
+    // side 0: the neighbour is the element left of interface i (record slot 0)
+    const int off = a.ring.off_U + (side == 0 ? 0 : 5 * M);
+    for (int jj = 0; jj < a.dl.q; ++jj) {
+      const double c = at_weight(a.dl.q, k, jj);
+      const double *h = ring_rec(a.ring, n - k - jj, a.stage, a.dl.nif, i) + off;
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int j = 0; j < M; ++j) nb[v][j] += c * h[v * M + j];
+    }
+    return;
+  }
+  const int en = side == 0 ? (e == 0 ? E - 1 : e - 1) : (e == E - 1 ? 0 : e + 1);
+  load_elem<M>(a.w, E, en, nb);
+}
+
+template <int M>
+__device__ __forceinline__ double trace_at(const double (&c)[M], int side) {
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) s += (side == 0 && (j & 1)) ? -c[j] : c[j];
+  return s;
+}
+
+template <int M>
+__global__ __launch_bounds__(128) void limiter_kernel(LimiterArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.E) return;
+  const long long n = *a.step;
+  double u[5][M];
+  load_elem<M>(a.w, a.E, e, u);
+  double nbL[5][M], nbR[5][M];
+  neighbour_modes<M>(a, n, e, 0, u, nbL);
+  neighbour_modes<M>(a, n, e, 1, u, nbR);
+  const bool ghostL = !a.periodic && e == 0, ghostR = !a.periodic && e == a.E - 1;
+
+  // KXRCF: jumps at inflow faces against h^((N_p+1)/2) max_q |w(xi_q)|, on rho and rho E.
+  const double uL_e = trace_at<M>(u[1], 0) / trace_at<M>(u[0], 0);
+  const double uR_e = trace_at<M>(u[1], 1) / trace_at<M>(u[0], 1);
+  const double uL_n = ghostL ? uL_e : trace_at<M>(nbL[1], 1) / trace_at<M>(nbL[0], 1);
+  const double uR_n = ghostR ? uR_e : trace_at<M>(nbR[1], 0) / trace_at<M>(nbR[0], 0);
+  bool flag = false;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int v = t == 0 ? 0 : 2;
+    double jump = 0.0;
+    if (0.5 * (uL_e + uL_n) > 0.0 && !ghostL) jump += trace_at<M>(u[v], 0) - trace_at<M>(nbL[v], 1);
+    if (0.5 * (uR_e + uR_n) < 0.0 && !ghostR) jump += trace_at<M>(u[v], 1) - trace_at<M>(nbR[v], 0);
+    double norm = 0.0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      double val = 0.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) val += u[v][j] * a.tb.B[q][j];
+      norm = fmax(norm, fabs(val));
+    }
+    if (fabs(jump) / (a.kx_h * norm) > 1.0) flag = true;
+  }
+  a.flags[e] = flag ? 1 : 0;
+  if (!flag) return;
+  atomicAdd(a.flag_count, 1ull);
+
+  double wb[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) wb[v] = u[v][0];
+  double Lm[5][5], Rm[5][5];
+  if (!char_matrices(a.ph, wb, Lm, Rm)) atomicOr(a.err, (int)kErrState);
+  double wl[5][M];
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int j = 0; j < M; ++j) wl[v][j] = 0.0;
+  for (int c = 0; c < 5; ++c) {
+    double vc[M], vL[M], vR[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double x0 = 0.0, xl = 0.0, xr = 0.0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        x0 += Lm[c][v] * u[v][j];
+        xl += Lm[c][v] * nbL[v][j];
+        xr += Lm[c][v] * nbR[v][j];
+      }
+      vc[j] = x0; vL[j] = xl; vR[j] = xr;
+    }
+    // re-expand the neighbours in the cell's coordinate and reset their mean
+    double tL[M], tR[M];
+#pragma unroll
+    for (int k2 = 0; k2 < M; ++k2) {
+      double sl = 0.0, sr = 0.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        sl += a.Tl[k2][j] * vL[j];
+        sr += a.Tr[k2][j] * vR[j];
+      }
+      tL[k2] = sl; tR[k2] = sr;
+    }
+    tL[0] = vc[0];
+    tR[0] = vc[0];
+    double beta[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        beta[0] += tL[p] * a.Bm[p][r] * tL[r];
+        beta[1] += vc[p] * a.Bm[p][r] * vc[r];
+        beta[2] += tR[p] * a.Bm[p][r] * tR[r];
+      }
+    double wbar[3], sum = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const double d = a.eps + beta[s];
+      wbar[s] = a.gam[s] / (d * d);
+      sum += wbar[s];
+    }
+    const double om0 = wbar[0] / sum, om1 = wbar[1] / sum, om2 = wbar[2] / sum;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const double vl = om0 * tL[j] + om1 * vc[j] + om2 * tR[j];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) wl[v][j] += Rm[v][c] * vl;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int j = 0; j < M; ++j) a.wlim[(size_t)(v * M + j) * a.E + e] = wl[v][j];
+}
+
+// Writes the limited values of troubled cells back (after every stencil has read
+// the unlimited data).
+template <int M>
+__global__ __launch_bounds__(256) void limiter_scatter_kernel(LimiterArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.E || !a.flags[e]) return;
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const size_t idx = (size_t)(v * M + j) * a.E + e;
+      a.w[idx] = a.wlim[idx];
+    }
+}
+
+__global__ void advance_kernel(long long *step) { *step += 1; }
+
+// [E][VM] <-> [VM][E]
+__global__ void to_planes_kernel(const double *__restrict__ src, double *__restrict__ dst, int E, int VM) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)E * VM) return;
+  const int c = (int)(idx / E), e = (int)(idx % E);
+  dst[idx] = src[(long long)e * VM + c];
+}
+__global__ void from_planes_kernel(const double *__restrict__ src, double *__restrict__ dst, int E, int VM) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)E * VM) return;
+  const int e = (int)(idx / VM), c = (int)(idx % VM);
+  dst[idx] = src[(long long)c * E + e];
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <int M>
+static hipError_t stage_M(int flux, const EulerArgs &a, hipStream_t s) {
+  const int blocks = (a.E + kEulerBlock - 1) / kEulerBlock;
+  if (flux == 1) hipLaunchKernelGGL((euler_stage_kernel<M, 1>), dim3(blocks), dim3(kEulerBlock), 0, s, a);
+  else hipLaunchKernelGGL((euler_stage_kernel<M, 0>), dim3(blocks), dim3(kEulerBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, hipStream_t s) {
+  switch (M) {
+    case 2: return stage_M<2>(flux, a, s);
+    case 3: return stage_M<3>(flux, a, s);
+    case 4: return stage_M<4>(flux, a, s);
+    case 5: return stage_M<5>(flux, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s) {
+  const int blocks = (a.E + 127) / 128;
+  switch (M) {
+    case 2: hipLaunchKernelGGL(limiter_kernel<2>, dim3(blocks), dim3(128), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(limiter_kernel<3>, dim3(blocks), dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(limiter_kernel<4>, dim3(blocks), dim3(128), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(limiter_kernel<5>, dim3(blocks), dim3(128), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s) {
+  const int blocks = (a.E + 255) / 256;
+  switch (M) {
+    case 2: hipLaunchKernelGGL(limiter_scatter_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(limiter_scatter_kernel<3>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(limiter_scatter_kernel<4>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(limiter_scatter_kernel<5>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(long long *step, hipStream_t s) {
+  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(1), 0, s, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_planes(const double *src, double *dst, int E, int VM, hipStream_t s) {
+  const long long n = (long long)E * VM;
+  hipLaunchKernelGGL(to_planes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, E, VM);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_planes(const double *src, double *dst, int E, int VM, hipStream_t s) {
+  const long long n = (long long)E * VM;
+  hipLaunchKernelGGL(from_planes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, E, VM);
+  return hipGetLastError();
+}
+
+}  // namespace adg

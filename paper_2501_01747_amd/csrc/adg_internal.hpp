@@ -1,0 +1,109 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// ADG library.  Device state layout: component planes [v][j][e] (element index
+// fastest) so that a wavefront reading one (variable, mode) plane of 64
+// consecutive elements issues one fully coalesced 512-byte access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adg {
+
+constexpr int kMaxM = 5;      // N_p <= 4
+constexpr int kMaxQ = 5;      // Gauss points = N_p + 1
+constexpr int kMaxL = 8;      // admissible delays
+constexpr int kMaxAT = 6;     // AT order q
+constexpr int kEulerBlock = 256;
+
+// Delay model of Sec. 4 (CAA / SAA) and the start-up clamp k <= n - q + 1.
+struct DelayParams {
+  int mode;        // 0 sync, 1 CAA, 2 SAA, 3 schedule
+  int L;
+  int nif;
+  int q;
+  int sched_steps;
+  double cum[kMaxL];            // cumulative SAA probabilities (summed left to right)
+  unsigned long long seed;
+  const int8_t *sched;          // device [sched_steps][nif]
+};
+
+// History of past levels at PE interfaces: D slots (level n lives in slot n mod D),
+// 3 stages, nif interfaces; one record per (slot, stage, interface) of `rec` doubles:
+// [F: V][Wc: V][U_left: V*M][U_right: V*M]  (Wc only for LDG, U only with the limiter).
+struct RingParams {
+  double *base;
+  int D;
+  int rec;
+  int off_F, off_Wc, off_U;
+};
+
+__host__ __device__ inline double *ring_rec(const RingParams &r, long long level, int stage, int nif, int i) {
+  long long slot = level % r.D;
+  return r.base + ((slot * 3 + stage) * (long long)nif + i) * r.rec;
+}
+
+// Per-element constant tables (host-computed).
+struct Tables {
+  double B[kMaxQ][kMaxM];   // P_j(xi_q)
+  double WG[kMaxQ][kMaxM];  // w_q P_j'(xi_q)
+  double WB[kMaxQ][kMaxM];  // w_q P_j(xi_q)
+  double Dm[kMaxM][kMaxM];  // int P_j' P_k dxi (LDG volume term)
+};
+
+struct OneStep {
+  double gamma, q_heat, e_act, k_pre;
+};
+
+struct EulerArgs {
+  const double *w0;     // w^n (may alias wout at the last stage)
+  const double *ws;     // stage input w^(s)
+  double *wout;         // stage output (unlimited)
+  const int *face_if;   // [E+1] interface index of face f, or -1
+  const long long *step;
+  int *err;
+  int E;
+  int periodic;
+  int stage;
+  int store_U;          // publish boundary-element outputs for the limiter
+  double dt;
+  double two_over_dx;
+  OneStep ph;
+  DelayParams dl;
+  RingParams ring;
+  Tables tb;
+};
+
+struct LimiterArgs {
+  double *w;            // unlimited stage output, limited in place by the scatter pass
+  double *wlim;         // limited values of troubled cells
+  int8_t *flags;        // [E]
+  unsigned long long *flag_count;
+  const int *face_if;
+  const long long *step;
+  int *err;
+  int E;
+  int periodic;
+  int stage;
+  double kx_h;          // dx^((N_p+1)/2)
+  double gam[3];
+  double eps;
+  OneStep ph;
+  DelayParams dl;
+  RingParams ring;
+  Tables tb;
+  double Bm[kMaxM][kMaxM];    // smoothness-indicator quadratic form
+  double Tl[kMaxM][kMaxM];    // re-expansion of the left neighbour in the cell
+  double Tr[kMaxM][kMaxM];    // re-expansion of the right neighbour
+};
+
+enum ErrBits { kErrState = 1, kErrNewton = 2 };
+
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, hipStream_t s);
+hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s);
+hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s);
+hipError_t launch_advance(long long *step, hipStream_t s);
+hipError_t launch_to_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
+hipError_t launch_from_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
+
+}  // namespace adg

@@ -1,0 +1,146 @@
+"""GPU parity of the one-step reactive-Euler path (fused stage kernel, AT fluxes, limiter)
+against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def adg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_01747_amd import adg as lib
+
+    return lib
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def compare_run(adg, orc, case, w0, steps, every=None, tol=1e-10):
+    print(f"[parity] {case['name']} E={case['disc']['n_elem']} P={case['async']['n_pe']} "
+          f"mode={case['async']['mode']} steps={steps}", flush=True)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, steps + 1)
+    every = every or steps
+    done = 0
+    worst = 0.0
+    while done < steps:
+        k = min(every, steps - done)
+        s.step(k)
+        o.step(k)
+        done += k
+        r = rel_l2(s.state(), o.state())
+        worst = max(worst, r)
+        assert r < tol, (done, r)
+    assert s.step_count() == steps
+    s.close()
+    return worst
+
+
+@pytest.mark.parametrize("E,P", [(1, 1), (7, 3), (200, 5), (256, 8), (513, 7)])
+def test_c0_shape_small_sizes(adg, orc, E, P):
+    """Several tiles, a ragged tail, one-element PEs and a single element."""
+    case, w0 = gen.case_c0(E=E, n_pe=P, mode="saa")
+    compare_run(adg, orc, case, w0, 30, every=10)
+
+
+@pytest.mark.parametrize("order_p", [1, 2, 3, 4])
+@pytest.mark.parametrize("mode", ["sync", "caa", "saa"])
+def test_orders_and_delay_models(adg, orc, order_p, mode):
+    # Courant numbers inside the AT stability region for delays up to 2
+    cfl = {1: 0.2, 2: 0.1, 3: 0.04, 4: 0.02}[order_p]
+    case, w0 = gen.case_c0(E=300, order_p=order_p, n_pe=6, mode=mode, pmf=(0.5, 0.3, 0.2), cfl=cfl)
+    if mode == "caa":
+        case["async"]["L"] = 3
+    compare_run(adg, orc, case, w0, 40, every=20)
+
+
+def test_zero_delay_is_synchronous_on_gpu(adg):
+    case, w0 = gen.case_c0(E=300, n_pe=6, mode="sync")
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(25)
+    ref = s.state()
+    case0 = dict(case, **{"async": dict(case["async"], mode="saa", pmf=[1.0, 0.0], L=2)})
+    s0 = adg.Solver(case0)
+    s0.set_state(w0)
+    s0.step(25)
+    np.testing.assert_array_equal(s0.state(), ref)
+
+
+def test_worst_case_schedule(adg, orc):
+    """Every interface at the largest delay from the first step it is admissible."""
+    case, w0 = gen.case_c0(E=256, n_pe=8, mode="sync", cfl=0.1)
+    case["async"].update(mode="schedule", L=3, schedule=np.full((1, 8), 2, dtype=np.int8))
+    compare_run(adg, orc, case, w0, 40, every=10)
+
+
+def test_c0_full_config(adg, orc):
+    """The full C0 workload: E = 512, N_p = 2, 8 PEs, SAA delays in {0,1}, 500 steps."""
+    case, w0 = gen.case_c0()
+    worst = compare_run(adg, orc, case, w0, 500, every=100)
+    print(f"[parity] c0 full: worst rel L2 {worst:.3e}")
+
+
+def test_graph_replay_matches_plain_launches(adg):
+    case, w0 = gen.case_c0(E=700, n_pe=7, mode="saa")
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(30)
+    ref = s.state()
+    g = adg.Solver(case)
+    g.set_graph(10)
+    g.set_state(w0)
+    for _ in range(3):
+        g.step(10)
+        g.sync()
+    np.testing.assert_array_equal(g.state(), ref)
+    assert g.step_count() == 30
+
+
+@pytest.mark.parametrize("E", [64, 333])
+def test_limiter_path_small(adg, orc, E):
+    case, w0 = gen.case_c2(E=E, order_p=3, length=E / 32.0, shock_x=E / 64.0, n_pe=4, mode="saa")
+    s = adg.Solver(case)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, 40)
+    for k in range(4):
+        s.step(5)
+        o.step(5)
+        r = rel_l2(s.state(), o.state())
+        fg, tot = s.flags()
+        assert np.array_equal(fg, o.flags()), k
+        assert tot == o.total_flags()
+        assert r < 1e-10, (k, r)
+
+
+def test_device_state_roundtrip(adg):
+    import torch
+
+    case, w0 = gen.case_c0(E=130, n_pe=2, mode="sync")
+    s = adg.Solver(case)
+    wt = torch.from_numpy(w0).cuda()
+    s.set_state(wt)
+    out = torch.empty_like(wt)
+    s.state_device(out)
+    np.testing.assert_array_equal(out.cpu().numpy(), w0)
+
+
+def test_bad_state_is_reported(adg):
+    case, w0 = gen.case_c0(E=64, n_pe=2, mode="sync")
+    w0 = w0.copy()
+    w0[10, 2, 0] = 0.0  # rho E = 0 -> negative pressure
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(1)
+    with pytest.raises(adg.AdgError) as ei:
+        s.state()
+    assert ei.value.code == adg.ADG_ERR_STATE

@@ -360,7 +360,7 @@ def ignition_state(mech, x, Lx, T_mean=1000.0, T_amp=50.0, phase=0.0, p=P_ATM, u
 
 
 def case_c1(E=2048, order_p=3, steps=200, n_pe=16, mode="saa", pmf=(0.3, 0.4, 0.3), seed=2502,
-            Lx=0.01, cfl=0.12, at_order=0, mech=None, viscous=1, phase=0.0):
+            Lx=0.01, cfl=0.04, at_order=0, mech=None, viscous=1, phase=0.0):
     """Spontaneous-ignition shape: periodic 1 cm, p = 1 atm, u = 0, T = 1000 + 50 sin(2 pi x/Lx) K."""
     dx = Lx / E
     if mech is None:
