@@ -1,4 +1,4 @@
-// Detailed-chemistry Navier-Stokes stage kernel: declarations.
+// Detailed-chemistry Navier-Stokes stage kernel (LDG): declarations.
 #pragma once
 
 #include "adg.h"
@@ -6,23 +6,52 @@
 
 namespace adg {
 
+constexpr int kNsMaxSpecies = 9;
+constexpr int kNsMaxReactions = 32;
+
+// Mechanism in device memory, read with wave-uniform indices (scalar loads).
 struct NsMech {
-  int dummy;
+  int ns, nr;
+  double Ru, p_ref, T_guess;
+  double mu_ref, inv_T_ref, mu_exp, inv_prandtl;
+  double ln_p_over_Ru;              // ln(p_ref / Ru)
+  double W[kNsMaxSpecies], invW[kNsMaxSpecies], Ri[kNsMaxSpecies];
+  // NASA-7 in Horner-ready form, per species:
+  //   cv/R - ... : c0m1 = a0 - 1, a1 .. a4       (cp/R - 1)
+  //   (h - R T)/R = T (a0-1 + T (a1/2 + T (a2/3 + T (a3/4 + T a4/5)))) + a5
+  //   h/(R T) = a0 + T (a1/2 + ...) + a5 / T
+  //   s/R = a0 ln T + T (a1 + T (a2/2 + T (a3/3 + T a4/4))) + a6
+  double a[kNsMaxSpecies][7];
+  double h2[kNsMaxSpecies][4];      // a1/2, a2/3, a3/4, a4/5
+  double s2[kNsMaxSpecies][3];      // a2/2, a3/3, a4/4
+  double lnA[kNsMaxReactions], b[kNsMaxReactions], EaR[kNsMaxReactions];
+  int dnu[kNsMaxReactions];
+  int nuf[kNsMaxReactions][kNsMaxSpecies];
+  int nur[kNsMaxReactions][kNsMaxSpecies];
 };
 
 struct NsArgs {
   const double *w0;
   const double *ws;
   double *wout;
+  const int *face_if;
+  const long long *step;
+  int *err;
+  const NsMech *mech;
+  int E;
   int stage;
+  int viscous;
+  double dt;
+  double inv_dx;       // 1/dx
+  DelayParams dl;
+  RingParams ring;
+  Tables tb;
 };
 
-inline bool ns_supported(int, int) { return false; }
-inline adg_status ns_setup(NsArgs &, const adg_physics *, const adg_discretization *, int, int, bool, double,
-                           const DelayParams &, const RingParams &, const Tables &, const int *, const long long *,
-                           int *, NsMech *) {
-  return ADG_ERR_UNSUPPORTED;
-}
-inline hipError_t launch_ns_stage(int, const NsArgs &, hipStream_t) { return hipErrorInvalidValue; }
+bool ns_supported(int n_species, int n_reactions);
+adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *d, int E, int M, bool periodic,
+                    double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
+                    const long long *step, int *err, NsMech *dev_mech);
+hipError_t launch_ns_stage(int M, const NsArgs &a, hipStream_t s);
 
 }  // namespace adg

@@ -1,0 +1,140 @@
+"""GPU parity of the detailed-chemistry Navier-Stokes path (LDG, 9 species / 21 reactions,
+AT fluxes and AT central traces) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def adg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_01747_amd import adg as lib
+
+    return lib
+
+
+@pytest.fixture(scope="module")
+def mech():
+    return gen.synthetic_mechanism(1747, dt=1e-10)
+
+
+def var_errors(a, b):
+    """L2 error of each conserved variable relative to that variable's physical scale:
+    ||rho|| for rho and the partial densities, ||rho E|| for the energy and
+    sqrt(||rho|| ||rho E||) (density times a velocity of the order of the sound
+    speed) for the momentum, which is near zero in these quiescent states."""
+    V = a.shape[1]
+    num = np.linalg.norm((a - b).transpose(1, 0, 2).reshape(V, -1), axis=1)
+    nrm = np.linalg.norm(b.transpose(1, 0, 2).reshape(V, -1), axis=1)
+    scale = np.full(V, nrm[0])
+    scale[1] = np.sqrt(nrm[0] * nrm[2])
+    scale[2] = nrm[2]
+    return num / scale
+
+
+def rel_per_var(a, b):
+    err = var_errors(a, b)
+    if np.max(err) >= 1e-10:
+        print("per-variable errors:", np.array2string(err, precision=2))
+    return float(np.max(err))
+
+
+def compare(adg, orc, case, w0, steps, every, tol=1e-10):
+    print(f"[parity-ns] E={case['disc']['n_elem']} Np={case['disc']['order_p']} P={case['async']['n_pe']} "
+          f"mode={case['async']['mode']} visc={case['physics']['viscous']} steps={steps}", flush=True)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, steps + 1)
+    done, worst = 0, 0.0
+    while done < steps:
+        k = min(every, steps - done)
+        s.step(k)
+        o.step(k)
+        done += k
+        r = rel_per_var(s.state(), o.state())
+        worst = max(worst, r)
+        assert r < tol, (done, r)
+    s.close()
+    return worst
+
+
+@pytest.mark.parametrize("E,P", [(1, 1), (5, 2), (8, 3), (13, 4), (64, 8), (100, 7)])
+def test_small_sizes(adg, orc, mech, E, P):
+    """Tiles of 8 elements: a single element, fewer elements than a halo, a ragged tail."""
+    case, w0 = gen.case_c1(E=E, n_pe=P, mech=mech, Lx=0.01 * E / 64)
+    compare(adg, orc, case, w0, 12, every=4)
+
+
+@pytest.mark.parametrize("order_p", [1, 2, 3, 4])
+@pytest.mark.parametrize("mode", ["sync", "caa", "saa"])
+def test_orders_and_delay_models(adg, orc, mech, order_p, mode):
+    cfl = {1: 0.1, 2: 0.08, 3: 0.04, 4: 0.02}[order_p]
+    case, w0 = gen.case_c1(E=48, order_p=order_p, n_pe=6, mech=mech, mode=mode, cfl=cfl, Lx=0.01 * 48 / 2048)
+    if mode == "caa":
+        case["async"]["L"] = 3
+    compare(adg, orc, case, w0, 12, every=6)
+
+
+def test_inviscid_detailed(adg, orc, mech):
+    case, w0 = gen.case_c1(E=40, n_pe=4, mech=mech, viscous=0, Lx=0.01 * 40 / 2048)
+    compare(adg, orc, case, w0, 10, every=5)
+
+
+def test_zero_delay_is_synchronous(adg, mech):
+    case, w0 = gen.case_c1(E=64, n_pe=8, mech=mech, mode="sync", Lx=0.01 * 64 / 2048)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(8)
+    ref = s.state()
+    case0 = dict(case, **{"async": dict(case["async"], mode="saa", pmf=[1.0, 0.0, 0.0], L=3)})
+    s0 = adg.Solver(case0)
+    s0.set_state(w0)
+    s0.step(8)
+    np.testing.assert_array_equal(s0.state(), ref)
+
+
+def test_worst_case_schedule(adg, orc, mech):
+    case, w0 = gen.case_c1(E=64, n_pe=8, mech=mech, mode="sync", Lx=0.01 * 64 / 2048)
+    case["async"].update(mode="schedule", L=3, schedule=np.full((1, 8), 2, dtype=np.int8))
+    compare(adg, orc, case, w0, 12, every=4)
+
+
+def test_c1_full_size(adg, orc, mech):
+    """The C1 workload at full size (E = 2048, N_p = 3, 16 PEs, SAA set-1) in the launch
+    configuration the benchmark times (HIP graph of 10 steps)."""
+    case, w0 = gen.case_c1()
+    s = adg.Solver(case)
+    s.set_graph(10)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, 21)
+    s.step(10)
+    o.step(10)
+    r1 = rel_per_var(s.state(), o.state())
+    s.step(10)
+    o.step(10)
+    r2 = rel_per_var(s.state(), o.state())
+    print(f"[parity-ns] c1 full size: rel {r1:.2e} after 10 steps, {r2:.2e} after 20")
+    assert r1 < 1e-10 and r2 < 1e-10
+
+
+def test_conservation_on_gpu(adg, mech):
+    case, w0 = gen.case_c1(E=128, n_pe=8, mech=mech, Lx=0.01 * 128 / 2048)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(30)
+    w = s.state()
+    scale = [abs(w0[:, 0, 0]).sum(), np.sqrt(abs(w0[:, 0, 0]).sum() * abs(w0[:, 2, 0]).sum()),
+             abs(w0[:, 2, 0]).sum()]   # the momentum starts at zero: use rho times a sound-speed scale
+    for v in range(3):
+        assert abs(w[:, v, 0].sum() - w0[:, v, 0].sum()) <= 1e-13 * scale[v]
+    comp = mech["composition"]
+    for el in range(3):
+        tot = lambda ww: np.sum(ww[:, 3:, 0] / mech["W"] * comp[:, el])
+        assert abs(tot(w) - tot(w0)) <= 1e-12 * abs(tot(w0))
+    np.testing.assert_allclose(w[:, 3:, :].sum(1), w[:, 0, :], rtol=0, atol=1e-13 * np.abs(w[:, 0, 0]).max())
