@@ -158,8 +158,8 @@ int32_t adg_n_interfaces(const adg_solver *s);
 /* Enqueue n_steps steps like adg_step and time every kernel launch with HIP
    events on the solver's stream.  ms_out[i] receives the mean duration in ms
    of kernel class i and launches_out[i] the launch count; n_classes is the
-   array length (classes: 0 stage kernel, 1 limiter, 2 limiter scatter,
-   3 step counter).  Synchronises. */
+   array length (classes: 0 stage kernel, 1 limiter, 2 limiter scatter).
+   Synchronises. */
 adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *launches_out, int32_t n_classes);
 
 /* Use a captured HIP graph of `steps_per_graph` time steps for adg_step

@@ -21,7 +21,7 @@ PERIODIC, TRANSMISSIVE = 0, 1
 RUSANOV, HLLC = 0, 1
 SYNC, CAA, SAA, SCHEDULE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
-PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter", "step_counter")
+PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")

@@ -209,6 +209,7 @@ struct adg_solver {
   int8_t *flags = nullptr;
   int *face_if = nullptr;
   long long *step = nullptr;
+  unsigned *done = nullptr;
   int *err = nullptr;
   unsigned long long *flag_count = nullptr;
   double *ring = nullptr;
@@ -255,6 +256,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       a.ws = s->W[in_buf[stage]];
       a.wout = s->W[out_buf[stage]];
       a.stage = stage;
+      a.advance = stage == 2 && !s->disc.limiter;
       if (timer) timer(s, 0, true);
       HIP_TRY(s, launch_euler_stage(M, s->disc.flux, a, st));
       if (timer) timer(s, 0, false);
@@ -262,9 +264,11 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
         LimiterArgs l = s->la;
         l.w = s->W[out_buf[stage]];
         l.stage = stage;
+        l.advance = 0;
         if (timer) timer(s, 1, true);
         HIP_TRY(s, launch_limiter(M, l, st));
         if (timer) timer(s, 1, false);
+        l.advance = stage == 2;
         if (timer) timer(s, 2, true);
         HIP_TRY(s, launch_limiter_scatter(M, l, st));
         if (timer) timer(s, 2, false);
@@ -275,14 +279,12 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       a.ws = s->W[in_buf[stage]];
       a.wout = s->W[out_buf[stage]];
       a.stage = stage;
+      a.advance = stage == 2;
       if (timer) timer(s, 0, true);
       HIP_TRY(s, launch_ns_stage(M, a, st));
       if (timer) timer(s, 0, false);
     }
   }
-  if (timer) timer(s, 3, true);
-  HIP_TRY(s, launch_advance(s->step, st));
-  if (timer) timer(s, 3, false);
   return ADG_OK;
 }
 
@@ -352,6 +354,7 @@ adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, c
   s->face_if = (int *)(s->ws + L.face_if);
   s->step = (long long *)(s->ws + L.counters);
   s->err = (int *)(s->ws + L.counters + 64);
+  s->done = (unsigned *)(s->ws + L.counters + 192);
   s->flag_count = (unsigned long long *)(s->ws + L.counters + 128);
   s->ring = (double *)(s->ws + L.ring);
 
@@ -397,6 +400,7 @@ adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, c
     EulerArgs &a = s->ea;
     a.face_if = s->face_if;
     a.step = s->step;
+    a.done = s->done;
     a.err = s->err;
     a.E = L.E;
     a.periodic = periodic;
@@ -414,6 +418,7 @@ adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, c
       l.flag_count = s->flag_count;
       l.face_if = s->face_if;
       l.step = s->step;
+      l.done = s->done;
       l.err = s->err;
       l.E = L.E;
       l.periodic = periodic;
@@ -427,7 +432,7 @@ adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, c
       build_limiter_tables(L.M, l);
     }
   } else {
-    adg_status rc = ns_setup(s->na, phys, disc, L.E, L.M, periodic, dx, dl, rp, tb, s->face_if, s->step, s->err,
+    adg_status rc = ns_setup(s->na, phys, disc, L.E, L.M, periodic, dx, dl, rp, tb, s->face_if, s->step, s->done, s->err,
                              (NsMech *)(s->ws + L.mech));
     if (rc != ADG_OK) { delete s; return rc; }
   }
@@ -552,7 +557,6 @@ adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *
     order.push_back(0);
     if (s->phys.model == ADG_ONESTEP && s->disc.limiter) { order.push_back(1); order.push_back(2); }
   }
-  order.push_back(3);
   HIP_TRY(s, hipStreamSynchronize(s->stream));
   std::vector<double> sum(n_classes, 0.0);
   std::vector<int64_t> cnt(n_classes, 0);

@@ -205,6 +205,7 @@ __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
     }
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
+  if (a.advance) finish_step(a.step, a.done);
 }
 
 // ------------------------------------------------------------------- limiter
@@ -416,17 +417,17 @@ __global__ __launch_bounds__(128) void limiter_kernel(LimiterArgs a) {
 template <int M>
 __global__ __launch_bounds__(256) void limiter_scatter_kernel(LimiterArgs a) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.E || !a.flags[e]) return;
+  if (e < a.E && a.flags[e]) {
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
+    for (int v = 0; v < 5; ++v)
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const size_t idx = (size_t)(v * M + j) * a.E + e;
-      a.w[idx] = a.wlim[idx];
-    }
+      for (int j = 0; j < M; ++j) {
+        const size_t idx = (size_t)(v * M + j) * a.E + e;
+        a.w[idx] = a.wlim[idx];
+      }
+  }
+  if (a.advance) finish_step(a.step, a.done);
 }
-
-__global__ void advance_kernel(long long *step) { *step += 1; }
 
 // [E][VM] <-> [VM][E]
 __global__ void to_planes_kernel(const double *__restrict__ src, double *__restrict__ dst, int E, int VM) {
@@ -483,11 +484,6 @@ hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s) {
     case 5: hipLaunchKernelGGL(limiter_scatter_kernel<5>, dim3(blocks), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_advance(long long *step, hipStream_t s) {
-  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(1), 0, s, step);
   return hipGetLastError();
 }
 

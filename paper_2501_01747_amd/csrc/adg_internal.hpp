@@ -59,7 +59,9 @@ struct EulerArgs {
   const double *ws;     // stage input w^(s)
   double *wout;         // stage output (unlimited)
   const int *face_if;   // [E+1] interface index of face f, or -1
-  const long long *step;
+  long long *step;
+  unsigned *done;       // workgroups finished in the step's last kernel
+  int advance;          // this launch ends the time step
   int *err;
   int E;
   int periodic;
@@ -79,7 +81,9 @@ struct LimiterArgs {
   int8_t *flags;        // [E]
   unsigned long long *flag_count;
   const int *face_if;
-  const long long *step;
+  long long *step;
+  unsigned *done;
+  int advance;
   int *err;
   int E;
   int periodic;
@@ -102,7 +106,6 @@ enum ErrBits { kErrState = 1, kErrNewton = 2 };
 hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, hipStream_t s);
 hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s);
 hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s);
-hipError_t launch_advance(long long *step, hipStream_t s);
 hipError_t launch_to_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
 hipError_t launch_from_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
 

@@ -25,7 +25,7 @@
 namespace adg {
 
 constexpr int kTile = 8;
-constexpr int kThreads = 64;
+constexpr int kThreads = 256;
 
 template <int NS>
 struct Thermo {
@@ -208,17 +208,22 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   constexpr int NH = TE + 4;   // tile + 2 halo elements per side; local l <-> element e0 - 2 + l
   constexpr int NF = TE + 3;   // faces e0-1 .. e0+TE+1; local fl <-> face e0 - 1 + fl
   constexpr int NQ = TE + 2;   // gradients of elements e0-1 .. e0+TE; local lq <-> element e0 - 1 + lq
-  constexpr int NP = TE * Q + 2 * (TE + 1);
+  constexpr int NN = TE * Q;   // quadrature nodes of the tile; node p <-> element p / Q, node p % Q
+  constexpr int NT = 2 * (TE + 1);  // face traces; trace pp <-> face e0 + pp/2, side pp%2
+  constexpr int NR = kNsMaxReactions;
+  static_assert(NN <= 64 && NT <= 64, "node and trace lanes each fit one wavefront");
   __shared__ double sW[V * M][NH];
   __shared__ double sTm[V][NH], sTp[V][NH];
   __shared__ double sWc[V][NF], sWa[V][NF];
   __shared__ double sQ[V * M][NQ];
-  __shared__ double sG[V][Q][TE];
-  __shared__ double sS[NS][Q][TE];
-  __shared__ double sT[Q][TE];
+  __shared__ double sG[V][NN];
+  __shared__ double sS[NS][NN];
+  __shared__ double sT[NN];
+  __shared__ double sConc[NS][NN], sGRT[NS][NN];
+  __shared__ double sRate[NR][NN];
   __shared__ double sGf[2][V][TE + 1], sGs[2][V][TE + 1];
   __shared__ double sLam[2][TE + 1];
-  __shared__ double sF[V][TE + 1];
+  __shared__ double sF[V][TE + 1], sFat[V][TE + 1];
   __shared__ int sI[NF], sK[NF];
   __shared__ double sB[Q][M], sWG[Q][M], sWB[Q][M], sD[M][M];   // tables, indexed at run time
 
@@ -227,10 +232,19 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   const int e0 = blockIdx.x * TE;
   const int nloc = min(TE, E - e0);
   const long long n = *a.step;
-  const NsMech *__restrict__ mk = a.mech;
+  __shared__ NsMech smech;
+  const NsMech *__restrict__ mk = &smech;
   const int q_at = a.dl.q;
   bool ok = true;
 
+  // 0. mechanism, state of the tile and its halo, tables, PE-interface data of the faces
+  {
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.mech);
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(&smech);
+    constexpr int nwords = (int)(sizeof(NsMech) / 8);
+    for (int idx = t; idx < nwords; idx += kThreads) dst[idx] = src[idx];
+  }
+#pragma unroll 3
   for (int idx = t; idx < V * M * NH; idx += kThreads) {
     const int c = idx / NH, l = idx % NH;
     int e = (e0 - 2 + l) % E;
@@ -252,8 +266,10 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     sK[fl] = i >= 0 ? eff_delay(a.dl, n, i) : 0;
   }
   __syncthreads();
+  const int nr = mk->nr;
 
-  // 1. traces of w
+  // 1. traces of w; meanwhile the AT combinations of past levels (Eq. (7)) of the central
+  //    traces and of the fluxes at delayed PE interfaces are gathered from the ring
   for (int idx = t; idx < V * NH; idx += kThreads) {
     const int v = idx / NH, l = idx % NH;
     double sm = 0.0, sp = 0.0;
@@ -266,32 +282,37 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     sTm[v][l] = sm;
     sTp[v][l] = sp;
   }
-  __syncthreads();
-
-  // 2. central traces; face fl sits between local elements fl (left) and fl + 1 (right)
   for (int idx = t; idx < V * NF; idx += kThreads) {
     const int v = idx / NF, fl = idx % NF;
-    const double wc = 0.5 * (sTp[v][fl] + sTm[v][fl + 1]);
-    double wa = wc;
-    const int i = sI[fl];
-    if (i >= 0) {
-      if (fl >= 1 && fl <= nloc)   // faces e0 .. e0+nloc-1 are owned by this tile
-        ring_rec(a.ring, n, a.stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
-      const int k = sK[fl];
-      if (k > 0) {
-        double acc = 0.0;
-        for (int j = 0; j < q_at; ++j)
-          acc += at_weight(q_at, k, j) * ring_rec(a.ring, n - k - j, a.stage, a.dl.nif, i)[a.ring.off_Wc + v];
-        wa = acc;
-      }
+    const int i = sI[fl], k = sK[fl];
+    if (i < 0 || k == 0) continue;
+    double acw = 0.0, acf = 0.0;
+    for (int j = 0; j < q_at; ++j) {
+      const double c = at_weight(q_at, k, j);
+      const double *rec = ring_rec(a.ring, n - k - j, a.stage, a.dl.nif, i);
+      acw += c * rec[a.ring.off_Wc + v];
+      acf += c * rec[a.ring.off_F + v];
     }
-    sWc[v][fl] = wc;
-    sWa[v][fl] = wa;
+    sWa[v][fl] = acw;
+    if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = acf;
   }
   __syncthreads();
 
-  // 3. LDG gradient q_j = (2j+1)/dx [w*_R - (-1)^j w*_L - sum_k D_jk w_k], element local lq + 1,
-  //    left face fl = lq, right face fl = lq + 1
+  // 2. central traces; face fl sits between local elements fl (left) and fl + 1 (right).
+  //    The synchronous value of a PE interface is published for this level.
+  for (int idx = t; idx < V * NF; idx += kThreads) {
+    const int v = idx / NF, fl = idx % NF;
+    const double wc = 0.5 * (sTp[v][fl] + sTm[v][fl + 1]);
+    const int i = sI[fl];
+    if (i >= 0 && fl >= 1 && fl <= nloc)   // faces e0 .. e0+nloc-1 are owned by this tile
+      ring_rec(a.ring, n, a.stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
+    sWc[v][fl] = wc;
+    if (i < 0 || sK[fl] == 0) sWa[v][fl] = wc;
+  }
+  __syncthreads();
+
+  // 3. LDG gradient q_j = (2j+1)/dx [w*_R - (-1)^j w*_L - sum_k D_jk w_k] of the element
+  //    with gradient slot lq (left face lq, right face lq + 1)
   for (int idx = t; idx < V * M * NQ; idx += kThreads) {
     const int c = idx / NQ, lq = idx % NQ;
     const int v = c / M, j = c % M;
@@ -303,93 +324,118 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   }
   __syncthreads();
 
-  // 4. point evaluations: nodes of the tile, then the two traces of faces e0 .. e0+TE
-  for (int p = t; p < NP; p += kThreads) {
-    double w[V], dw[V], g[V];
-    double lam;
-    if (p < TE * Q) {
-      const int el = p / Q, qn = p % Q;
+  // 4a. point evaluations: wavefront 0 takes the quadrature nodes, wavefront 1 the face traces
+  if (t < NN) {
+    const int el = t / Q, qn = t % Q;
+    double w[V], dw[V], g[V], gs[V], lam, T;
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        double x = 0.0, d = 0.0;
+    for (int v = 0; v < V; ++v) {
+      double x = 0.0, d = 0.0;
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-          x += sB[qn][j] * sW[v * M + j][el + 2];
-          d += sB[qn][j] * sQ[v * M + j][el + 1];
-        }
-        w[v] = x;
-        dw[v] = d;
+      for (int j = 0; j < M; ++j) {
+        x += sB[qn][j] * sW[v * M + j][el + 2];
+        d += sB[qn][j] * sQ[v * M + j][el + 1];
       }
-      double T, gs[V];
-      ok = ns_point<NS>(mk, a.viscous, w, dw, false, dw, g, gs, lam, T) && ok;
+      w[v] = x;
+      dw[v] = d;
+    }
+    ok = ns_point<NS>(mk, a.viscous, w, dw, false, dw, g, gs, lam, T) && ok;
 #pragma unroll
-      for (int v = 0; v < V; ++v) sG[v][qn][el] = g[v];
-      sT[qn][el] = T;
-    } else {
-      const int pp = p - TE * Q;
-      const int ff = pp >> 1, side = pp & 1;  // face e0 + ff; side 0 = element left of it (at xi = +1)
-      const int l = ff + 1 + side;            // local element
-      const int lq = ff + side;               // its gradient slot; faces lq (left), lq + 1 (right)
-      const double sgn = side ? -1.0 : 1.0;   // P_j(+-1) = (+-1)^j
+    for (int v = 0; v < V; ++v) sG[v][t] = g[v];
+    sT[t] = T;
+  } else if (t >= 64 && t < 64 + NT) {
+    const int pp = t - 64;
+    const int ff = pp >> 1, side = pp & 1;  // face e0 + ff; side 0 = element left of it (at xi = +1)
+    const int l = ff + 1 + side;            // local element
+    const int lq = ff + side;               // its gradient slot; faces lq (left), lq + 1 (right)
+    const double sgn = side ? -1.0 : 1.0;   // P_j(+-1) = (+-1)^j
+    double w[V], dw[V], g[V], gs[V], dws[V], lam, T;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      w[v] = side ? sTm[v][l] : sTp[v][l];
+      double d = 0.0, pj = 1.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        d += pj * sQ[v * M + j][lq];
+        pj *= sgn;
+      }
+      dw[v] = d;
+      dws[v] = d;
+    }
+    const bool pe = sI[ff + 1] >= 0;
+    if (pe) {
+      // synchronous gradient trace: undo the AT central traces of this element's faces
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        w[v] = side ? sTm[v][l] : sTp[v][l];
-        double d = 0.0, pj = 1.0;
+        const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
+        double corr = 0.0, pj = 1.0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          d += pj * sQ[v * M + j][lq];
+          corr += pj * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
           pj *= sgn;
         }
-        dw[v] = d;
+        dws[v] = dw[v] + corr;
       }
-      const bool pe = sI[ff + 1] >= 0;
-      double dws[V], gs[V];
-#pragma unroll
-      for (int v = 0; v < V; ++v) dws[v] = dw[v];
-      if (pe) {
-        // synchronous gradient trace: undo the AT central traces of this element's faces
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
-          double corr = 0.0, pj = 1.0;
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            corr += pj * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
-            pj *= sgn;
-          }
-          dws[v] = dw[v] + corr;
-        }
-      }
-      double T;
-      ok = ns_point<NS>(mk, a.viscous, w, dw, pe, dws, g, gs, lam, T) && ok;
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        sGf[side][v][ff] = g[v];
-        if (pe) sGs[side][v][ff] = gs[v];
-      }
-      sLam[side][ff] = lam;
     }
+    ok = ns_point<NS>(mk, a.viscous, w, dw, pe, dws, g, gs, lam, T) && ok;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      sGf[side][v][ff] = g[v];
+      if (pe) sGs[side][v][ff] = gs[v];
+    }
+    sLam[side][ff] = lam;
   }
   __syncthreads();
 
-  // 4b. chemistry at the quadrature nodes of the tile
-  for (int p = t; p < TE * Q; p += kThreads) {
+  // 4b. chemistry (Sec. 2: W_i omega_i), one lane per (node, species), then one lane per
+  //     (node, reaction), then one lane per (node, species) again
+  for (int idx = t; idx < NS * NN; idx += kThreads) {
+    const int i = idx / NN, p = idx % NN;
     const int el = p / Q, qn = p % Q;
-    double rhoY[NS], src[NS];
+    double x = 0.0;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      double x = 0.0;
-#pragma unroll
-      for (int j = 0; j < M; ++j) x += sB[qn][j] * sW[(3 + i) * M + j][el + 2];
-      rhoY[i] = x;
-    }
-    ns_source<NS>(mk, rhoY, sT[qn][el], src);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) sS[i][qn][el] = src[i];
+    for (int j = 0; j < M; ++j) x += sB[qn][j] * sW[(3 + i) * M + j][el + 2];
+    const double T = sT[p];
+    const double lnT = log(T);
+    const double *c = mk->a[i];
+    const double *h2 = mk->h2[i];
+    const double *s2 = mk->s2[i];
+    const double hRT = c[0] + T * (h2[0] + T * (h2[1] + T * (h2[2] + T * h2[3]))) + c[5] / T;
+    const double sR = c[0] * lnT + T * (c[1] + T * (s2[0] + T * (s2[1] + T * s2[2]))) + c[6];
+    sGRT[i][p] = hRT - sR;
+    sConc[i][p] = x * mk->invW[i];
   }
   __syncthreads();
+  for (int idx = t; idx < nr * NN; idx += kThreads) {
+    const int r = idx / NN, p = idx % NN;
+    const double T = sT[p];
+    const double lnT = log(T);
+    const double lnkf = mk->lnA[r] + mk->b[r] * lnT - mk->EaR[r] / T;
+    double dG = 0.0;
+    for (int g = 0; g < mk->ng[r]; ++g) dG += mk->gnu[r][g] * sGRT[mk->gidx[r][g]][p];
+    const double lnKc = -dG + (double)mk->dnu[r] * (mk->ln_p_over_Ru - lnT);
+    double fwd = exp(lnkf), rev = exp(lnkf - lnKc);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int sf = mk->rf[r][m], sb = mk->rr[r][m];
+      if (sf >= 0) fwd *= sConc[sf][p];
+      if (sb >= 0) rev *= sConc[sb][p];
+    }
+    sRate[r][p] = fwd - rev;
+  }
+  __syncthreads();
+  for (int idx = t; idx < NS * NN; idx += kThreads) {
+    const int i = idx / NN, p = idx % NN;
+    double wdot = 0.0;
+    for (int r = 0; r < nr; ++r) {
+      const double nu = mk->nud[r][i];
+      if (nu != 0.0) wdot += nu * sRate[r][p];
+    }
+    sS[i][p] = mk->W[i] * wdot;
+  }
 
-  // 5. Rusanov total flux f = (g- + g+)/2 - lambda (w+ - w-)/2 at faces e0 + ff
+  // 5. Rusanov total flux f = (g- + g+)/2 - lambda (w+ - w-)/2 at faces e0 + ff; at PE
+  //    interfaces the synchronous flux is published and the AT combination is used
   for (int idx = t; idx < V * (TE + 1); idx += kThreads) {
     const int v = idx / (TE + 1), ff = idx % (TE + 1);
     const double wm = sTp[v][ff + 1], wp = sTm[v][ff + 2];
@@ -400,15 +446,7 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     if (i >= 0) {
       const double Fs = 0.5 * (sGs[0][v][ff] + sGs[1][v][ff] - diss);
       if (ff < nloc) ring_rec(a.ring, n, a.stage, a.dl.nif, i)[a.ring.off_F + v] = Fs;
-      const int k = sK[ff + 1];
-      if (k > 0) {
-        double acc = 0.0;
-        for (int j = 0; j < q_at; ++j)
-          acc += at_weight(q_at, k, j) * ring_rec(a.ring, n - k - j, a.stage, a.dl.nif, i)[a.ring.off_F + v];
-        F = acc;
-      } else {
-        F = Fs;
-      }
+      F = sK[ff + 1] > 0 ? sFat[v][ff] : Fs;
     } else {
       F = 0.5 * (sGf[0][v][ff] + sGf[1][v][ff] - diss);
     }
@@ -423,8 +461,8 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     double vol = 0.0, src = 0.0;
 #pragma unroll
     for (int qn = 0; qn < Q; ++qn) {
-      vol += sWG[qn][j] * sG[v][qn][el];
-      if (v >= 3) src += sWB[qn][j] * sS[v >= 3 ? v - 3 : 0][qn][el];
+      vol += sWG[qn][j] * sG[v][el * Q + qn];
+      if (v >= 3) src += sWB[qn][j] * sS[v >= 3 ? v - 3 : 0][el * Q + qn];
     }
     const double half2j1 = 0.5 * (2 * j + 1);
     const double b = vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
@@ -438,6 +476,7 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     a.wout[gi] = o;
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
+  if (a.advance) finish_step(a.step, a.done);
 }
 
 // ------------------------------------------------------------------ host side
@@ -448,7 +487,7 @@ bool ns_supported(int n_species, int n_reactions) {
 
 adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *d, int E, int M, bool periodic,
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
-                    const long long *step, int *err, NsMech *dev_mech) {
+                    long long *step, unsigned *done, int *err, NsMech *dev_mech) {
   if (!periodic) return ADG_ERR_UNSUPPORTED;
   const adg_mechanism *m = ph->mech;
   if (!ns_supported(m->n_species, m->n_reactions)) return ADG_ERR_UNSUPPORTED;
@@ -492,10 +531,32 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
       dnu += b - f;
     }
     hm.dnu[r] = dnu;
+    int nf = 0, nb = 0, g = 0;
+    hm.rf[r][0] = hm.rf[r][1] = hm.rr[r][0] = hm.rr[r][1] = -1;
+    for (int i = 0; i < hm.ns; ++i) {
+      for (int c = 0; c < hm.nuf[r][i]; ++c) {
+        if (nf == 2) return ADG_ERR_UNSUPPORTED;   // at most two reactant molecules
+        hm.rf[r][nf++] = i;
+      }
+      for (int c = 0; c < hm.nur[r][i]; ++c) {
+        if (nb == 2) return ADG_ERR_UNSUPPORTED;
+        hm.rr[r][nb++] = i;
+      }
+      const int nu = hm.nur[r][i] - hm.nuf[r][i];
+      hm.nud[r][i] = nu;
+      if (nu != 0) {
+        if (g == 4) return ADG_ERR_UNSUPPORTED;
+        hm.gidx[r][g] = i;
+        hm.gnu[r][g] = nu;
+        ++g;
+      }
+    }
+    hm.ng[r] = g;
   }
   if (hipMemcpy(dev_mech, &hm, sizeof hm, hipMemcpyHostToDevice) != hipSuccess) return ADG_ERR_HIP;
   a.face_if = face_if;
   a.step = step;
+  a.done = done;
   a.err = err;
   a.mech = dev_mech;
   a.E = E;

@@ -28,6 +28,13 @@ struct NsMech {
   int dnu[kNsMaxReactions];
   int nuf[kNsMaxReactions][kNsMaxSpecies];
   int nur[kNsMaxReactions][kNsMaxSpecies];
+  // compact per-reaction form for one lane per (point, reaction): the species
+  // multiplied into the forward and reverse rates (-1 = none) and the nonzero
+  // net coefficients nu_i = nu''_i - nu'_i
+  int rf[kNsMaxReactions][2], rr[kNsMaxReactions][2];
+  int ng[kNsMaxReactions], gidx[kNsMaxReactions][4];
+  double gnu[kNsMaxReactions][4];
+  double nud[kNsMaxReactions][kNsMaxSpecies];
 };
 
 struct NsArgs {
@@ -35,7 +42,9 @@ struct NsArgs {
   const double *ws;
   double *wout;
   const int *face_if;
-  const long long *step;
+  long long *step;
+  unsigned *done;       // workgroups finished in the step's last kernel
+  int advance;          // this launch ends the time step
   int *err;
   const NsMech *mech;
   int E;
@@ -51,7 +60,7 @@ struct NsArgs {
 bool ns_supported(int n_species, int n_reactions);
 adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *d, int E, int M, bool periodic,
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
-                    const long long *step, int *err, NsMech *dev_mech);
+                    long long *step, unsigned *done, int *err, NsMech *dev_mech);
 hipError_t launch_ns_stage(int M, const NsArgs &a, hipStream_t s);
 
 }  // namespace adg
