@@ -30,18 +30,43 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
-def workload(name: str):
+def workload(name: str, n_elem: int | None = None):
     from workloads import gen
 
+    kw = {} if n_elem is None else {"E": n_elem}
     if name == "c0":
-        case, w0 = gen.case_c0()
+        case, w0 = gen.case_c0(**kw)
     elif name == "c1":
-        case, w0 = gen.case_c1()
+        case, w0 = gen.case_c1(**kw)
     elif name == "c2":
-        case, w0 = gen.case_c2()
+        case, w0 = gen.case_c2(**kw)
     else:
         raise SystemExit(f"unknown workload {name}")
     return case, w0
+
+
+COPY_PROBE_BYTES = 256 * 1024 * 1024
+
+
+def pmc_probe(args):
+    """Run under rocprofv3 --pmc: one plain device copy of COPY_PROBE_BYTES (the calibration
+    kernel for FETCH_SIZE / WRITE_SIZE), then args.steps time steps with plain launches."""
+    import torch
+
+    from paper_2501_01747_amd import adg
+
+    src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    case, w0 = workload(args.workload, args.n_elem)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(args.steps)
+    s.sync()
+    print(json.dumps({"probe": case["name"], "n_elem": case["disc"]["n_elem"], "copy_bytes": COPY_PROBE_BYTES,
+                      "steps": args.steps}), flush=True)
 
 
 def euler_stage_bytes(case) -> float:
@@ -130,6 +155,38 @@ def cpu_baseline(case, w0, budget_s: float = 12.0):
                       f"({el:.1f} s, single thread, gcc -O2)"}
 
 
+def sweep_euler(sizes, steps=20):
+    """Size sweep of the one-step Euler stage kernel (C0 physics, N_p = 2, 8 PEs, SAA) into the
+    HBM-bound regime: per size, the stage kernel's mean launch time and its algorithmic bandwidth."""
+    import torch
+
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    import numpy as np
+
+    out = []
+    base_case, base = gen.case_c0(E=1024)
+    for E in sizes:
+        case, _ = gen.case_c0(E=min(E, 1024))
+        case["disc"]["n_elem"] = E
+        case["disc"]["dt"] *= min(E, 1024) / E      # same Courant number on the finer mesh
+        # a smooth valid state of the right size: the 1024-element projection repeated
+        w0 = np.ascontiguousarray(np.tile(base, (max(1, E // 1024), 1, 1))[:E]) if E >= 1024 else gen.case_c0(E=E)[1]
+        s = adg.Solver(case)
+        s.set_state(w0)
+        s.step(3)
+        prof = s.profile(steps)
+        ms = prof["stage"][0]
+        nbytes = euler_stage_bytes(case)
+        out.append({"n_elem": E, "dof": gen.dof(case), "stage_ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9,
+                    "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +195,11 @@ def main():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--graph", type=int, default=10, help="time steps per captured HIP graph (0 = plain launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep-euler", action="store_true",
+                    help="print the Euler stage-kernel size sweep instead of the benchmark line")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="calibration copy + plain-launch steps for rocprofv3 --pmc (no benchmark line)")
+    ap.add_argument("--n-elem", type=int, default=None, help="override the workload's element count")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -150,7 +212,14 @@ def main():
     from workloads import gen
 
     torch.cuda.set_device(0)
-    case, w0 = workload(args.workload)
+    if args.pmc_probe:
+        pmc_probe(args)
+        return
+    if args.sweep_euler:
+        print(json.dumps({"sweep": "euler_stage_kernel", "results": sweep_euler([2**p for p in range(10, 23, 1)])}),
+              flush=True)
+        return
+    case, w0 = workload(args.workload, args.n_elem)
     s = adg.Solver(case)
     s.set_state(w0)
     if args.graph:

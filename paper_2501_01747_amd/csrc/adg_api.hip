@@ -181,7 +181,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   L.off_U = 2 * L.V;
   L.rec = 2 * L.V + (d->limiter ? 2 * L.V * L.M : 0);
   (void)visc;
-  size_t nstate = (size_t)L.E * L.V * L.M * sizeof(double);
+  size_t nstate = state_doubles(L.E, L.V * L.M) * sizeof(double);
   size_t off = 0;
   L.state = off;  off += 3 * align256(nstate);
   L.wlim = off;   off += d->limiter ? align256(nstate) : 0;
@@ -347,7 +347,7 @@ adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, c
   s->lay = L;
   s->stream = (hipStream_t)hip_stream;
   s->ws = (char *)device_workspace;
-  size_t nstate = (size_t)L.E * L.V * L.M * sizeof(double);
+  size_t nstate = state_doubles(L.E, L.V * L.M) * sizeof(double);
   for (int b = 0; b < 3; ++b) s->W[b] = (double *)(s->ws + L.state + b * align256(nstate));
   s->Wlim = disc->limiter ? (double *)(s->ws + L.wlim) : nullptr;
   s->flags = (int8_t *)(s->ws + L.flags);
@@ -446,9 +446,9 @@ adg_status adg_set_state(adg_solver *s, const double *w, int64_t count, int32_t 
   const int VM = L.V * L.M;
   if (count != (int64_t)L.E * VM) return fail(s, ADG_ERR_ARG, "state size mismatch");
   if (where == ADG_HOST) {
-    std::vector<double> planes((size_t)L.E * VM);
+    std::vector<double> planes(state_doubles(L.E, VM), 0.0);
     for (int e = 0; e < L.E; ++e)
-      for (int c = 0; c < VM; ++c) planes[(size_t)c * L.E + e] = w[(size_t)e * VM + c];
+      for (int c = 0; c < VM; ++c) planes[sidx(e, c, VM)] = w[(size_t)e * VM + c];
     HIP_TRY(s, hipMemcpyAsync(s->W[0], planes.data(), planes.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
   } else if (where == ADG_DEVICE) {
@@ -500,11 +500,11 @@ adg_status adg_get_state(adg_solver *s, double *w, int64_t count, int32_t where)
   const int VM = L.V * L.M;
   if (count != (int64_t)L.E * VM) return fail(s, ADG_ERR_ARG, "state size mismatch");
   if (where == ADG_HOST) {
-    std::vector<double> planes((size_t)L.E * VM);
+    std::vector<double> planes(state_doubles(L.E, VM));
     HIP_TRY(s, hipMemcpyAsync(planes.data(), s->W[0], planes.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     for (int e = 0; e < L.E; ++e)
-      for (int c = 0; c < VM; ++c) w[(size_t)e * VM + c] = planes[(size_t)c * L.E + e];
+      for (int c = 0; c < VM; ++c) w[(size_t)e * VM + c] = planes[sidx(e, c, VM)];
   } else if (where == ADG_DEVICE) {
     HIP_TRY(s, launch_from_planes(s->W[0], w, L.E, VM, s->stream));
   } else {

@@ -73,10 +73,11 @@ struct Prim1 {
 // rho E = rho u^2/2 + p/(gamma-1) + q rho Y_R;  T = p/rho (R = 1).
 __device__ __forceinline__ bool prim1(const OneStep &ph, const double *w, Prim1 &pr) {
   pr.rho = w[0];
-  pr.u = w[1] / pr.rho;
-  pr.p = (ph.gamma - 1.0) * (w[2] - 0.5 * pr.rho * pr.u * pr.u - ph.q_heat * w[3]);
-  pr.T = pr.p / pr.rho;
-  pr.a = sqrt(ph.gamma * pr.p / pr.rho);
+  const double rinv = 1.0 / pr.rho;
+  pr.u = w[1] * rinv;
+  pr.p = (ph.gamma - 1.0) * (w[2] - 0.5 * w[1] * pr.u - ph.q_heat * w[3]);
+  pr.T = pr.p * rinv;
+  pr.a = sqrt(ph.gamma * pr.T);
   return pr.rho > 0.0 && pr.p > 0.0 && isfinite(pr.p) && isfinite(pr.rho);
 }
 

@@ -1,11 +1,11 @@
 // Fused SSP-RK3 stage kernel for the one-step reactive Euler model and the
 // KXRCF + characteristic (AT-)WENO limiter.
 //
-// Stage kernel (Sec. 3.1 Eq. (5), Sec. 3.2 Eq. (7)): one thread per element,
-// 256 elements per workgroup.  Each thread loads its element's modal DoFs from
-// the component planes (coalesced), forms both face traces, and publishes them
-// in LDS; the two tile-edge threads also load the neighbouring element of the
-// tile.  One numerical flux per face is computed from LDS; at PE-interface
+// Stage kernel (Sec. 3.1 Eq. (5), Sec. 3.2 Eq. (7)): one thread per element;
+// each wavefront owns 62 consecutive elements and holds their two neighbours.
+// Every lane loads its element's modal DoFs from the component planes
+// (coalesced) and forms both face traces; one numerical flux per face is
+// computed and passed to the neighbouring lane by a shuffle; at PE-interface
 // faces the synchronous flux of this level is written to the history ring and
 // replaced by the AT combination of past levels.  The volume integral, the
 // source projection, the lift and the RK combination then run in registers and
@@ -35,15 +35,14 @@ __device__ __forceinline__ void load_elem(const double *__restrict__ w, int E, i
 #pragma unroll
   for (int v = 0; v < 5; ++v)
 #pragma unroll
-    for (int j = 0; j < M; ++j) u[v][j] = w[(size_t)(v * M + j) * E + e];
+    for (int j = 0; j < M; ++j) u[v][j] = w[sidx(e, v * M + j, 5 * M)];
 }
 
-// Numerical flux at face f from its two traces; at PE interfaces the AT flux.
+// Numerical flux at a face from its two traces; at PE interface i the AT flux.
 template <int FLUX>
-__device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int f, const double *wm,
+__device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int i, const double *wm,
                                           const double *wp, double *F) {
   bool ok = numflux1<FLUX>(a.ph, wm, wp, F);
-  const int i = a.face_if[f];
   if (i >= 0) {
     double *rec = ring_rec(a.ring, n, a.stage, a.dl.nif, i) + a.ring.off_F;
 #pragma unroll
@@ -64,76 +63,72 @@ __device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int f
   return ok;
 }
 
+// Wavefront-local stage kernel.  Lane l of a wavefront holds element
+// base + l - 1 (base = 62 * wavefront index): lanes 1..62 own their element,
+// lanes 0 and 63 hold the halo neighbours, loaded together with the owned
+// elements.  Lane k computes the flux at the face between its element and lane
+// k+1's; traces and fluxes move between lanes by cross-lane shuffles, so no
+// LDS and no workgroup barrier is needed.
 template <int M, int FLUX>
 __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
   constexpr int V = 5, Q = M;
-  __shared__ double sR[kEulerBlock + 1][V];  // right trace of the element left of face t
-  __shared__ double sL[kEulerBlock + 1][V];  // left trace of the element right of face t
-  __shared__ double sF[kEulerBlock + 1][V];  // numerical flux at face e0 + t
-  const int t = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int base = ((blockIdx.x * kEulerBlock + threadIdx.x) >> 6) * kWaveElems;
   const int E = a.E;
-  const int e0 = blockIdx.x * kEulerBlock;
-  const int nloc = min(kEulerBlock, E - e0);
-  const bool act = t < nloc;
-  const int e = e0 + t;
+  const int xu = base + lane - 1;                       // element index before periodic wrap
+  const bool live = base < E;
+  const bool own = live && lane >= 1 && lane <= kWaveElems && xu < E;
+  const bool ghost_l = !a.periodic && xu == -1;         // transmissive ends: ghost = interior trace
+  const bool ghost_r = !a.periodic && xu == E;
+  const bool loads = live && xu <= E && !ghost_l && !ghost_r;
+  const bool face_lane = live && lane <= kWaveElems && xu + 1 <= E;  // face xu + 1 in [0, E]
+  int x = xu % E;
+  if (x < 0) x += E;
   const long long n = *a.step;
   bool ok = true;
 
-  double u[V][M];
+  double u[V][M], wn[V][M];
+  if (loads) {
+    load_elem<M>(a.ws, E, x, u);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int j = 0; j < M; ++j) u[v][j] = 0.0;
+  }
+  const int iface = face_lane ? a.face_if[xu + 1] : -1;
+
   double wl[V], wr[V];
-  if (act) {
-    load_elem<M>(a.ws, E, e, u);
-    traces<M>(u, wl, wr);
+  traces<M>(u, wl, wr);
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      sR[t + 1][v] = wr[v];
-      sL[t][v] = wl[v];
-    }
+  for (int v = 0; v < V; ++v) {
+    const double next_l = __shfl_down(wl[v], 1);
+    const double prev_r = __shfl_up(wr[v], 1);
+    if (ghost_l) wr[v] = next_l;
+    if (ghost_r) wl[v] = prev_r;
   }
-  if (t == 0) {
-    if (e0 == 0 && !a.periodic) {
+  // flux at the face to the right of this lane's element
+  double F[V];
+  {
+    double wp[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) sR[0][v] = wl[v];   // ghost = interior trace
-    } else {
-      double nb[V][M], tl[V], tr[V];
-      load_elem<M>(a.ws, E, e0 == 0 ? E - 1 : e0 - 1, nb);
-      traces<M>(nb, tl, tr);
-#pragma unroll
-      for (int v = 0; v < V; ++v) sR[0][v] = tr[v];
-    }
+    for (int v = 0; v < V; ++v) wp[v] = __shfl_down(wl[v], 1);
+    const bool fok = face_flux<FLUX>(a, n, iface, wr, wp, F);
+    if (face_lane) ok = fok && ok;
   }
-  if (t == nloc - 1) {
-    if (e == E - 1 && !a.periodic) {
+  double Fl[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) sL[nloc][v] = wr[v];
-    } else {
-      double nb[V][M], tl[V], tr[V];
-      load_elem<M>(a.ws, E, e == E - 1 ? 0 : e + 1, nb);
-      traces<M>(nb, tl, tr);
-#pragma unroll
-      for (int v = 0; v < V; ++v) sL[nloc][v] = tl[v];
-    }
-  }
-  __syncthreads();
-  if (act) {
-    double F[V];
-    ok = face_flux<FLUX>(a, n, e, sR[t], sL[t], F) && ok;
-#pragma unroll
-    for (int v = 0; v < V; ++v) sF[t][v] = F[v];
-    if (t == nloc - 1) {
-      ok = face_flux<FLUX>(a, n, e + 1, sR[nloc], sL[nloc], F) && ok;
-#pragma unroll
-      for (int v = 0; v < V; ++v) sF[nloc][v] = F[v];
-    }
-  }
-  __syncthreads();
-  if (act) {
+  for (int v = 0; v < V; ++v) Fl[v] = __shfl_up(F[v], 1);
+  const int if_left = __shfl_up(iface, 1);
+
+  if (own) {
+    // b_j = sum_q w_q P_j'(xi_q) f_q - F_{e+1} P_j(1) + F_e P_j(-1); the face terms go in first
     double vol[V][M], srcR[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       srcR[j] = 0.0;
 #pragma unroll
-      for (int v = 0; v < V; ++v) vol[v][j] = 0.0;
+      for (int v = 0; v < V; ++v) vol[v][j] = -F[v] + ((j & 1) ? -Fl[v] : Fl[v]);
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -149,7 +144,7 @@ __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
       ok = prim1(a.ph, wq, pr) && ok;
       double f[V];
       flux1(wq, pr, f);
-      const double rate = a.ph.k_pre * wq[3] * exp(-a.ph.e_act / pr.T);
+      const double rate = a.ph.k_pre * wq[3] * exp(-a.ph.e_act * (pr.rho / pr.p));
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const double g = a.tb.WG[q][j];
@@ -158,49 +153,31 @@ __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
         srcR[j] += a.tb.WB[q][j] * (-rate);
       }
     }
-    const double *Fl = sF[t], *Fr = sF[t + 1];
-    double out[V][M];
+    if (a.stage != 0) load_elem<M>(a.w0, E, x, wn);
     const bool st_last = a.stage == 2;
+    double *recR = (a.store_U && if_left >= 0)   // this element is right of interface if_left
+                       ? ring_rec(a.ring, n, a.stage, a.dl.nif, if_left) + a.ring.off_U + V * M : nullptr;
+    double *recL = (a.store_U && iface >= 0)     // left of interface iface
+                       ? ring_rec(a.ring, n, a.stage, a.dl.nif, iface) + a.ring.off_U : nullptr;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const double half2j1 = 0.5 * (2 * j + 1);
-        const double b = vol[v][j] + (-Fr[v] + ((j & 1) ? -Fl[v] : Fl[v]));
         double s = 0.0;
         if (v == 3) s = srcR[j];
         if (v == 4) s = -srcR[j];
-        const double L = a.two_over_dx * (half2j1 * b) + half2j1 * s;
+        const double L = a.two_over_dx * (half2j1 * vol[v][j]) + half2j1 * s;
         const double y = u[v][j] + a.dt * L;
         double o;
         if (a.stage == 0) {
           o = y;
         } else {
-          const double wn = a.w0[(size_t)(v * M + j) * E + e];
-          o = st_last ? (1.0 / 3.0) * wn + (2.0 / 3.0) * y : 0.75 * wn + 0.25 * y;
+          o = st_last ? (1.0 / 3.0) * wn[v][j] + (2.0 / 3.0) * y : 0.75 * wn[v][j] + 0.25 * y;
         }
-        out[v][j] = o;
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-#pragma unroll
-      for (int j = 0; j < M; ++j) a.wout[(size_t)(v * M + j) * E + e] = out[v][j];
-    if (a.store_U) {
-      const int il = a.face_if[e], ir = a.face_if[e + 1];
-      if (il >= 0) {  // this element is right of interface il
-        double *rec = ring_rec(a.ring, n, a.stage, a.dl.nif, il) + a.ring.off_U + V * M;
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-#pragma unroll
-          for (int j = 0; j < M; ++j) rec[v * M + j] = out[v][j];
-      }
-      if (ir >= 0) {  // left of interface ir
-        double *rec = ring_rec(a.ring, n, a.stage, a.dl.nif, ir) + a.ring.off_U;
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-#pragma unroll
-          for (int j = 0; j < M; ++j) rec[v * M + j] = out[v][j];
+        a.wout[sidx(x, v * M + j, V * M)] = o;
+        if (recR) recR[v * M + j] = o;
+        if (recL) recL[v * M + j] = o;
       }
     }
   }
@@ -409,7 +386,7 @@ __global__ __launch_bounds__(128) void limiter_kernel(LimiterArgs a) {
 #pragma unroll
   for (int v = 0; v < 5; ++v)
 #pragma unroll
-    for (int j = 0; j < M; ++j) a.wlim[(size_t)(v * M + j) * a.E + e] = wl[v][j];
+    for (int j = 0; j < M; ++j) a.wlim[sidx(e, v * M + j, 5 * M)] = wl[v][j];
 }
 
 // Writes the limited values of troubled cells back (after every stencil has read
@@ -422,32 +399,33 @@ __global__ __launch_bounds__(256) void limiter_scatter_kernel(LimiterArgs a) {
     for (int v = 0; v < 5; ++v)
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const size_t idx = (size_t)(v * M + j) * a.E + e;
+        const size_t idx = sidx(e, v * M + j, 5 * M);
         a.w[idx] = a.wlim[idx];
       }
   }
   if (a.advance) finish_step(a.step, a.done);
 }
 
-// [E][VM] <-> [VM][E]
+// caller layout [E][VM] <-> device layout (sidx)
 __global__ void to_planes_kernel(const double *__restrict__ src, double *__restrict__ dst, int E, int VM) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)E * VM) return;
-  const int c = (int)(idx / E), e = (int)(idx % E);
-  dst[idx] = src[(long long)e * VM + c];
+  const int e = (int)(idx / VM), c = (int)(idx % VM);
+  dst[sidx(e, c, VM)] = src[idx];
 }
 __global__ void from_planes_kernel(const double *__restrict__ src, double *__restrict__ dst, int E, int VM) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)E * VM) return;
   const int e = (int)(idx / VM), c = (int)(idx % VM);
-  dst[idx] = src[(long long)c * E + e];
+  dst[idx] = src[sidx(e, c, VM)];
 }
 
 // ---------------------------------------------------------------- launchers
 
 template <int M>
 static hipError_t stage_M(int flux, const EulerArgs &a, hipStream_t s) {
-  const int blocks = (a.E + kEulerBlock - 1) / kEulerBlock;
+  const int waves = (a.E + kWaveElems - 1) / kWaveElems;
+  const int blocks = (waves + kEulerBlock / 64 - 1) / (kEulerBlock / 64);
   if (flux == 1) hipLaunchKernelGGL((euler_stage_kernel<M, 1>), dim3(blocks), dim3(kEulerBlock), 0, s, a);
   else hipLaunchKernelGGL((euler_stage_kernel<M, 0>), dim3(blocks), dim3(kEulerBlock), 0, s, a);
   return hipGetLastError();

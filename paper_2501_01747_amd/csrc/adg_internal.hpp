@@ -1,7 +1,5 @@
 // Internal declarations shared by the host runtime and the HIP kernels of the
-// ADG library.  Device state layout: component planes [v][j][e] (element index
-// fastest) so that a wavefront reading one (variable, mode) plane of 64
-// consecutive elements issues one fully coalesced 512-byte access.
+// ADG library.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,6 +12,7 @@ constexpr int kMaxQ = 5;      // Gauss points = N_p + 1
 constexpr int kMaxL = 8;      // admissible delays
 constexpr int kMaxAT = 6;     // AT order q
 constexpr int kEulerBlock = 256;
+constexpr int kWaveElems = 62;   // elements owned by one wavefront of the Euler stage kernel
 
 // Delay model of Sec. 4 (CAA / SAA) and the start-up clamp k <= n - q + 1.
 struct DelayParams {
@@ -36,6 +35,19 @@ struct RingParams {
   int rec;
   int off_F, off_Wc, off_U;
 };
+
+// Device state layout: blocks of 64 elements, each block holding its V*M
+// component segments of 64 consecutive elements: [E/64][V*M][64].  A wavefront
+// reading one component of 64 neighbouring elements issues one contiguous
+// 512-byte access, and all components of those elements lie in one 64*V*M*8
+// byte span.
+constexpr int kLayoutBlock = 64;
+__host__ __device__ inline size_t sidx(int e, int c, int VM) {
+  return ((size_t)(e >> 6) * VM + c) * kLayoutBlock + (e & 63);
+}
+__host__ __device__ inline size_t state_doubles(int E, int VM) {
+  return (size_t)((E + kLayoutBlock - 1) / kLayoutBlock) * kLayoutBlock * VM;
+}
 
 __host__ __device__ inline double *ring_rec(const RingParams &r, long long level, int stage, int nif, int i) {
   long long slot = level % r.D;

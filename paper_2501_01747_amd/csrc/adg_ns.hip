@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     const int c = idx / NH, l = idx % NH;
     int e = (e0 - 2 + l) % E;
     if (e < 0) e += E;
-    sW[c][l] = a.ws[(size_t)c * E + e];
+    sW[c][l] = a.ws[sidx(e, c, V * M)];
   }
   for (int idx = t; idx < Q * M; idx += kThreads) {
     const int qn = idx / M, j = idx % M;
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     const double b = vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
     const double L = 2.0 * a.inv_dx * (half2j1 * b) + half2j1 * src;
     const double y = sW[c][el + 2] + a.dt * L;
-    const size_t gi = (size_t)c * E + e0 + el;
+    const size_t gi = sidx(e0 + el, c, V * M);
     double o;
     if (a.stage == 0) o = y;
     else if (a.stage == 1) o = 0.75 * a.w0[gi] + 0.25 * y;

@@ -144,3 +144,24 @@ def test_bad_state_is_reported(adg):
     with pytest.raises(adg.AdgError) as ei:
         s.state()
     assert ei.value.code == adg.ADG_ERR_STATE
+
+
+def test_c2_full_size_limiter(adg, orc):
+    """The C2 workload at full size (E = 8192, N_p = 3, HLLC, KXRCF + AT-WENO, 64 PEs, delays
+    up to 3) in the launch configuration of the benchmark: every step compared, flags included."""
+    case, w0 = gen.case_c2()
+    s = adg.Solver(case)
+    s.set_graph(10)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, 61)
+    worst = 0.0
+    for k in range(6):
+        s.step(10)
+        o.step(10)
+        r = rel_l2(s.state(), o.state())
+        worst = max(worst, r)
+        fg, tot = s.flags()
+        assert np.array_equal(fg, o.flags()), k
+        assert tot == o.total_flags()
+        assert r < 1e-10, (k, r)
+    print(f"[parity] c2 full size: worst rel L2 {worst:.2e}, troubled cells so far {tot}")
