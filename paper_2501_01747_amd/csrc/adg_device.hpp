@@ -49,15 +49,16 @@ __device__ __forceinline__ double at_weight(int q, int k, int j) {
   return (double)num / (double)den;
 }
 
-// End of a time step, called by every workgroup of the step's last kernel after
-// its work: the last workgroup to finish advances the step counter.  Every
-// workgroup has read the counter at its start, before it signs in here.
-__device__ __forceinline__ void finish_step(long long *step, unsigned *done) {
+// End of a time step, called by every one of the `nblocks` workgroups that work
+// on one problem in the step's last kernel, after its work: the last one to
+// finish advances the problem's step counter.  Every workgroup has read the
+// counter at its start, before it signs in here.
+__device__ __forceinline__ void finish_step(long long *step, unsigned *done, unsigned nblocks) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
     const unsigned prev = atomicAdd(done, 1u);
-    if (prev == gridDim.x - 1) {
+    if (prev == nblocks - 1) {
       atomicAdd((unsigned long long *)step, 1ull);
       atomicExch(done, 0u);
       __threadfence();

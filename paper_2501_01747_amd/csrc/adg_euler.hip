@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
     }
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
-  if (a.advance) finish_step(a.step, a.done);
+  if (a.advance) finish_step(a.step, a.done, gridDim.x);
 }
 
 // ------------------------------------------------------------------- limiter
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void limiter_scatter_kernel(LimiterArgs a) {
         a.w[idx] = a.wlim[idx];
       }
   }
-  if (a.advance) finish_step(a.step, a.done);
+  if (a.advance) finish_step(a.step, a.done, gridDim.x);
 }
 
 // caller layout [E][VM] <-> device layout (sidx)

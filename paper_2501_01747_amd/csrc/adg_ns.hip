@@ -24,28 +24,25 @@
 
 namespace adg {
 
-constexpr int kTile = 8;
+constexpr int kTile = kNsTile;
 constexpr int kThreads = 256;
 
-template <int NS>
 struct Thermo {
   double T, cp, cv, p, a;
-  double hRT[NS];    // h_i / (R_i T)
-  double eR[NS];     // e_i / R_i = T (h/(R T) - 1)
 };
 
 // Temperature from the internal energy by Newton's method from the fixed start
-// T_guess, |dT| <= 1e-12 T; then the thermodynamic state at that T.  The
-// mixture energy sum_i Y_i e_i(T) is linear in the species, so its polynomial
-// coefficients are formed once per point and the iteration runs on one
-// quintic: e(T)/1 = T (c0 + T (c1 + T (c2 + T (c3 + T c4)))) + c5.
+// T_guess, |dT| <= 1e-12 T; then cp, cv, p and the frozen sound speed at that T.
+// The mixture energy sum_i Y_i e_i(T) is linear in the species, so its
+// polynomial coefficients are formed once per point and the iteration runs on
+// one quintic: e(T) = T (c0 + T (c1 + T (c2 + T (c3 + T c4)))) + c5.
 template <int NS>
-__device__ __forceinline__ bool ns_thermo(const NsMech *__restrict__ mk, const double *Y, double rho, double estar,
-                                          Thermo<NS> &th) {
+__device__ __forceinline__ bool ns_thermo(const NsMech *__restrict__ mk, const double *w, int st, double rho_inv,
+                                          double estar, Thermo &th) {
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0, c5 = 0.0, Rmix = 0.0;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const double yr = Y[i] * mk->Ri[i];
+    const double yr = (w[(3 + i) * st] * rho_inv) * mk->Ri[i];
     c0 += yr * (mk->a[i][0] - 1.0);
     c1 += yr * mk->h2[i][0];
     c2 += yr * mk->h2[i][1];
@@ -67,51 +64,44 @@ __device__ __forceinline__ bool ns_thermo(const NsMech *__restrict__ mk, const d
     if (fabs(dT) <= 1e-12 * T) { conv = true; break; }
   }
   th.T = T;
-  const double invT = 1.0 / T;
-  const double cv = c0 + T * (d1 + T * (d2 + T * (d3 + T * d4)));
-#pragma unroll
+  th.cv = c0 + T * (d1 + T * (d2 + T * (d3 + T * d4)));
+  th.cp = th.cv + Rmix;
+  th.p = w[0] * Rmix * T;
+  th.a = sqrt(th.cp / th.cv * th.p * rho_inv);
+  return conv && th.p > 0.0 && isfinite(th.p) && w[0] > 0.0;
+}
+
+// Subtracts f^d of Eq. (2)-(3) from g (stride gs): tau = 4/3 mu u_x,
+// q = -k T_x + sum_i h_i J_i, unit Lewis number J_i = -rho D dY_i/dx with
+// rho D = mu/Pr.  Species enthalpies are re-evaluated at T (no arrays kept).
+template <int NS>
+__device__ __forceinline__ void ns_diffusive_sub(const NsMech *__restrict__ mk, const double *w, int st,
+                                                 double rho_inv, double u, const Thermo &th, double mu,
+                                                 const double *dw, double *g, int gs) {
+  const double T = th.T;
+  const double kappa = mu * th.cp * mk->inv_prandtl;
+  const double rhoD = mu * mk->inv_prandtl;
+  const double dw0 = dw[0];
+  const double u_x = (dw[st] - u * dw0) * rho_inv;
+  const double E = w[2 * st] * rho_inv;
+  const double e_x = (dw[2 * st] - E * dw0) * rho_inv - u * u_x;
+  double sum_eY = 0.0, sum_hJ = 0.0;
+#pragma unroll 1
   for (int i = 0; i < NS; ++i) {
     const double *a = mk->a[i];
     const double *h2 = mk->h2[i];
-    const double hT = T * (a[0] + T * (h2[0] + T * (h2[1] + T * (h2[2] + T * h2[3])))) + a[5];
-    th.hRT[i] = hT * invT;
-    th.eR[i] = hT - T;
-  }
-  th.cv = cv;
-  th.cp = cv + Rmix;
-  th.p = rho * Rmix * T;
-  th.a = sqrt(th.cp / cv * th.p / rho);
-  return conv && th.p > 0.0 && isfinite(th.p) && rho > 0.0;
-}
-
-// f^d of Eq. (2)-(3) with unit Lewis number: J_i = -rho D dY_i/dx, rho D = mu/Pr.
-template <int NS>
-__device__ __forceinline__ void ns_diffusive(const NsMech *__restrict__ mk, const double *w, const double *Y, double u,
-                                             double rho_inv, const Thermo<NS> &th, double mu, const double *dw,
-                                             double *fd) {
-  const double kappa = mu * th.cp * mk->inv_prandtl;
-  const double rhoD = mu * mk->inv_prandtl;
-  const double u_x = (dw[1] - u * dw[0]) * rho_inv;
-  const double E = w[2] * rho_inv;
-  const double e_x = (dw[2] - E * dw[0]) * rho_inv - u * u_x;
-  double sum_eY = 0.0, sum_hJ = 0.0;
-  double Jm[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const double Yx = (dw[3 + i] - Y[i] * dw[0]) * rho_inv;
-    sum_eY += mk->Ri[i] * th.eR[i] * Yx;
+    const double hT = T * (a[0] + T * (h2[0] + T * (h2[1] + T * (h2[2] + T * h2[3])))) + a[5];  // h_i/R_i
+    const double Yx = (dw[(3 + i) * st] - (w[(3 + i) * st] * rho_inv) * dw0) * rho_inv;
+    sum_eY += mk->Ri[i] * (hT - T) * Yx;
     const double J = -rhoD * Yx;
-    Jm[i] = J;
-    sum_hJ += mk->Ri[i] * th.T * th.hRT[i] * J;
+    sum_hJ += mk->Ri[i] * hT * J;
+    g[(3 + i) * gs] += J;            // f^d_i = -J_i
   }
   const double T_x = (e_x - sum_eY) / th.cv;
   const double tau = (4.0 / 3.0) * mu * u_x;
   const double qh = -kappa * T_x + sum_hJ;
-  fd[0] = 0.0;
-  fd[1] = tau;
-  fd[2] = tau * u - qh;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) fd[3 + i] = -Jm[i];
+  g[1 * gs] -= tau;
+  g[2 * gs] -= tau * u - qh;
 }
 
 // Mass-action source W_i omega_i of the reversible mechanism.
@@ -161,78 +151,113 @@ __device__ __forceinline__ void ns_source(const NsMech *__restrict__ mk, const d
   for (int i = 0; i < NS; ++i) src[i] = mk->W[i] * wdot[i];
 }
 
-// Everything but the chemistry evaluated at one point: g = f^c - f^d (and
-// g_sync with the synchronous gradient when dw_sync is given), the spectral
-// radius |u| + a and the temperature.
+// Everything but the chemistry evaluated at one point, written to LDS:
+// g = f^c - f^d (stride gs), and when `sync` also g_sync with the synchronous
+// gradient dw_sync; returns the spectral radius |u| + a and the temperature.
 template <int NS>
-__device__ __forceinline__ bool ns_point(const NsMech *__restrict__ mk, int viscous, const double (&w)[3 + NS],
-                                         const double (&dw)[3 + NS], bool sync, const double (&dw_sync)[3 + NS],
-                                         double (&g)[3 + NS], double (&g_sync)[3 + NS], double &lam, double &T) {
-  constexpr int V = 3 + NS;
-  const double rho = w[0];
-  const double rho_inv = 1.0 / rho;
-  const double u = w[1] * rho_inv;
-  double Y[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) Y[i] = w[3 + i] * rho_inv;
-  const double estar = w[2] * rho_inv - 0.5 * u * u;
-  Thermo<NS> th;
-  const bool ok = ns_thermo<NS>(mk, Y, rho, estar, th);
+__device__ __forceinline__ bool ns_point(const NsMech *__restrict__ mk, int viscous, const double *w,
+                                         const double *dw, bool sync, const double *dw_sync, int st, double *g,
+                                         double *g_sync, int gs, double &lam, double &T) {
+  const double rho_inv = 1.0 / w[0];
+  const double u = w[st] * rho_inv;
+  const double estar = w[2 * st] * rho_inv - 0.5 * u * u;
+  Thermo th;
+  const bool ok = ns_thermo<NS>(mk, w, st, rho_inv, estar, th);
   lam = fabs(u) + th.a;
-  g[0] = w[1];
-  g[1] = w[1] * u + th.p;
-  g[2] = u * (w[2] + th.p);
+  T = th.T;
+  const double fc0 = w[st], fc1 = w[st] * u + th.p, fc2 = u * (w[2 * st] + th.p);
+  g[0] = fc0;
+  g[gs] = fc1;
+  g[2 * gs] = fc2;
 #pragma unroll
-  for (int i = 0; i < NS; ++i) g[3 + i] = w[3 + i] * u;
+  for (int i = 0; i < NS; ++i) g[(3 + i) * gs] = w[(3 + i) * st] * u;
+  if (sync) {
+    g_sync[0] = fc0;
+    g_sync[gs] = fc1;
+    g_sync[2 * gs] = fc2;
 #pragma unroll
-  for (int v = 0; v < V; ++v) g_sync[v] = g[v];
+    for (int i = 0; i < NS; ++i) g_sync[(3 + i) * gs] = w[(3 + i) * st] * u;
+  }
   if (viscous) {
     const double mu = mk->mu_ref * exp(mk->mu_exp * log(th.T * mk->inv_T_ref));
-    double fd[V];
-    ns_diffusive<NS>(mk, w, Y, u, rho_inv, th, mu, dw, fd);
-#pragma unroll
-    for (int v = 0; v < V; ++v) g[v] -= fd[v];
-    if (sync) {
-      ns_diffusive<NS>(mk, w, Y, u, rho_inv, th, mu, dw_sync, fd);
-#pragma unroll
-      for (int v = 0; v < V; ++v) g_sync[v] -= fd[v];
-    }
+    ns_diffusive_sub<NS>(mk, w, st, rho_inv, u, th, mu, dw, g, gs);
+    if (sync) ns_diffusive_sub<NS>(mk, w, st, rho_inv, u, th, mu, dw_sync, g_sync, gs);
   }
-  T = th.T;
   return ok;
 }
 
+// LDS arena of one tile.
 template <int M, int NS>
-__global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
+struct NsLds {
+  static constexpr int V = 3 + NS, Q = M, TE = kTile;
+  static constexpr int NH = TE + 4;   // tile + 2 halo elements per side; local l <-> element e0 - 2 + l
+  static constexpr int NF = TE + 3;   // faces e0-1 .. e0+TE+1; local fl <-> face e0 - 1 + fl
+  static constexpr int NQ = TE + 2;   // gradients of elements e0-1 .. e0+TE; local lq <-> element e0 - 1 + lq
+  static constexpr int NN = TE * Q;   // quadrature nodes of the tile; node p <-> element p / Q, node p % Q
+  static constexpr int NR = kNsMaxReactions;
+  double sW[V * M][NH];
+  double sTm[V][NH], sTp[V][NH];
+  double sWc[V][NF], sWa[V][NF];
+  double sQ[V * M][NQ];
+  double sG[V][NN];
+  double sS[NS][NN];
+  double sT[NN];
+  double sConc[NS][NN], sGRT[NS][NN];
+  double sRate[NR][NN];
+  double sGf[2][V][TE + 1], sGs[2][V][TE + 1];
+  double sLam[2][TE + 1];
+  static constexpr int NP = NN + 2 * (TE + 1);   // points: the nodes, then the face traces
+  double sPw[V][NP], sPd[V][NP], sPs[V][NP];   // value, gradient, synchronous gradient (PE traces)
+  double sF[V][TE + 1], sFat[V][TE + 1];
+  double sB[Q][M], sWG[Q][M], sWB[Q][M], sD[M][M];   // tables, indexed at run time
+  int sI[NF], sK[NF];
+};
+
+// One tile of one stage (all phases).  OpT is the arithmetic type of the modal
+// operators (interpolation, traces, LDG gradient, projection and lift): double
+// for the plain path, float for the mixed-precision path.  Point physics
+// (temperature Newton, fluxes, transport, chemistry) and the RK update are
+// FP64 in both.
+template <int M, int NS, typename OpT>
+__device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
+                                        double *wout, int stage, int advance, int e0, int ntiles,
+                                        NsLds<M, NS> &Ls, NsMech &smech) {
   constexpr int V = 3 + NS, Q = M, TE = kTile;
-  constexpr int NH = TE + 4;   // tile + 2 halo elements per side; local l <-> element e0 - 2 + l
-  constexpr int NF = TE + 3;   // faces e0-1 .. e0+TE+1; local fl <-> face e0 - 1 + fl
-  constexpr int NQ = TE + 2;   // gradients of elements e0-1 .. e0+TE; local lq <-> element e0 - 1 + lq
-  constexpr int NN = TE * Q;   // quadrature nodes of the tile; node p <-> element p / Q, node p % Q
+  constexpr int NH = NsLds<M, NS>::NH, NF = NsLds<M, NS>::NF, NQ = NsLds<M, NS>::NQ, NN = NsLds<M, NS>::NN;
   constexpr int NT = 2 * (TE + 1);  // face traces; trace pp <-> face e0 + pp/2, side pp%2
-  constexpr int NR = kNsMaxReactions;
   static_assert(NN <= 64 && NT <= 64, "node and trace lanes each fit one wavefront");
-  __shared__ double sW[V * M][NH];
-  __shared__ double sTm[V][NH], sTp[V][NH];
-  __shared__ double sWc[V][NF], sWa[V][NF];
-  __shared__ double sQ[V * M][NQ];
-  __shared__ double sG[V][NN];
-  __shared__ double sS[NS][NN];
-  __shared__ double sT[NN];
-  __shared__ double sConc[NS][NN], sGRT[NS][NN];
-  __shared__ double sRate[NR][NN];
-  __shared__ double sGf[2][V][TE + 1], sGs[2][V][TE + 1];
-  __shared__ double sLam[2][TE + 1];
-  __shared__ double sF[V][TE + 1], sFat[V][TE + 1];
-  __shared__ int sI[NF], sK[NF];
-  __shared__ double sB[Q][M], sWG[Q][M], sWB[Q][M], sD[M][M];   // tables, indexed at run time
+  auto &sW = Ls.sW;
+  auto &sTm = Ls.sTm;
+  auto &sTp = Ls.sTp;
+  auto &sWc = Ls.sWc;
+  auto &sWa = Ls.sWa;
+  auto &sQ = Ls.sQ;
+  auto &sG = Ls.sG;
+  auto &sS = Ls.sS;
+  auto &sT = Ls.sT;
+  auto &sConc = Ls.sConc;
+  auto &sGRT = Ls.sGRT;
+  auto &sRate = Ls.sRate;
+  auto &sGf = Ls.sGf;
+  auto &sGs = Ls.sGs;
+  auto &sLam = Ls.sLam;
+  auto &sF = Ls.sF;
+  auto &sFat = Ls.sFat;
+  auto &sB = Ls.sB;
+  auto &sWG = Ls.sWG;
+  auto &sWB = Ls.sWB;
+  auto &sD = Ls.sD;
+  auto &sI = Ls.sI;
+  auto &sK = Ls.sK;
+  auto &sPw = Ls.sPw;
+  auto &sPd = Ls.sPd;
+  auto &sPs = Ls.sPs;
+  constexpr int NP = NsLds<M, NS>::NP;
 
   const int t = threadIdx.x;
   const int E = a.E;
-  const int e0 = blockIdx.x * TE;
   const int nloc = min(TE, E - e0);
   const long long n = *a.step;
-  __shared__ NsMech smech;
   const NsMech *__restrict__ mk = &smech;
   const int q_at = a.dl.q;
   bool ok = true;
@@ -249,7 +274,7 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     const int c = idx / NH, l = idx % NH;
     int e = (e0 - 2 + l) % E;
     if (e < 0) e += E;
-    sW[c][l] = a.ws[sidx(e, c, V * M)];
+    sW[c][l] = ws[sidx(e, c, V * M)];
   }
   for (int idx = t; idx < Q * M; idx += kThreads) {
     const int qn = idx / M, j = idx % M;
@@ -272,15 +297,15 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   //    traces and of the fluxes at delayed PE interfaces are gathered from the ring
   for (int idx = t; idx < V * NH; idx += kThreads) {
     const int v = idx / NH, l = idx % NH;
-    double sm = 0.0, sp = 0.0;
+    OpT sm = 0, sp = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      const double c = sW[v * M + j][l];
+      const OpT c = (OpT)sW[v * M + j][l];
       sp += c;
       sm += (j & 1) ? -c : c;
     }
-    sTm[v][l] = sm;
-    sTp[v][l] = sp;
+    sTm[v][l] = (double)sm;
+    sTp[v][l] = (double)sp;
   }
   for (int idx = t; idx < V * NF; idx += kThreads) {
     const int v = idx / NF, fl = idx % NF;
@@ -289,7 +314,7 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     double acw = 0.0, acf = 0.0;
     for (int j = 0; j < q_at; ++j) {
       const double c = at_weight(q_at, k, j);
-      const double *rec = ring_rec(a.ring, n - k - j, a.stage, a.dl.nif, i);
+      const double *rec = ring_rec(a.ring, n - k - j, stage, a.dl.nif, i);
       acw += c * rec[a.ring.off_Wc + v];
       acf += c * rec[a.ring.off_F + v];
     }
@@ -302,10 +327,10 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   //    The synchronous value of a PE interface is published for this level.
   for (int idx = t; idx < V * NF; idx += kThreads) {
     const int v = idx / NF, fl = idx % NF;
-    const double wc = 0.5 * (sTp[v][fl] + sTm[v][fl + 1]);
+    const double wc = (double)((OpT)0.5 * ((OpT)sTp[v][fl] + (OpT)sTm[v][fl + 1]));
     const int i = sI[fl];
     if (i >= 0 && fl >= 1 && fl <= nloc)   // faces e0 .. e0+nloc-1 are owned by this tile
-      ring_rec(a.ring, n, a.stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
+      ring_rec(a.ring, n, stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
     sWc[v][fl] = wc;
     if (i < 0 || sK[fl] == 0) sWa[v][fl] = wc;
   }
@@ -316,85 +341,83 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   for (int idx = t; idx < V * M * NQ; idx += kThreads) {
     const int c = idx / NQ, lq = idx % NQ;
     const int v = c / M, j = c % M;
-    double vol = 0.0;
+    OpT vol = 0;
 #pragma unroll
-    for (int k = 0; k < M; ++k) vol += sD[j][k] * sW[v * M + k][lq + 1];
-    const double wl = (j & 1) ? -sWa[v][lq] : sWa[v][lq];
-    sQ[c][lq] = (2 * j + 1) * a.inv_dx * (sWa[v][lq + 1] - wl - vol);
+    for (int k = 0; k < M; ++k) vol += (OpT)sD[j][k] * (OpT)sW[v * M + k][lq + 1];
+    const OpT wl = (OpT)((j & 1) ? -sWa[v][lq] : sWa[v][lq]);
+    sQ[c][lq] = (double)((OpT)((2 * j + 1) * a.inv_dx) * ((OpT)sWa[v][lq + 1] - wl - vol));
   }
   __syncthreads();
 
-  // 4a. point evaluations: wavefront 0 takes the quadrature nodes, wavefront 1 the face traces
-  if (t < NN) {
-    const int el = t / Q, qn = t % Q;
-    double w[V], dw[V], g[V], gs[V], lam, T;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      double x = 0.0, d = 0.0;
+  // 4a. values and gradients at every point (quadrature nodes of the tile, then both traces
+  //     of faces e0 .. e0+TE) into LDS, one lane per (point, variable)
+  for (int idx = t; idx < V * NP; idx += kThreads) {
+    const int v = idx / NP, p = idx % NP;
+    if (p < NN) {
+      const int el = p / Q, qn = p % Q;
+      OpT x = 0, d = 0;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        x += sB[qn][j] * sW[v * M + j][el + 2];
-        d += sB[qn][j] * sQ[v * M + j][el + 1];
+        x += (OpT)sB[qn][j] * (OpT)sW[v * M + j][el + 2];
+        d += (OpT)sB[qn][j] * (OpT)sQ[v * M + j][el + 1];
       }
-      w[v] = x;
-      dw[v] = d;
-    }
-    ok = ns_point<NS>(mk, a.viscous, w, dw, false, dw, g, gs, lam, T) && ok;
+      sPw[v][p] = (double)x;
+      sPd[v][p] = (double)d;
+    } else {
+      const int pp = p - NN;
+      const int ff = pp >> 1, side = pp & 1;  // face e0 + ff; side 0 = element left of it (at xi = +1)
+      const int l = ff + 1 + side;            // local element
+      const int lq = ff + side;               // its gradient slot; faces lq (left), lq + 1 (right)
+      const OpT sgn = side ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
+      OpT d = 0, pj = 1;
 #pragma unroll
-    for (int v = 0; v < V; ++v) sG[v][t] = g[v];
+      for (int j = 0; j < M; ++j) {
+        d += pj * (OpT)sQ[v * M + j][lq];
+        pj *= sgn;
+      }
+      sPw[v][p] = side ? sTm[v][l] : sTp[v][l];
+      sPd[v][p] = (double)d;
+      if (sI[ff + 1] >= 0) {
+        // synchronous gradient trace at a PE interface: undo the AT central traces of the element's faces
+        const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
+        double corr = 0.0, pk = 1.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
+          pk *= side ? -1.0 : 1.0;
+        }
+        sPs[v][p] = (double)d + corr;
+      }
+    }
+  }
+  __syncthreads();
+
+  // 4b. point physics: wavefront 0 takes the quadrature nodes, wavefront 1 the face traces
+  if (t < NN) {
+    double lam, T;
+    ok = ns_point<NS>(mk, a.viscous, &sPw[0][t], &sPd[0][t], false, &sPd[0][t], NP, &sG[0][t], &sG[0][t], NN,
+                      lam, T) && ok;
     sT[t] = T;
   } else if (t >= 64 && t < 64 + NT) {
     const int pp = t - 64;
-    const int ff = pp >> 1, side = pp & 1;  // face e0 + ff; side 0 = element left of it (at xi = +1)
-    const int l = ff + 1 + side;            // local element
-    const int lq = ff + side;               // its gradient slot; faces lq (left), lq + 1 (right)
-    const double sgn = side ? -1.0 : 1.0;   // P_j(+-1) = (+-1)^j
-    double w[V], dw[V], g[V], gs[V], dws[V], lam, T;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      w[v] = side ? sTm[v][l] : sTp[v][l];
-      double d = 0.0, pj = 1.0;
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        d += pj * sQ[v * M + j][lq];
-        pj *= sgn;
-      }
-      dw[v] = d;
-      dws[v] = d;
-    }
+    const int ff = pp >> 1, side = pp & 1;
     const bool pe = sI[ff + 1] >= 0;
-    if (pe) {
-      // synchronous gradient trace: undo the AT central traces of this element's faces
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
-        double corr = 0.0, pj = 1.0;
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          corr += pj * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
-          pj *= sgn;
-        }
-        dws[v] = dw[v] + corr;
-      }
-    }
-    ok = ns_point<NS>(mk, a.viscous, w, dw, pe, dws, g, gs, lam, T) && ok;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      sGf[side][v][ff] = g[v];
-      if (pe) sGs[side][v][ff] = gs[v];
-    }
+    double lam, T;
+    ok = ns_point<NS>(mk, a.viscous, &sPw[0][NN + pp], &sPd[0][NN + pp], pe, &sPs[0][NN + pp], NP, &sGf[side][0][ff],
+                      &sGs[side][0][ff], TE + 1, lam, T) && ok;
     sLam[side][ff] = lam;
   }
   __syncthreads();
 
-  // 4b. chemistry (Sec. 2: W_i omega_i), one lane per (node, species), then one lane per
+  // 4c. chemistry (Sec. 2: W_i omega_i), one lane per (node, species), then one lane per
   //     (node, reaction), then one lane per (node, species) again
   for (int idx = t; idx < NS * NN; idx += kThreads) {
     const int i = idx / NN, p = idx % NN;
     const int el = p / Q, qn = p % Q;
-    double x = 0.0;
+    OpT xo = 0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) x += sB[qn][j] * sW[(3 + i) * M + j][el + 2];
+    for (int j = 0; j < M; ++j) xo += (OpT)sB[qn][j] * (OpT)sW[(3 + i) * M + j][el + 2];
+    const double x = (double)xo;
     const double T = sT[p];
     const double lnT = log(T);
     const double *c = mk->a[i];
@@ -445,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
     double F;
     if (i >= 0) {
       const double Fs = 0.5 * (sGs[0][v][ff] + sGs[1][v][ff] - diss);
-      if (ff < nloc) ring_rec(a.ring, n, a.stage, a.dl.nif, i)[a.ring.off_F + v] = Fs;
+      if (ff < nloc) ring_rec(a.ring, n, stage, a.dl.nif, i)[a.ring.off_F + v] = Fs;
       F = sK[ff + 1] > 0 ? sFat[v][ff] : Fs;
     } else {
       F = 0.5 * (sGf[0][v][ff] + sGf[1][v][ff] - diss);
@@ -458,25 +481,60 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   for (int idx = t; idx < V * M * nloc; idx += kThreads) {
     const int c = idx / nloc, el = idx % nloc;
     const int v = c / M, j = c % M;
-    double vol = 0.0, src = 0.0;
+    OpT vol = 0, srcs = 0;
 #pragma unroll
     for (int qn = 0; qn < Q; ++qn) {
-      vol += sWG[qn][j] * sG[v][el * Q + qn];
-      if (v >= 3) src += sWB[qn][j] * sS[v >= 3 ? v - 3 : 0][el * Q + qn];
+      vol += (OpT)sWG[qn][j] * (OpT)sG[v][el * Q + qn];
+      if (v >= 3) srcs += (OpT)sWB[qn][j] * (OpT)sS[v >= 3 ? v - 3 : 0][el * Q + qn];
     }
+    const double src = (double)srcs;
     const double half2j1 = 0.5 * (2 * j + 1);
-    const double b = vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
+    const double b = (double)vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
     const double L = 2.0 * a.inv_dx * (half2j1 * b) + half2j1 * src;
     const double y = sW[c][el + 2] + a.dt * L;
     const size_t gi = sidx(e0 + el, c, V * M);
     double o;
-    if (a.stage == 0) o = y;
-    else if (a.stage == 1) o = 0.75 * a.w0[gi] + 0.25 * y;
-    else o = (1.0 / 3.0) * a.w0[gi] + (2.0 / 3.0) * y;
-    a.wout[gi] = o;
+    if (stage == 0) o = y;
+    else if (stage == 1) o = 0.75 * w0[gi] + 0.25 * y;
+    else o = (1.0 / 3.0) * w0[gi] + (2.0 / 3.0) * y;
+    wout[gi] = o;
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
-  if (a.advance) finish_step(a.step, a.done);
+  if (advance) finish_step(a.step, a.done, ntiles);
+}
+
+template <int M, int NS>
+__global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
+  __shared__ NsLds<M, NS> L;
+  __shared__ NsMech smech;
+  ns_tile<M, NS, double>(a, a.ws, a.w0, a.wout, a.stage, a.advance, blockIdx.x * kTile, gridDim.x, L, smech);
+}
+
+// Batched stage kernel: one workgroup per (instance, tile) entry of the work
+// list; instances differ in size, order, PE layout and delays.
+template <typename OpT>
+__global__ __launch_bounds__(kThreads) void ns_batch_kernel(const NsArgs *__restrict__ insts,
+                                                            const int2 *__restrict__ tiles, int stage) {
+  __shared__ union {
+    NsLds<2, kNsMaxSpecies> m2;
+    NsLds<3, kNsMaxSpecies> m3;
+    NsLds<4, kNsMaxSpecies> m4;
+    NsLds<5, kNsMaxSpecies> m5;
+  } L;
+  __shared__ NsMech smech;
+  const int2 tl = tiles[blockIdx.x];
+  const NsArgs &a = insts[tl.x];
+  const int in_buf = stage, out_buf = stage == 2 ? 0 : stage + 1;
+  const double *ws = a.W[in_buf];
+  const double *w0 = a.W[0];
+  double *wout = a.W[out_buf];
+  const int ntiles = (a.E + kTile - 1) / kTile;
+  switch (a.M) {
+    case 2: ns_tile<2, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech); break;
+    case 3: ns_tile<3, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech); break;
+    case 4: ns_tile<4, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech); break;
+    default: ns_tile<5, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech); break;
+  }
 }
 
 // ------------------------------------------------------------------ host side
@@ -566,7 +624,7 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
   a.dl = dl;
   a.ring = rp;
   a.tb = tb;
-  (void)M;
+  a.M = M;
   return ADG_OK;
 }
 
@@ -574,6 +632,13 @@ template <int M>
 static hipError_t ns_M(const NsArgs &a, hipStream_t s) {
   const int blocks = (a.E + kTile - 1) / kTile;
   hipLaunchKernelGGL((ns_stage_kernel<M, kNsMaxSpecies>), dim3(blocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (mixed) hipLaunchKernelGGL(ns_batch_kernel<float>, dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage);
+  else hipLaunchKernelGGL(ns_batch_kernel<double>, dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage);
   return hipGetLastError();
 }
 

@@ -41,6 +41,8 @@ struct NsArgs {
   const double *w0;
   const double *ws;
   double *wout;
+  double *W[3];         // the three state buffers (batched kernel picks them by stage)
+  int M;                // N_p + 1
   const int *face_if;
   long long *step;
   unsigned *done;       // workgroups finished in the step's last kernel
@@ -62,5 +64,8 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
                     long long *step, unsigned *done, int *err, NsMech *dev_mech);
 hipError_t launch_ns_stage(int M, const NsArgs &a, hipStream_t s);
+// One stage for every (instance, tile) entry of `tiles` (device); mixed = FP32 modal operators.
+hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, hipStream_t s);
+constexpr int kNsTile = 8;
 
 }  // namespace adg

@@ -1,0 +1,324 @@
+// Placement of one ADG problem in device memory and the construction of its
+// kernel arguments (shared by the single-problem solver and the batch).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "adg_problem.hpp"
+
+namespace adg {
+
+// ------------------------------------------------------------- host tables
+
+// Legendre P_j(x) and P_j'(x) by the three-term recurrence and the derivative
+// identity P'_{j+1} = P'_{j-1} + (2j+1) P_j.
+void legendre_all(int n, double x, double *P, double *dP) {
+  P[0] = 1.0;
+  dP[0] = 0.0;
+  if (n > 1) { P[1] = x; dP[1] = 1.0; }
+  for (int j = 1; j + 1 < n; ++j) {
+    P[j + 1] = ((2 * j + 1) * x * P[j] - j * P[j - 1]) / (j + 1);
+    dP[j + 1] = dP[j - 1] + (2 * j + 1) * P[j];
+  }
+}
+
+// Gauss-Legendre nodes (ascending) and weights, Newton iteration on P_n.
+void gauss(int n, double *x, double *w) {
+  double P[16], dP[16];
+  for (int i = 0; i < n; ++i) {
+    double z = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 60; ++it) {
+      legendre_all(n + 1, z, P, dP);
+      double dz = P[n] / dP[n];
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    legendre_all(n + 1, z, P, dP);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dP[n] * dP[n]);
+  }
+}
+
+// Derivative of a Legendre series: if g = sum c_k P_k then g' = sum d_k P_k with
+// d_k = (2k+1) sum_{m > k, m - k odd} c_m.
+void legendre_series_derivative(int n, const double *c, double *d) {
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int m = k + 1; m < n; m += 2) s += c[m];
+    d[k] = (2 * k + 1) * s;
+  }
+}
+
+void build_tables(int M, Tables &tb) {
+  std::memset(&tb, 0, sizeof tb);
+  double x[kMaxQ], w[kMaxQ], P[16], dP[16];
+  gauss(M, x, w);
+  for (int q = 0; q < M; ++q) {
+    legendre_all(M, x[q], P, dP);
+    for (int j = 0; j < M; ++j) {
+      tb.B[q][j] = P[j];
+      tb.WG[q][j] = w[q] * dP[j];
+      tb.WB[q][j] = w[q] * P[j];
+    }
+  }
+  for (int j = 0; j < M; ++j)
+    for (int k = 0; k < M; ++k) {
+      double s = 0.0;
+      for (int q = 0; q < M; ++q) {
+        legendre_all(M, x[q], P, dP);
+        s += w[q] * dP[j] * P[k];
+      }
+      tb.Dm[j][k] = s;
+    }
+}
+
+// Smoothness quadratic form sum_s 2^(2s-1) int P_a^(s) P_b^(s) (Legendre
+// coefficient space, where int P_k P_l = 2/(2k+1) delta_kl) and the
+// re-expansion matrices of the left/right neighbour polynomials.
+void build_limiter_tables(int M, LimiterArgs &la) {
+  std::memset(la.Bm, 0, sizeof la.Bm);
+  for (int a = 0; a < M; ++a)
+    for (int b = 0; b < M; ++b) {
+      double ca[kMaxM] = {0}, cb[kMaxM] = {0}, da[kMaxM], db[kMaxM];
+      ca[a] = 1.0;
+      cb[b] = 1.0;
+      double sum = 0.0;
+      for (int s = 1; s < M; ++s) {
+        legendre_series_derivative(M, ca, da);
+        legendre_series_derivative(M, cb, db);
+        std::memcpy(ca, da, sizeof ca);
+        std::memcpy(cb, db, sizeof cb);
+        double ip = 0.0;
+        for (int k = 0; k < M; ++k) ip += ca[k] * cb[k] * 2.0 / (2 * k + 1);
+        sum += std::ldexp(1.0, 2 * s - 1) * ip;
+      }
+      la.Bm[a][b] = sum;
+    }
+  double x[kMaxQ + 1], w[kMaxQ + 1], P[16], dP[16], Ps[16], dPs[16];
+  gauss(M + 1, x, w);
+  for (int side = -1; side <= 1; side += 2) {
+    double(*T)[kMaxM] = side < 0 ? la.Tl : la.Tr;
+    for (int k = 0; k < kMaxM; ++k)
+      for (int j = 0; j < kMaxM; ++j) T[k][j] = 0.0;
+    for (int k = 0; k < M; ++k)
+      for (int j = 0; j < M; ++j) {
+        double s = 0.0;
+        for (int q = 0; q < M + 1; ++q) {
+          legendre_all(M, x[q], P, dP);
+          legendre_all(M, x[q] - 2.0 * side, Ps, dPs);
+          s += w[q] * Ps[j] * P[k];
+        }
+        T[k][j] = s * (2 * k + 1) / 2.0;
+      }
+  }
+}
+
+bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_async *as, Layout &L,
+                 std::string *why) {
+  auto bad = [&](const char *m) { if (why) *why = m; return false; };
+  if (!ph || !d || !as) return bad("null argument");
+  if (d->order_p < 1 || d->order_p > 4) return bad("order_p must be 1..4");
+  if (d->n_quad != 0 && d->n_quad != d->order_p + 1) return bad("n_quad must be 0 or order_p + 1");
+  if (d->n_elem < 1) return bad("n_elem must be >= 1");
+  if (!(d->dt > 0.0)) return bad("dt must be > 0");
+  if (!(d->x_right > d->x_left)) return bad("x_right must exceed x_left");
+  if (as->n_pe < 1 || as->n_pe > d->n_elem) return bad("n_pe must be in 1..n_elem");
+  if (as->mode < 0 || as->mode > 3) return bad("unknown delay mode");
+  if (as->mode != ADG_SYNC && (as->L < 1 || as->L > kMaxL)) return bad("L must be in 1..8");
+  if (as->at_order < 0 || as->at_order > kMaxAT) return bad("at_order must be 0..6");
+  if (ph->model == ADG_ONESTEP) {
+    if (ph->n_species != 2) return bad("the one-step model has 2 species");
+  } else if (ph->model == ADG_DETAILED) {
+    if (!ph->mech) return bad("detailed model needs a mechanism");
+    if (ph->n_species != ph->mech->n_species) return bad("n_species differs from the mechanism");
+    if (d->limiter) return bad("the limiter supports the one-step model only");
+    if (d->flux != ADG_RUSANOV) return bad("the detailed model uses the Rusanov flux");
+  } else {
+    return bad("unknown model");
+  }
+  if (as->mode == ADG_SAA) {
+    if (!as->pmf) return bad("SAA needs pmf");
+    double s = 0.0;
+    for (int k = 0; k < as->L; ++k) {
+      if (!(as->pmf[k] >= 0.0)) return bad("pmf entries must be >= 0");
+      s += as->pmf[k];
+    }
+    if (std::fabs(s - 1.0) > 1e-12) return bad("pmf must sum to 1");
+  }
+  if (as->mode == ADG_SCHEDULE && (!as->schedule || as->schedule_steps < 1)) return bad("schedule missing");
+  const bool periodic = d->bc == ADG_PERIODIC;
+  L.E = d->n_elem;
+  L.M = d->order_p + 1;
+  L.V = 3 + ph->n_species;
+  L.nif = periodic ? as->n_pe : as->n_pe - 1;
+  L.nfaces = periodic ? L.E : L.E + 1;
+  L.q = as->at_order > 0 ? as->at_order : d->order_p + 1;
+  const int kmax = as->mode == ADG_SYNC ? 0 : as->L - 1;
+  L.D = kmax + L.q;
+  const bool visc = ph->model == ADG_DETAILED && ph->viscous;
+  L.off_F = 0;
+  L.off_Wc = L.V;
+  L.off_U = 2 * L.V;
+  L.rec = 2 * L.V + (d->limiter ? 2 * L.V * L.M : 0);
+  (void)visc;
+  size_t nstate = state_doubles(L.E, L.V * L.M) * sizeof(double);
+  size_t off = 0;
+  L.state = off;  off += 3 * align256(nstate);
+  L.wlim = off;   off += d->limiter ? align256(nstate) : 0;
+  L.flags = off;  off += align256((size_t)L.E);
+  L.face_if = off; off += align256(sizeof(int) * (L.E + 1));
+  L.counters = off; off += 256;
+  L.ring = off;   off += align256(sizeof(double) * (size_t)L.D * 3 * (L.nif > 0 ? L.nif : 1) * L.rec);
+  L.sched = off;  off += as->mode == ADG_SCHEDULE ? align256((size_t)as->schedule_steps * (L.nif > 0 ? L.nif : 1)) : 0;
+  L.mech = off;   off += ph->model == ADG_DETAILED ? align256(sizeof(NsMech)) : 0;
+  L.total = off;
+  return true;
+}
+
+
+adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc, const adg_async *as, char *base,
+                         const Layout &L, Problem &P) {
+  if (phys->model == ADG_DETAILED && !ns_supported(phys->n_species, phys->mech->n_reactions))
+    return ADG_ERR_UNSUPPORTED;
+  std::vector<int32_t> off(as->n_pe + 1);
+  for (int p = 0; p <= as->n_pe; ++p)
+    off[p] = as->pe_offsets ? as->pe_offsets[p] : (int32_t)(((int64_t)p * L.E) / as->n_pe);
+  if (off[0] != 0 || off[as->n_pe] != L.E) return ADG_ERR_ARG;
+  for (int p = 0; p < as->n_pe; ++p)
+    if (off[p + 1] <= off[p]) return ADG_ERR_ARG;
+  P = Problem{};
+  P.phys = *phys;
+  P.disc = *disc;
+  P.as = *as;
+  P.lay = L;
+  P.base = base;
+  size_t nstate = state_doubles(L.E, L.V * L.M) * sizeof(double);
+  for (int b = 0; b < 3; ++b) P.W[b] = (double *)(base + L.state + b * align256(nstate));
+  P.Wlim = disc->limiter ? (double *)(base + L.wlim) : nullptr;
+  P.flags = (int8_t *)(base + L.flags);
+  P.face_if = (int *)(base + L.face_if);
+  P.step = (long long *)(base + L.counters);
+  P.err = (int *)(base + L.counters + 64);
+  P.flag_count = (unsigned long long *)(base + L.counters + 128);
+  P.done = (unsigned *)(base + L.counters + 192);
+  P.ring = (double *)(base + L.ring);
+
+  const bool periodic = disc->bc == ADG_PERIODIC;
+  std::vector<int> fif(L.E + 1, -1);
+  if (periodic) {
+    for (int p = 0; p < as->n_pe; ++p) fif[off[p]] = p;
+    fif[L.E] = fif[0];
+  } else {
+    for (int p = 1; p < as->n_pe; ++p) fif[off[p]] = p - 1;
+  }
+  if (hipMemcpy(P.face_if, fif.data(), sizeof(int) * (L.E + 1), hipMemcpyHostToDevice) != hipSuccess)
+    return ADG_ERR_HIP;
+
+  DelayParams dl{};
+  dl.mode = as->mode;
+  dl.L = as->L > 0 ? as->L : 1;
+  dl.nif = L.nif;
+  dl.q = L.q;
+  dl.seed = as->seed;
+  if (as->mode == ADG_SAA) {
+    double cum = 0.0;
+    for (int k = 0; k < as->L; ++k) { cum += as->pmf[k]; dl.cum[k] = cum; }
+  }
+  if (as->mode == ADG_SCHEDULE) {
+    dl.sched = (const int8_t *)(base + L.sched);
+    dl.sched_steps = as->schedule_steps;
+    if (hipMemcpy(base + L.sched, as->schedule, (size_t)as->schedule_steps * L.nif, hipMemcpyHostToDevice) != hipSuccess)
+      return ADG_ERR_HIP;
+  }
+  RingParams rp{};
+  rp.base = P.ring;
+  rp.D = L.D;
+  rp.rec = L.rec;
+  rp.off_F = L.off_F;
+  rp.off_Wc = L.off_Wc;
+  rp.off_U = L.off_U;
+  const double dx = (disc->x_right - disc->x_left) / L.E;
+  Tables tb;
+  build_tables(L.M, tb);
+
+  if (phys->model == ADG_ONESTEP) {
+    EulerArgs &a = P.ea;
+    a.face_if = P.face_if;
+    a.step = P.step;
+    a.done = P.done;
+    a.err = P.err;
+    a.E = L.E;
+    a.periodic = periodic;
+    a.store_U = disc->limiter && L.nif > 0;
+    a.dt = disc->dt;
+    a.two_over_dx = 2.0 / dx;
+    a.ph = {phys->gamma, phys->q_heat, phys->e_act, phys->k_pre};
+    a.dl = dl;
+    a.ring = rp;
+    a.tb = tb;
+    if (disc->limiter) {
+      LimiterArgs &l = P.la;
+      l.wlim = P.Wlim;
+      l.flags = P.flags;
+      l.flag_count = P.flag_count;
+      l.face_if = P.face_if;
+      l.step = P.step;
+      l.done = P.done;
+      l.err = P.err;
+      l.E = L.E;
+      l.periodic = periodic;
+      l.kx_h = std::pow(dx, 0.5 * (disc->order_p + 1));
+      for (int k = 0; k < 3; ++k) l.gam[k] = disc->weno_gamma[k];
+      l.eps = disc->weno_eps;
+      l.ph = a.ph;
+      l.dl = dl;
+      l.ring = rp;
+      l.tb = tb;
+      build_limiter_tables(L.M, l);
+    }
+  } else {
+    adg_status rc = ns_setup(P.na, phys, disc, L.E, L.M, periodic, dx, dl, rp, tb, P.face_if, P.step, P.done, P.err,
+                             (NsMech *)(base + L.mech));
+    if (rc != ADG_OK) return rc;
+    for (int b = 0; b < 3; ++b) P.na.W[b] = P.W[b];
+  }
+  return ADG_OK;
+}
+
+hipError_t upload_state_host(const Problem &P, const double *w, hipStream_t st) {
+  const Layout &L = P.lay;
+  const int VM = L.V * L.M;
+  std::vector<double> planes(state_doubles(L.E, VM), 0.0);
+  for (int e = 0; e < L.E; ++e)
+    for (int c = 0; c < VM; ++c) planes[sidx(e, c, VM)] = w[(size_t)e * VM + c];
+  hipError_t e = hipMemcpyAsync(P.W[0], planes.data(), planes.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t download_state_host(const Problem &P, double *w, hipStream_t st) {
+  const Layout &L = P.lay;
+  const int VM = L.V * L.M;
+  std::vector<double> planes(state_doubles(L.E, VM));
+  hipError_t e = hipMemcpyAsync(planes.data(), P.W[0], planes.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  for (int el = 0; el < L.E; ++el)
+    for (int c = 0; c < VM; ++c) w[(size_t)el * VM + c] = planes[sidx(el, c, VM)];
+  return hipSuccess;
+}
+
+hipError_t reset_problem(const Problem &P, hipStream_t st) {
+  const Layout &L = P.lay;
+  hipError_t e = hipMemsetAsync(P.base + L.counters, 0, 256, st);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(P.ring, 0, sizeof(double) * (size_t)L.D * 3 * (L.nif > 0 ? L.nif : 1) * L.rec, st);
+  if (e == hipSuccess) e = hipMemsetAsync(P.flags, 0, (size_t)L.E, st);
+  return e;
+}
+
+}  // namespace adg

@@ -1,0 +1,55 @@
+// One ADG problem placed in device memory: layout of its region of a
+// workspace, device pointers and the argument blocks of its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "adg.h"
+#include "adg_internal.hpp"
+#include "adg_ns.hpp"
+
+namespace adg {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t state, wlim, flags, face_if, counters, ring, sched, mech, total;
+  int nif, nfaces, D, rec, q, V, M, E;
+  int off_F, off_Wc, off_U;
+};
+
+struct Problem {
+  adg_physics phys{};
+  adg_discretization disc{};
+  adg_async as{};
+  Layout lay{};
+  char *base = nullptr;
+  double *W[3] = {nullptr, nullptr, nullptr};
+  double *Wlim = nullptr;
+  int8_t *flags = nullptr;
+  int *face_if = nullptr;
+  long long *step = nullptr;
+  unsigned *done = nullptr;
+  int *err = nullptr;
+  unsigned long long *flag_count = nullptr;
+  double *ring = nullptr;
+  EulerArgs ea{};
+  LimiterArgs la{};
+  NsArgs na{};
+};
+
+// Validates a problem and computes the layout of its device region (bytes in L.total).
+bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_async *as, Layout &L,
+                 std::string *why);
+// Places the problem at `base` (256-byte aligned, L.total bytes), uploads its
+// constant data and fills the kernel arguments.
+adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc, const adg_async *as, char *base,
+                         const Layout &L, Problem &P);
+hipError_t upload_state_host(const Problem &P, const double *w, hipStream_t st);
+hipError_t download_state_host(const Problem &P, double *w, hipStream_t st);
+// Step counter, error flag, history ring and flags back to zero.
+hipError_t reset_problem(const Problem &P, hipStream_t st);
+
+}  // namespace adg
