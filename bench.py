@@ -60,6 +60,14 @@ def pmc_probe(args):
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
+    if args.workload == "c3":
+        b, cases = build_c3_batch(args.precision)
+        b.step(args.steps)
+        b.poll()
+        b.close()
+        print(json.dumps({"probe": "c3_batched_ignition", "instances": len(cases), "copy_bytes": COPY_PROBE_BYTES,
+                          "steps": args.steps}), flush=True)
+        return
     case, w0 = workload(args.workload, args.n_elem)
     s = adg.Solver(case)
     s.set_state(w0)
@@ -155,6 +163,56 @@ def cpu_baseline(case, w0, budget_s: float = 12.0):
                       f"({el:.1f} s, single thread, gcc -O2)"}
 
 
+def build_c3_batch(precision: str, n_inst: int = 4096):
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    cases = list(gen.case_c3(n_inst=n_inst, mech=gen.c1_mechanism()))
+    heap = sum(adg.Batch.instance_bytes(c) for c, _ in cases)
+    elems = sum(c["disc"]["n_elem"] for c, _ in cases)
+    b = adg.Batch(len(cases), elems, heap, precision=precision)
+    for c, w in cases:
+        b.add(c, w)
+    return b, cases
+
+
+def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed", n_inst: int = 4096):
+    """The batched ignition workload: n_inst instances (element counts log-uniform in
+    [128, 4096], N_p in {2, 3}, 4-32 PEs, SAA delays k <= 2) in one batch; every stage of
+    every instance is one batched launch.  Returns the measurement as a dict."""
+    import torch
+
+    from workloads import gen
+
+    b, cases = build_c3_batch(precision, n_inst)
+    elems = sum(c["disc"]["n_elem"] for c, _ in cases)
+    if graph:
+        b.set_graph(graph)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st, er = b.poll()
+    dof = sum(gen.dof(c) for c, _ in cases)
+    prof = b.profile(3)
+    stage_ms = prof["detailed_stage"][0]
+    flops = sum(detailed_stage_flops(c) for c, _ in cases)
+    achieved = flops / (stage_ms * 1e-3) / 1e12
+    b.close()
+    return {
+        "value": dof * 3 * steps / el, "unit": "DOF-updates/s", "ms_per_step": el * 1e3 / steps,
+        "steps": steps, "warmup": warmup, "precision": precision,
+        "config": {"workload": "c3_batched_ignition", "instances": len(cases), "elements": elems, "dof": dof,
+                   "order_p": [2, 3], "graph_steps": graph},
+        "state_errors": int(er.sum()), "steps_done_min": int(st[st >= 0].min()),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "ns_batch_kernel",
+                     "launch_ms": stage_ms, "flops_per_launch": flops},
+    }
+
+
 def sweep_euler(sizes, steps=20):
     """Size sweep of the one-step Euler stage kernel (C0 physics, N_p = 2, 8 PEs, SAA) into the
     HBM-bound regime: per size, the stage kernel's mean launch time and its algorithmic bandwidth."""
@@ -200,6 +258,9 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="calibration copy + plain-launch steps for rocprofv3 --pmc (no benchmark line)")
     ap.add_argument("--n-elem", type=int, default=None, help="override the workload's element count")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision measurement")
+    ap.add_argument("--batch-steps", type=int, default=60, help="timed steps of the batched workload")
+    ap.add_argument("--precision", default="mixed", help="batched workload precision: mixed | fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -212,6 +273,13 @@ def main():
     from workloads import gen
 
     torch.cuda.set_device(0)
+    if args.workload == "c3" and not args.pmc_probe:
+        out = bench_batched(args.steps, args.warmup, args.graph, args.precision)
+        out.update({"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+                    "vs_baseline": None, "dtype": "f64+f32" if args.precision == "mixed" else "f64",
+                    "data": "synthetic"})
+        print(json.dumps(out), flush=True)
+        return
     if args.pmc_probe:
         pmc_probe(args)
         return
@@ -266,6 +334,10 @@ def main():
         "kernel_ms": {k: v[0] for k, v in prof.items()},
     }
     s.close()
+    if not args.no_batched and detailed:
+        bb = bench_batched(args.batch_steps, 5, args.graph, args.precision)
+        out["batched_mixed"] = bb
+        out["batched_over_plain"] = bb["value"] / value
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, w0)
     print(json.dumps(out), flush=True)

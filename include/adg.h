@@ -171,6 +171,96 @@ void adg_destroy(adg_solver *s);
 
 const char *adg_last_error(const adg_solver *s);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent instances in one workspace.
+ *
+ * Many ADG problems of different sizes, orders, PE layouts and delay models
+ * advance together: every RK stage of a time step is one batched launch for
+ * all detailed-chemistry instances (plus one per order and flux for the
+ * one-step model, and the limiter launches of limited instances), so small
+ * instances fill the device together.  Each workgroup works on one instance
+ * with that instance's own arguments: an instance's result does not depend on
+ * what else is in the batch (alone and in the mix are bitwise identical for
+ * the same precision).  The method per instance is the one of adg_create.
+ *
+ * Workspace: a header of adg_batch_header_bytes(max_instances, max_elements)
+ * followed by a heap; an instance occupies adg_batch_instance_bytes() of it
+ * (its states, history ring, flags and constant data).  Admission is by this
+ * footprint: adg_batch_add fails with ADG_ERR_NOMEM when no free region, slot
+ * or element capacity is left, and succeeds again once removals free space.
+ *
+ * Precision (per batch, detailed-chemistry instances): ADG_FP64 runs every
+ * step in FP64; ADG_MIXED_FP32 evaluates the modal operators (interpolation
+ * to nodes and traces, LDG gradient, projection and lift) in FP32 with FP32
+ * accumulation, while the temperature Newton inversion, the Arrhenius rates and
+ * equilibrium constants, the interface fluxes and the RK update stay FP64.
+ * One-step instances always run in FP64.
+ *
+ * Calls on one batch must not overlap.  adg_batch_add and adg_batch_remove
+ * synchronise the batch's stream.
+ * ---------------------------------------------------------------------- */
+enum { ADG_FP64 = 0, ADG_MIXED_FP32 = 1 };
+
+typedef struct adg_batch adg_batch;
+
+/* Header bytes of a batch with up to max_instances instances whose element
+   counts sum to at most max_elements (0 on invalid arguments). */
+size_t adg_batch_header_bytes(int32_t max_instances, int64_t max_elements);
+
+/* Heap bytes one instance occupies (0 on invalid arguments). */
+size_t adg_batch_instance_bytes(const adg_physics *phys, const adg_discretization *disc, const adg_async *as);
+
+/* Create an empty batch in the caller's workspace (256-byte aligned; header
+   followed by the heap, workspace_bytes in total). */
+adg_status adg_batch_create(int32_t max_instances, int64_t max_elements, int32_t precision,
+                            void *device_workspace, size_t workspace_bytes, void *hip_stream,
+                            adg_batch **out);
+
+/* Admit one instance with initial state w0 ([E][V][M] FP64, count = E*V*M,
+   on the host or the device per `where`).  It runs n_steps time steps in the
+   following adg_batch_step calls and then idles (0 = no limit).  Its step count
+   starts at 0.  *slot receives its slot number (0 .. max_instances-1). */
+adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discretization *disc,
+                         const adg_async *as, const double *w0, int64_t count, int32_t where,
+                         int64_t n_steps, int32_t *slot);
+
+/* Release an instance's slot and workspace region. */
+adg_status adg_batch_remove(adg_batch *b, int32_t slot);
+
+/* Enqueue n_steps time steps of every admitted instance that has not reached
+   its n_steps (asynchronous). */
+adg_status adg_batch_step(adg_batch *b, int32_t n_steps);
+
+/* Synchronise; steps[i] = completed time steps of slot i (-1 if empty) and
+   state_err[i] = 1 if slot i latched a non-physical state.  Both arrays have
+   max_instances entries; either may be NULL. */
+adg_status adg_batch_poll(adg_batch *b, int64_t *steps, int32_t *state_err);
+
+/* Copy an instance's current state out ([E][V][M]); synchronises; returns
+   ADG_ERR_STATE if that instance latched a non-physical state. */
+adg_status adg_batch_get_state(adg_batch *b, int32_t slot, double *w, int64_t count, int32_t where);
+
+/* Use captured HIP graphs of steps_per_graph time steps (0 = plain launches);
+   the graph is rebuilt after the batch's composition changes. */
+adg_status adg_batch_set_graph(adg_batch *b, int32_t steps_per_graph);
+
+/* Enqueue n_steps steps with HIP events around every launch; ms_out[c] is the
+   mean duration of launch class c (0 detailed stage, 1 one-step stage,
+   2 limiter, 3 limiter scatter) and launches_out[c] its count.  Synchronises. */
+adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int64_t *launches_out,
+                             int32_t n_classes);
+
+/* Number of admitted instances. */
+int32_t adg_batch_active(const adg_batch *b);
+
+/* Size of the largest free heap region. */
+int64_t adg_batch_free_bytes(const adg_batch *b);
+
+/* Release the batch (synchronises; the workspace is not freed). */
+void adg_batch_destroy(adg_batch *b);
+
+const char *adg_batch_last_error(const adg_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadg.so")
-SOURCES = ["adg_api.hip", "adg_problem.hip", "adg_euler.hip", "adg_ns.hip"]
+SOURCES = ["adg_api.hip", "adg_problem.hip", "adg_batch.hip", "adg_euler.hip", "adg_ns.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -21,7 +21,9 @@ PERIODIC, TRANSMISSIVE = 0, 1
 RUSANOV, HLLC = 0, 1
 SYNC, CAA, SAA, SCHEDULE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
+FP64, MIXED_FP32 = 0, 1
 PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter")
+BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage", "limiter", "limiter_scatter")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
@@ -84,6 +86,22 @@ _sig = {
     "adg_set_graph": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_destroy": (None, [C.c_void_p]),
     "adg_last_error": (C.c_char_p, [C.c_void_p]),
+    "adg_batch_header_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
+    "adg_batch_instance_bytes": (C.c_size_t, [_P(Physics), _P(Discretization), _P(Async)]),
+    "adg_batch_create": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                     _P(C.c_void_p)]),
+    "adg_batch_add": (C.c_int32, [C.c_void_p, _P(Physics), _P(Discretization), _P(Async), C.c_void_p, C.c_int64,
+                                  C.c_int32, C.c_int64, _P(C.c_int32)]),
+    "adg_batch_remove": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "adg_batch_step": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "adg_batch_poll": (C.c_int32, [C.c_void_p, _P(C.c_int64), _P(C.c_int32)]),
+    "adg_batch_get_state": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32]),
+    "adg_batch_set_graph": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "adg_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_int64), C.c_int32]),
+    "adg_batch_active": (C.c_int32, [C.c_void_p]),
+    "adg_batch_free_bytes": (C.c_int64, [C.c_void_p]),
+    "adg_batch_destroy": (None, [C.c_void_p]),
+    "adg_batch_last_error": (C.c_char_p, [C.c_void_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -253,6 +271,115 @@ class Solver:
     def close(self):
         if getattr(self, "h", None):
             adg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent instances advanced together (adg_batch_*): torch owns
+    the workspace (header + heap of ``heap_bytes``), the library places
+    instances in it and runs every step on the current torch stream."""
+
+    def __init__(self, max_instances: int, max_elements: int, heap_bytes: int, precision: str = "fp64",
+                 device: str = "cuda"):
+        import torch
+
+        prec = {"fp64": FP64, "mixed": MIXED_FP32}[precision]
+        hdr = int(adg_batch_header_bytes(int(max_instances), int(max_elements)))
+        if hdr == 0:
+            raise AdgError(ADG_ERR_ARG, "invalid batch capacity")
+        nbytes = hdr + int(heap_bytes)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        h = C.c_void_p()
+        rc = adg_batch_create(int(max_instances), int(max_elements), prec, C.c_void_p(self._ws_ptr),
+                              C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != ADG_OK:
+            raise AdgError(rc, "adg_batch_create failed")
+        self.h = h
+        self.max_instances = int(max_instances)
+        self.shapes = {}
+
+    @staticmethod
+    def instance_bytes(case: dict) -> int:
+        p = Problem(case)
+        return int(adg_batch_instance_bytes(C.byref(p.phys), C.byref(p.disc), C.byref(p.asyn)))
+
+    def _check(self, rc):
+        if rc != ADG_OK:
+            raise AdgError(rc, adg_batch_last_error(self.h).decode())
+
+    def add(self, case: dict, w0, n_steps: int = 0) -> int:
+        """Admit an instance; raises AdgError with code ADG_ERR_NOMEM when it does not fit."""
+        p = Problem(case)
+        shape = (p.E, p.V, p.M)
+        slot = C.c_int32(-1)
+        import torch
+
+        if isinstance(w0, torch.Tensor):
+            assert w0.is_cuda and w0.dtype == torch.float64 and tuple(w0.shape) == shape
+            w0 = w0.contiguous()
+            rc = adg_batch_add(self.h, C.byref(p.phys), C.byref(p.disc), C.byref(p.asyn), C.c_void_p(w0.data_ptr()),
+                               w0.numel(), DEVICE, int(n_steps), C.byref(slot))
+        else:
+            w = np.ascontiguousarray(w0, dtype=np.float64)
+            assert w.shape == shape, (w.shape, shape)
+            rc = adg_batch_add(self.h, C.byref(p.phys), C.byref(p.disc), C.byref(p.asyn),
+                               w.ctypes.data_as(C.c_void_p), w.size, HOST, int(n_steps), C.byref(slot))
+        self._check(rc)
+        self.shapes[slot.value] = shape
+        return slot.value
+
+    def remove(self, slot: int):
+        self._check(adg_batch_remove(self.h, int(slot)))
+        self.shapes.pop(slot, None)
+
+    def step(self, n: int = 1):
+        self._check(adg_batch_step(self.h, int(n)))
+
+    def poll(self):
+        """(steps, state_err) per slot; steps is -1 for empty slots."""
+        st = np.empty(self.max_instances, dtype=np.int64)
+        er = np.empty(self.max_instances, dtype=np.int32)
+        self._check(adg_batch_poll(self.h, st.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   er.ctypes.data_as(C.POINTER(C.c_int32))))
+        return st, er
+
+    def state(self, slot: int) -> np.ndarray:
+        w = np.empty(self.shapes[slot])
+        self._check(adg_batch_get_state(self.h, int(slot), w.ctypes.data_as(C.c_void_p), w.size, HOST))
+        return w
+
+    def state_device(self, slot: int, out):
+        self._check(adg_batch_get_state(self.h, int(slot), C.c_void_p(out.data_ptr()), out.numel(), DEVICE))
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(adg_batch_set_graph(self.h, int(steps_per_graph)))
+
+    def profile(self, n_steps: int) -> dict:
+        k = len(BATCH_PROFILE_CLASSES)
+        ms = (C.c_double * k)()
+        cnt = (C.c_int64 * k)()
+        self._check(adg_batch_profile(self.h, int(n_steps), ms, cnt, k))
+        return {name: (ms[i], int(cnt[i])) for i, name in enumerate(BATCH_PROFILE_CLASSES)}
+
+    @property
+    def active(self) -> int:
+        return int(adg_batch_active(self.h))
+
+    @property
+    def free_bytes(self) -> int:
+        return int(adg_batch_free_bytes(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            adg_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,508 @@
+// Batched ADG instances in one device workspace (the adg_batch_* C ABI).
+//
+// The caller's workspace holds a header (per-slot kernel argument blocks, the
+// work list of the launches, per-slot step counters and error flags) followed
+// by a heap from which each admitted instance takes one contiguous region
+// (first fit, coalescing on release).  An admission that does not fit is
+// refused with ADG_ERR_NOMEM: admission is by device-memory footprint.
+//
+// A time step launches, per stage, one batched kernel for all detailed-
+// chemistry instances (orders dispatched inside the kernel) and one batched
+// kernel per (order, flux) group of one-step instances, then the limiter and
+// scatter kernels of the limited ones.  Every workgroup works on one instance
+// only, with that instance's own arguments, so the arithmetic of an instance
+// does not depend on what else is in the batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "adg.h"
+#include "adg_internal.hpp"
+#include "adg_ns.hpp"
+#include "adg_problem.hpp"
+
+using namespace adg;
+
+namespace {
+
+struct Slot {
+  bool used = false;
+  Problem P;
+  size_t off = 0, bytes = 0;  // heap region
+  long long target = kNoTarget;
+};
+
+struct Group {
+  int kind;  // 0 detailed stage, 1 one-step stage, 2 limiter, 3 scatter
+  int M, flux;
+  int off, n;  // range of the work list
+};
+
+constexpr int kProfileClasses = 4;
+
+}  // namespace
+
+struct adg_batch {
+  hipStream_t stream = nullptr;
+  int precision = ADG_FP64;
+  char *ws = nullptr;
+  size_t bytes = 0;
+  int max_inst = 0;
+  long long max_elem = 0;
+  long long max_tiles = 0;
+  NsArgs *d_ns = nullptr;
+  EulerSet *d_eu = nullptr;
+  int2 *d_tiles = nullptr;
+  long long *d_step = nullptr;
+  int *d_err = nullptr;
+  unsigned *d_done = nullptr;
+  size_t heap_off = 0;
+  std::map<size_t, size_t> free_list;  // offset -> bytes
+  std::vector<Slot> slots;
+  long long elems = 0;
+  int active = 0;
+  bool dirty = true;
+  std::vector<Group> groups;
+  std::vector<int2> h_tiles;
+  int graph_steps = 0;
+  bool graph_valid = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipEvent_t> prof_events;
+  std::vector<int> prof_class;
+  std::string msg;
+};
+
+namespace {
+
+struct Header {
+  size_t ns, eu, tiles, step, err, done, total;
+};
+
+Header header_layout(int max_inst, long long max_tiles) {
+  Header h;
+  size_t off = 0;
+  h.ns = off;    off += align256(sizeof(NsArgs) * (size_t)max_inst);
+  h.eu = off;    off += align256(sizeof(EulerSet) * (size_t)max_inst);
+  h.tiles = off; off += align256(sizeof(int2) * (size_t)max_tiles);
+  h.step = off;  off += align256(sizeof(long long) * (size_t)max_inst);
+  h.err = off;   off += align256(sizeof(int) * (size_t)max_inst);
+  h.done = off;  off += align256(sizeof(unsigned) * (size_t)max_inst);
+  h.total = off;
+  return h;
+}
+
+long long tile_bound(int max_inst, long long max_elem) { return (max_elem + kNsTile - 1) / kNsTile + 4LL * max_inst; }
+
+adg_status bfail(adg_batch *b, adg_status code, const std::string &m) {
+  if (b) b->msg = m;
+  return code;
+}
+
+#define BHIP(b, expr)                                                                    \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) return bfail(b, ADG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+bool heap_take(adg_batch *b, size_t need, size_t &off) {
+  for (auto it = b->free_list.begin(); it != b->free_list.end(); ++it) {
+    if (it->second >= need) {
+      off = it->first;
+      const size_t rest = it->second - need;
+      b->free_list.erase(it);
+      if (rest) b->free_list[off + need] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void heap_give(adg_batch *b, size_t off, size_t bytes) {
+  auto it = b->free_list.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != b->free_list.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    b->free_list.erase(nx);
+  }
+  if (it != b->free_list.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      b->free_list.erase(it);
+    }
+  }
+}
+
+long long slot_tiles(const Slot &s) {
+  const Layout &L = s.P.lay;
+  if (s.P.phys.model == ADG_DETAILED) return (L.E + kNsTile - 1) / kNsTile;
+  long long t = euler_batch_blocks(0, L.E);
+  if (s.P.disc.limiter) t += euler_batch_blocks(1, L.E) + euler_batch_blocks(2, L.E);
+  return t;
+}
+
+// Work list: detailed instances first (one group), then one-step instances by
+// (kind, order, flux).  Entries of one instance are consecutive.
+void rebuild_tiles(adg_batch *b) {
+  b->groups.clear();
+  b->h_tiles.clear();
+  auto add_group = [&](int kind, int M, int flux, auto pick, auto nblocks) {
+    Group g{kind, M, flux, (int)b->h_tiles.size(), 0};
+    for (int i = 0; i < (int)b->slots.size(); ++i) {
+      const Slot &s = b->slots[i];
+      if (!s.used || !pick(s)) continue;
+      const int nb = nblocks(s);
+      for (int k = 0; k < nb; ++k) b->h_tiles.push_back(make_int2(i, k * (kind == 0 ? kNsTile : 1)));
+    }
+    g.n = (int)b->h_tiles.size() - g.off;
+    if (g.n > 0) b->groups.push_back(g);
+  };
+  add_group(0, 0, 0, [](const Slot &s) { return s.P.phys.model == ADG_DETAILED; },
+            [](const Slot &s) { return (s.P.lay.E + kNsTile - 1) / kNsTile; });
+  for (int kind = 1; kind <= 3; ++kind)
+    for (int M = 2; M <= kMaxM; ++M)
+      for (int flux = 0; flux <= (kind == 1 ? 1 : 0); ++flux)
+        add_group(kind, M, flux,
+                  [&](const Slot &s) {
+                    return s.P.phys.model == ADG_ONESTEP && s.P.lay.M == M && (kind != 1 || s.P.disc.flux == flux) &&
+                           (kind == 1 || s.P.disc.limiter);
+                  },
+                  [&](const Slot &s) { return euler_batch_blocks(kind - 1, s.P.lay.E); });
+}
+
+adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
+  for (int stage = 0; stage < 3; ++stage) {
+    for (const Group &g : b->groups) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        BHIP(b, hipEventCreate(&e0));
+        BHIP(b, hipEventRecord(e0, st));
+      }
+      if (g.kind == 0) {
+        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->precision == ADG_MIXED_FP32, st));
+      } else {
+        BHIP(b, launch_euler_batch(g.kind - 1, g.M, g.flux, b->d_eu, b->d_tiles + g.off, g.n, stage, st));
+      }
+      if (timed) {
+        BHIP(b, hipEventCreate(&e1));
+        BHIP(b, hipEventRecord(e1, st));
+        b->prof_events.push_back(e0);
+        b->prof_events.push_back(e1);
+        b->prof_class.push_back(g.kind);
+      }
+    }
+  }
+  return ADG_OK;
+}
+
+void destroy_batch_graph(adg_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->graph_valid = false;
+}
+
+adg_status prepare(adg_batch *b) {
+  if (!b->dirty) return ADG_OK;
+  destroy_batch_graph(b);
+  rebuild_tiles(b);
+  if ((long long)b->h_tiles.size() > b->max_tiles) return bfail(b, ADG_ERR_NOMEM, "work list exceeds its capacity");
+  BHIP(b, hipStreamSynchronize(b->stream));
+  if (!b->h_tiles.empty())
+    BHIP(b, hipMemcpy(b->d_tiles, b->h_tiles.data(), sizeof(int2) * b->h_tiles.size(), hipMemcpyHostToDevice));
+  b->dirty = false;
+  return ADG_OK;
+}
+
+adg_status build_batch_graph(adg_batch *b) {
+  destroy_batch_graph(b);
+  if (!b->cap_stream) BHIP(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  adg_status rc = ADG_OK;
+  for (int i = 0; i < b->graph_steps && rc == ADG_OK; ++i) rc = enqueue_batch_step(b, b->cap_stream, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc != ADG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return bfail(b, ADG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  b->graph = g;
+  BHIP(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+  b->graph_valid = true;
+  return ADG_OK;
+}
+
+bool valid_slot(const adg_batch *b, int slot) { return b && slot >= 0 && slot < b->max_inst && b->slots[slot].used; }
+
+}  // namespace
+
+extern "C" {
+
+size_t adg_batch_header_bytes(int32_t max_instances, int64_t max_elements) {
+  if (max_instances < 1 || max_elements < 1) return 0;
+  return header_layout(max_instances, tile_bound(max_instances, max_elements)).total;
+}
+
+size_t adg_batch_instance_bytes(const adg_physics *phys, const adg_discretization *disc, const adg_async *as) {
+  Layout L;
+  if (!make_layout(phys, disc, as, L, nullptr)) return 0;
+  return align256(L.total);
+}
+
+adg_status adg_batch_create(int32_t max_instances, int64_t max_elements, int32_t precision, void *device_workspace,
+                            size_t workspace_bytes, void *hip_stream, adg_batch **out) {
+  if (!out) return ADG_ERR_ARG;
+  *out = nullptr;
+  if (max_instances < 1 || max_elements < 1) return ADG_ERR_ARG;
+  if (precision != ADG_FP64 && precision != ADG_MIXED_FP32) return ADG_ERR_ARG;
+  if (!device_workspace || ((uintptr_t)device_workspace & 255)) return ADG_ERR_ARG;
+  const long long max_tiles = tile_bound(max_instances, max_elements);
+  if (max_tiles > 0x7fffffffLL) return ADG_ERR_ARG;
+  const Header h = header_layout(max_instances, max_tiles);
+  if (workspace_bytes < h.total) return ADG_ERR_NOMEM;
+  adg_batch *b = new adg_batch();
+  b->stream = (hipStream_t)hip_stream;
+  b->precision = precision;
+  b->ws = (char *)device_workspace;
+  b->bytes = workspace_bytes;
+  b->max_inst = max_instances;
+  b->max_elem = max_elements;
+  b->max_tiles = max_tiles;
+  b->d_ns = (NsArgs *)(b->ws + h.ns);
+  b->d_eu = (EulerSet *)(b->ws + h.eu);
+  b->d_tiles = (int2 *)(b->ws + h.tiles);
+  b->d_step = (long long *)(b->ws + h.step);
+  b->d_err = (int *)(b->ws + h.err);
+  b->d_done = (unsigned *)(b->ws + h.done);
+  b->heap_off = h.total;
+  const size_t heap = (workspace_bytes - h.total) & ~(size_t)255;
+  if (heap) b->free_list[h.total] = heap;
+  b->slots.resize(max_instances);
+  *out = b;
+  return ADG_OK;
+}
+
+adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discretization *disc, const adg_async *as,
+                         const double *w0, int64_t count, int32_t where, int64_t n_steps, int32_t *slot_out) {
+  if (!b || !w0 || !slot_out || n_steps < 0) return ADG_ERR_ARG;
+  *slot_out = -1;
+  Layout L;
+  std::string why;
+  if (!make_layout(phys, disc, as, L, &why)) return bfail(b, ADG_ERR_ARG, why);
+  if (count != (int64_t)L.E * L.V * L.M) return bfail(b, ADG_ERR_ARG, "state size mismatch");
+  if (where != ADG_HOST && where != ADG_DEVICE) return bfail(b, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
+  int slot = -1;
+  for (int i = 0; i < b->max_inst; ++i)
+    if (!b->slots[i].used) { slot = i; break; }
+  if (slot < 0) return bfail(b, ADG_ERR_NOMEM, "no free instance slot");
+  if (b->elems + L.E > b->max_elem) return bfail(b, ADG_ERR_NOMEM, "element capacity of the batch exceeded");
+  const size_t need = align256(L.total);
+  size_t off = 0;
+  if (!heap_take(b, need, off)) return bfail(b, ADG_ERR_NOMEM, "no free workspace region large enough");
+  // kernels still in flight may read the region that was just handed out
+  hipError_t he = hipStreamSynchronize(b->stream);
+  Slot s;
+  adg_status rc = he == hipSuccess ? setup_problem(phys, disc, as, b->ws + off, L, s.P) : ADG_ERR_HIP;
+  if (rc != ADG_OK) {
+    heap_give(b, off, need);
+    return bfail(b, rc, rc == ADG_ERR_HIP ? "HIP call failed while placing the instance" : "unsupported instance");
+  }
+  s.used = true;
+  s.off = off;
+  s.bytes = need;
+  s.target = n_steps > 0 ? n_steps : kNoTarget;
+  // counters of the slot live in the header so that one copy reads them all
+  Problem &P = s.P;
+  P.step = b->d_step + slot;
+  P.err = b->d_err + slot;
+  P.done = b->d_done + slot;
+  auto fail_release = [&](hipError_t e, const char *what) {
+    heap_give(b, off, need);
+    return bfail(b, ADG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  if (P.phys.model == ADG_DETAILED) {
+    NsArgs na = P.na;
+    na.step = P.step;
+    na.err = P.err;
+    na.done = P.done;
+    na.target = s.target;
+    he = hipMemcpy(b->d_ns + slot, &na, sizeof na, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return fail_release(he, "descriptor upload");
+  } else {
+    EulerSet es;
+    std::memset(&es, 0, sizeof es);
+    const int in_buf[3] = {0, 1, 2}, out_buf[3] = {1, 2, 0};
+    for (int st = 0; st < 3; ++st) {
+      EulerArgs a = P.ea;
+      a.w0 = P.W[0];
+      a.ws = P.W[in_buf[st]];
+      a.wout = P.W[out_buf[st]];
+      a.stage = st;
+      a.advance = st == 2 && !P.disc.limiter;
+      a.step = P.step;
+      a.err = P.err;
+      a.done = P.done;
+      a.target = s.target;
+      es.st[st] = a;
+      if (P.disc.limiter) {
+        LimiterArgs l = P.la;
+        l.w = P.W[out_buf[st]];
+        l.stage = st;
+        l.advance = st == 2;
+        l.step = P.step;
+        l.err = P.err;
+        l.done = P.done;
+        l.target = s.target;
+        es.lim[st] = l;
+      }
+    }
+    he = hipMemcpy(b->d_eu + slot, &es, sizeof es, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return fail_release(he, "descriptor upload");
+  }
+  const int VM = L.V * L.M;
+  if (where == ADG_HOST) he = upload_state_host(P, w0, b->stream);
+  else he = launch_to_planes(w0, P.W[0], L.E, VM, b->stream);
+  if (he == hipSuccess) he = reset_problem(P, b->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(P.step, 0, sizeof(long long), b->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(P.err, 0, sizeof(int), b->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(P.done, 0, sizeof(unsigned), b->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(b->stream);
+  if (he != hipSuccess) return fail_release(he, "initial state");
+  b->slots[slot] = s;
+  b->elems += L.E;
+  b->active += 1;
+  b->dirty = true;
+  *slot_out = slot;
+  return ADG_OK;
+}
+
+adg_status adg_batch_remove(adg_batch *b, int32_t slot) {
+  if (!valid_slot(b, slot)) return bfail(b, ADG_ERR_ARG, "no instance in this slot");
+  BHIP(b, hipStreamSynchronize(b->stream));
+  Slot &s = b->slots[slot];
+  heap_give(b, s.off, s.bytes);
+  b->elems -= s.P.lay.E;
+  b->active -= 1;
+  s = Slot();
+  b->dirty = true;
+  return ADG_OK;
+}
+
+adg_status adg_batch_step(adg_batch *b, int32_t n_steps) {
+  if (!b || n_steps < 0) return ADG_ERR_ARG;
+  adg_status rc = prepare(b);
+  if (rc != ADG_OK) return rc;
+  if (b->groups.empty()) return ADG_OK;
+  int done = 0;
+  if (b->graph_steps > 0) {
+    if (!b->graph_valid) {
+      rc = build_batch_graph(b);
+      if (rc != ADG_OK) return rc;
+    }
+    for (; done + b->graph_steps <= n_steps; done += b->graph_steps) BHIP(b, hipGraphLaunch(b->gexec, b->stream));
+  }
+  for (; done < n_steps; ++done) {
+    rc = enqueue_batch_step(b, b->stream, false);
+    if (rc != ADG_OK) return rc;
+  }
+  return ADG_OK;
+}
+
+adg_status adg_batch_poll(adg_batch *b, int64_t *steps, int32_t *state_err) {
+  if (!b) return ADG_ERR_ARG;
+  BHIP(b, hipStreamSynchronize(b->stream));
+  std::vector<long long> st(b->max_inst);
+  std::vector<int> er(b->max_inst);
+  BHIP(b, hipMemcpy(st.data(), b->d_step, sizeof(long long) * b->max_inst, hipMemcpyDeviceToHost));
+  BHIP(b, hipMemcpy(er.data(), b->d_err, sizeof(int) * b->max_inst, hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->max_inst; ++i) {
+    const bool u = b->slots[i].used;
+    if (steps) steps[i] = u ? st[i] : -1;
+    if (state_err) state_err[i] = u ? (er[i] != 0) : 0;
+  }
+  return ADG_OK;
+}
+
+adg_status adg_batch_get_state(adg_batch *b, int32_t slot, double *w, int64_t count, int32_t where) {
+  if (!valid_slot(b, slot) || !w) return bfail(b, ADG_ERR_ARG, "no instance in this slot");
+  const Problem &P = b->slots[slot].P;
+  const Layout &L = P.lay;
+  const int VM = L.V * L.M;
+  if (count != (int64_t)L.E * VM) return bfail(b, ADG_ERR_ARG, "state size mismatch");
+  if (where == ADG_HOST) {
+    BHIP(b, download_state_host(P, w, b->stream));
+  } else if (where == ADG_DEVICE) {
+    BHIP(b, launch_from_planes(P.W[0], w, L.E, VM, b->stream));
+  } else {
+    return bfail(b, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
+  }
+  BHIP(b, hipStreamSynchronize(b->stream));
+  int err = 0;
+  BHIP(b, hipMemcpy(&err, P.err, sizeof err, hipMemcpyDeviceToHost));
+  if (err) return bfail(b, ADG_ERR_STATE, "non-physical state in this instance");
+  return ADG_OK;
+}
+
+adg_status adg_batch_set_graph(adg_batch *b, int32_t steps_per_graph) {
+  if (!b || steps_per_graph < 0) return ADG_ERR_ARG;
+  if (steps_per_graph != b->graph_steps) destroy_batch_graph(b);
+  b->graph_steps = steps_per_graph;
+  return ADG_OK;
+}
+
+adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int64_t *launches_out, int32_t n_classes) {
+  if (!b || n_steps < 1 || !ms_out || !launches_out || n_classes < 1) return ADG_ERR_ARG;
+  adg_status rc = prepare(b);
+  if (rc != ADG_OK) return rc;
+  b->prof_events.clear();
+  b->prof_class.clear();
+  for (int i = 0; i < n_steps && rc == ADG_OK; ++i) rc = enqueue_batch_step(b, b->stream, true);
+  hipError_t he = hipStreamSynchronize(b->stream);
+  std::vector<double> sum(n_classes, 0.0);
+  std::vector<int64_t> cnt(n_classes, 0);
+  for (size_t k = 0; k < b->prof_class.size(); ++k) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, b->prof_events[2 * k], b->prof_events[2 * k + 1]);
+    const int c = b->prof_class[k];
+    if (c < n_classes) { sum[c] += ms; cnt[c] += 1; }
+  }
+  for (hipEvent_t ev : b->prof_events) (void)hipEventDestroy(ev);
+  b->prof_events.clear();
+  b->prof_class.clear();
+  if (rc != ADG_OK) return rc;
+  if (he != hipSuccess) return bfail(b, ADG_ERR_HIP, hipGetErrorString(he));
+  for (int c = 0; c < n_classes; ++c) {
+    ms_out[c] = cnt[c] ? sum[c] / cnt[c] : 0.0;
+    launches_out[c] = cnt[c];
+  }
+  return ADG_OK;
+}
+
+int32_t adg_batch_active(const adg_batch *b) { return b ? b->active : -1; }
+
+int64_t adg_batch_free_bytes(const adg_batch *b) {
+  if (!b) return -1;
+  size_t best = 0;
+  for (const auto &kv : b->free_list) best = std::max(best, kv.second);
+  return (int64_t)best;
+}
+
+void adg_batch_destroy(adg_batch *b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  destroy_batch_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+}
+
+const char *adg_batch_last_error(const adg_batch *b) { return b ? b->msg.c_str() : "null batch"; }
+
+}  // extern "C"

@@ -70,10 +70,10 @@ __device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int i
 // k+1's; traces and fluxes move between lanes by cross-lane shuffles, so no
 // LDS and no workgroup barrier is needed.
 template <int M, int FLUX>
-__global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
+__device__ __forceinline__ void euler_stage_body(const EulerArgs &a, int blk, int nblk) {
   constexpr int V = 5, Q = M;
   const int lane = threadIdx.x & 63;
-  const int base = ((blockIdx.x * kEulerBlock + threadIdx.x) >> 6) * kWaveElems;
+  const int base = ((blk * kEulerBlock + threadIdx.x) >> 6) * kWaveElems;
   const int E = a.E;
   const int xu = base + lane - 1;                       // element index before periodic wrap
   const bool live = base < E;
@@ -182,7 +182,29 @@ __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
     }
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
-  if (a.advance) finish_step(a.step, a.done, gridDim.x);
+  if (a.advance) finish_step(a.step, a.done, nblk);
+}
+
+template <int M, int FLUX>
+__global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
+  euler_stage_body<M, FLUX>(a, blockIdx.x, gridDim.x);
+}
+
+__host__ __device__ inline int euler_blocks(int E) {
+  const int waves = (E + kWaveElems - 1) / kWaveElems;
+  return (waves + kEulerBlock / 64 - 1) / (kEulerBlock / 64);
+}
+
+// Batched stage kernel: one workgroup per (instance, block) entry of the work
+// list, for instances of one order and flux; an instance whose step count has
+// reached its target is skipped by all of its workgroups alike.
+template <int M, int FLUX>
+__global__ __launch_bounds__(kEulerBlock) void euler_batch_kernel(const EulerSet *__restrict__ sets,
+                                                                  const int2 *__restrict__ tiles, int stage) {
+  const int2 tl = tiles[blockIdx.x];
+  const EulerArgs &a = sets[tl.x].st[stage];
+  if (*a.step >= a.target) return;
+  euler_stage_body<M, FLUX>(a, tl.y, euler_blocks(a.E));
 }
 
 // ------------------------------------------------------------------- limiter
@@ -285,8 +307,8 @@ __device__ __forceinline__ double trace_at(const double (&c)[M], int side) {
 }
 
 template <int M>
-__global__ __launch_bounds__(128) void limiter_kernel(LimiterArgs a) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void limiter_body(const LimiterArgs &a, int blk) {
+  const int e = blk * kLimBlock + threadIdx.x;
   if (e >= a.E) return;
   const long long n = *a.step;
   double u[5][M];
@@ -389,11 +411,25 @@ __global__ __launch_bounds__(128) void limiter_kernel(LimiterArgs a) {
     for (int j = 0; j < M; ++j) a.wlim[sidx(e, v * M + j, 5 * M)] = wl[v][j];
 }
 
+template <int M>
+__global__ __launch_bounds__(kLimBlock) void limiter_kernel(LimiterArgs a) {
+  limiter_body<M>(a, blockIdx.x);
+}
+
+template <int M>
+__global__ __launch_bounds__(kLimBlock) void limiter_batch_kernel(const EulerSet *__restrict__ sets,
+                                                                  const int2 *__restrict__ tiles, int stage) {
+  const int2 tl = tiles[blockIdx.x];
+  const LimiterArgs &a = sets[tl.x].lim[stage];
+  if (*a.step >= a.target) return;
+  limiter_body<M>(a, tl.y);
+}
+
 // Writes the limited values of troubled cells back (after every stencil has read
 // the unlimited data).
 template <int M>
-__global__ __launch_bounds__(256) void limiter_scatter_kernel(LimiterArgs a) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void scatter_body(const LimiterArgs &a, int blk, int nblk) {
+  const int e = blk * kScatterBlock + threadIdx.x;
   if (e < a.E && a.flags[e]) {
 #pragma unroll
     for (int v = 0; v < 5; ++v)
@@ -403,7 +439,21 @@ __global__ __launch_bounds__(256) void limiter_scatter_kernel(LimiterArgs a) {
         a.w[idx] = a.wlim[idx];
       }
   }
-  if (a.advance) finish_step(a.step, a.done, gridDim.x);
+  if (a.advance) finish_step(a.step, a.done, nblk);
+}
+
+template <int M>
+__global__ __launch_bounds__(kScatterBlock) void limiter_scatter_kernel(LimiterArgs a) {
+  scatter_body<M>(a, blockIdx.x, gridDim.x);
+}
+
+template <int M>
+__global__ __launch_bounds__(kScatterBlock) void scatter_batch_kernel(const EulerSet *__restrict__ sets,
+                                                                      const int2 *__restrict__ tiles, int stage) {
+  const int2 tl = tiles[blockIdx.x];
+  const LimiterArgs &a = sets[tl.x].lim[stage];
+  if (*a.step >= a.target) return;
+  scatter_body<M>(a, tl.y, (a.E + kScatterBlock - 1) / kScatterBlock);
 }
 
 // caller layout [E][VM] <-> device layout (sidx)
@@ -424,8 +474,7 @@ __global__ void from_planes_kernel(const double *__restrict__ src, double *__res
 
 template <int M>
 static hipError_t stage_M(int flux, const EulerArgs &a, hipStream_t s) {
-  const int waves = (a.E + kWaveElems - 1) / kWaveElems;
-  const int blocks = (waves + kEulerBlock / 64 - 1) / (kEulerBlock / 64);
+  const int blocks = euler_blocks(a.E);
   if (flux == 1) hipLaunchKernelGGL((euler_stage_kernel<M, 1>), dim3(blocks), dim3(kEulerBlock), 0, s, a);
   else hipLaunchKernelGGL((euler_stage_kernel<M, 0>), dim3(blocks), dim3(kEulerBlock), 0, s, a);
   return hipGetLastError();
@@ -442,27 +491,61 @@ hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, hipStream_t s
 }
 
 hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s) {
-  const int blocks = (a.E + 127) / 128;
+  const int blocks = (a.E + kLimBlock - 1) / kLimBlock;
   switch (M) {
-    case 2: hipLaunchKernelGGL(limiter_kernel<2>, dim3(blocks), dim3(128), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(limiter_kernel<3>, dim3(blocks), dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(limiter_kernel<4>, dim3(blocks), dim3(128), 0, s, a); break;
-    case 5: hipLaunchKernelGGL(limiter_kernel<5>, dim3(blocks), dim3(128), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(limiter_kernel<2>, dim3(blocks), dim3(kLimBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(limiter_kernel<3>, dim3(blocks), dim3(kLimBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(limiter_kernel<4>, dim3(blocks), dim3(kLimBlock), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(limiter_kernel<5>, dim3(blocks), dim3(kLimBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s) {
-  const int blocks = (a.E + 255) / 256;
+  const int blocks = (a.E + kScatterBlock - 1) / kScatterBlock;
   switch (M) {
-    case 2: hipLaunchKernelGGL(limiter_scatter_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(limiter_scatter_kernel<3>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(limiter_scatter_kernel<4>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL(limiter_scatter_kernel<5>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(limiter_scatter_kernel<2>, dim3(blocks), dim3(kScatterBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(limiter_scatter_kernel<3>, dim3(blocks), dim3(kScatterBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(limiter_scatter_kernel<4>, dim3(blocks), dim3(kScatterBlock), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(limiter_scatter_kernel<5>, dim3(blocks), dim3(kScatterBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+int euler_batch_blocks(int kind, int E) {
+  if (kind == 0) return euler_blocks(E);
+  if (kind == 1) return (E + kLimBlock - 1) / kLimBlock;
+  return (E + kScatterBlock - 1) / kScatterBlock;
+}
+
+template <int M>
+static hipError_t batch_M(int kind, int flux, const EulerSet *sets, const int2 *tiles, int ntiles, int stage,
+                          hipStream_t s) {
+  if (kind == 0) {
+    if (flux == 1)
+      hipLaunchKernelGGL((euler_batch_kernel<M, 1>), dim3(ntiles), dim3(kEulerBlock), 0, s, sets, tiles, stage);
+    else
+      hipLaunchKernelGGL((euler_batch_kernel<M, 0>), dim3(ntiles), dim3(kEulerBlock), 0, s, sets, tiles, stage);
+  } else if (kind == 1) {
+    hipLaunchKernelGGL(limiter_batch_kernel<M>, dim3(ntiles), dim3(kLimBlock), 0, s, sets, tiles, stage);
+  } else {
+    hipLaunchKernelGGL(scatter_batch_kernel<M>, dim3(ntiles), dim3(kScatterBlock), 0, s, sets, tiles, stage);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_euler_batch(int kind, int M, int flux, const EulerSet *sets, const int2 *tiles, int ntiles,
+                              int stage, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (M) {
+    case 2: return batch_M<2>(kind, flux, sets, tiles, ntiles, stage, s);
+    case 3: return batch_M<3>(kind, flux, sets, tiles, ntiles, stage, s);
+    case 4: return batch_M<4>(kind, flux, sets, tiles, ntiles, stage, s);
+    case 5: return batch_M<5>(kind, flux, sets, tiles, ntiles, stage, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_to_planes(const double *src, double *dst, int E, int VM, hipStream_t s) {

@@ -75,6 +75,7 @@ struct EulerArgs {
   unsigned *done;       // workgroups finished in the step's last kernel
   int advance;          // this launch ends the time step
   int *err;
+  long long target;     // batched launches skip the instance once *step reaches it
   int E;
   int periodic;
   int stage;
@@ -97,6 +98,7 @@ struct LimiterArgs {
   unsigned *done;
   int advance;
   int *err;
+  long long target;
   int E;
   int periodic;
   int stage;
@@ -114,10 +116,25 @@ struct LimiterArgs {
 
 enum ErrBits { kErrState = 1, kErrNewton = 2 };
 
+constexpr int kLimBlock = 128;
+constexpr int kScatterBlock = 256;
+
+// Argument blocks of one instance of the one-step model in a batch, per stage.
+struct EulerSet {
+  EulerArgs st[3];
+  LimiterArgs lim[3];
+};
+
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, hipStream_t s);
 hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s);
 hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s);
+// Batched one-step launches over a work list of (instance, block) entries, all of
+// order M: kind 0 stage kernel (flux selects Rusanov/HLLC), 1 limiter, 2 scatter.
+hipError_t launch_euler_batch(int kind, int M, int flux, const EulerSet *sets, const int2 *tiles, int ntiles,
+                              int stage, hipStream_t s);
+// Workgroups per instance of E elements for each kind.
+int euler_batch_blocks(int kind, int E);
 hipError_t launch_to_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
 hipError_t launch_from_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
 

@@ -21,6 +21,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 namespace adg {
 
@@ -214,10 +215,21 @@ struct NsLds {
 };
 
 // One tile of one stage (all phases).  OpT is the arithmetic type of the modal
-// operators (interpolation, traces, LDG gradient, projection and lift): double
-// for the plain path, float for the mixed-precision path.  Point physics
-// (temperature Newton, fluxes, transport, chemistry) and the RK update are
-// FP64 in both.
+// operators (interpolation to nodes and traces, LDG gradient, volume integral):
+// double for the plain path, float for the mixed-precision path.  Point physics
+// (temperature Newton, fluxes, transport, chemistry), face averages, the source
+// projection and the RK update are FP64 in both.
+//
+// The mixed path contracts in FP32 only what is small against the element's
+// own level: P_0 = 1, so nodal values and traces are mode 0 (FP64) plus the
+// FP32 sum of the higher modes; the volume integral uses
+// sum_q w_q P_j'(xi_q) = P_j(1) - P_j(-1) to integrate the deviation of the
+// flux from its value at the first node in FP32 and the rest in FP64; the LDG
+// gradient likewise takes the element mean out of its face and volume terms.
+// The FP32 rounding then scales with the variation inside an element, not with
+// the magnitude of the state (pressure-sized fluxes would otherwise lose about
+// 4 digits of their element-to-element differences).  Gradients at nodes and
+// traces are likewise mode 0 plus the FP32 sum of the higher modes.
 template <int M, int NS, typename OpT>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
                                         double *wout, int stage, int advance, int e0, int ntiles,
@@ -253,6 +265,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   auto &sPd = Ls.sPd;
   auto &sPs = Ls.sPs;
   constexpr int NP = NsLds<M, NS>::NP;
+  constexpr bool kMixed = !std::is_same<OpT, double>::value;
 
   const int t = threadIdx.x;
   const int E = a.E;
@@ -299,13 +312,18 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const int v = idx / NH, l = idx % NH;
     OpT sm = 0, sp = 0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
+    for (int j = kMixed ? 1 : 0; j < M; ++j) {
       const OpT c = (OpT)sW[v * M + j][l];
       sp += c;
       sm += (j & 1) ? -c : c;
     }
-    sTm[v][l] = (double)sm;
-    sTp[v][l] = (double)sp;
+    if constexpr (kMixed) {
+      sTm[v][l] = sW[v * M][l] + (double)sm;
+      sTp[v][l] = sW[v * M][l] + (double)sp;
+    } else {
+      sTm[v][l] = (double)sm;
+      sTp[v][l] = (double)sp;
+    }
   }
   for (int idx = t; idx < V * NF; idx += kThreads) {
     const int v = idx / NF, fl = idx % NF;
@@ -327,7 +345,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   //    The synchronous value of a PE interface is published for this level.
   for (int idx = t; idx < V * NF; idx += kThreads) {
     const int v = idx / NF, fl = idx % NF;
-    const double wc = (double)((OpT)0.5 * ((OpT)sTp[v][fl] + (OpT)sTm[v][fl + 1]));
+    const double wc = kMixed ? 0.5 * (sTp[v][fl] + sTm[v][fl + 1])
+                             : (double)((OpT)0.5 * ((OpT)sTp[v][fl] + (OpT)sTm[v][fl + 1]));
     const int i = sI[fl];
     if (i >= 0 && fl >= 1 && fl <= nloc)   // faces e0 .. e0+nloc-1 are owned by this tile
       ring_rec(a.ring, n, stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
@@ -342,10 +361,19 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const int c = idx / NQ, lq = idx % NQ;
     const int v = c / M, j = c % M;
     OpT vol = 0;
+    if constexpr (kMixed) {
+      // D_j0 = 1 - (-1)^j: the mean cancels against the face terms
+      const double m0 = sW[v * M][lq + 1];
 #pragma unroll
-    for (int k = 0; k < M; ++k) vol += (OpT)sD[j][k] * (OpT)sW[v * M + k][lq + 1];
-    const OpT wl = (OpT)((j & 1) ? -sWa[v][lq] : sWa[v][lq]);
-    sQ[c][lq] = (double)((OpT)((2 * j + 1) * a.inv_dx) * ((OpT)sWa[v][lq + 1] - wl - vol));
+      for (int k = 1; k < M; ++k) vol += (OpT)sD[j][k] * (OpT)sW[v * M + k][lq + 1];
+      const double dl = sWa[v][lq] - m0, dr = sWa[v][lq + 1] - m0;
+      sQ[c][lq] = (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl) - (double)vol);
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) vol += (OpT)sD[j][k] * (OpT)sW[v * M + k][lq + 1];
+      const OpT wl = (OpT)((j & 1) ? -sWa[v][lq] : sWa[v][lq]);
+      sQ[c][lq] = (double)((OpT)((2 * j + 1) * a.inv_dx) * ((OpT)sWa[v][lq + 1] - wl - vol));
+    }
   }
   __syncthreads();
 
@@ -357,26 +385,27 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const int el = p / Q, qn = p % Q;
       OpT x = 0, d = 0;
 #pragma unroll
-      for (int j = 0; j < M; ++j) {
+      for (int j = kMixed ? 1 : 0; j < M; ++j) {
         x += (OpT)sB[qn][j] * (OpT)sW[v * M + j][el + 2];
         d += (OpT)sB[qn][j] * (OpT)sQ[v * M + j][el + 1];
       }
-      sPw[v][p] = (double)x;
-      sPd[v][p] = (double)d;
+      sPw[v][p] = kMixed ? sW[v * M][el + 2] + (double)x : (double)x;
+      sPd[v][p] = kMixed ? sQ[v * M][el + 1] + (double)d : (double)d;
     } else {
       const int pp = p - NN;
       const int ff = pp >> 1, side = pp & 1;  // face e0 + ff; side 0 = element left of it (at xi = +1)
       const int l = ff + 1 + side;            // local element
       const int lq = ff + side;               // its gradient slot; faces lq (left), lq + 1 (right)
       const OpT sgn = side ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
-      OpT d = 0, pj = 1;
+      OpT d = 0, pj = kMixed ? sgn : (OpT)1;
 #pragma unroll
-      for (int j = 0; j < M; ++j) {
+      for (int j = kMixed ? 1 : 0; j < M; ++j) {
         d += pj * (OpT)sQ[v * M + j][lq];
         pj *= sgn;
       }
+      const double dtr = kMixed ? sQ[v * M][lq] + (double)d : (double)d;
       sPw[v][p] = side ? sTm[v][l] : sTp[v][l];
-      sPd[v][p] = (double)d;
+      sPd[v][p] = dtr;
       if (sI[ff + 1] >= 0) {
         // synchronous gradient trace at a PE interface: undo the AT central traces of the element's faces
         const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
@@ -386,7 +415,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
           corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
           pk *= side ? -1.0 : 1.0;
         }
-        sPs[v][p] = (double)d + corr;
+        sPs[v][p] = dtr + corr;
       }
     }
   }
@@ -416,8 +445,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const int el = p / Q, qn = p % Q;
     OpT xo = 0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) xo += (OpT)sB[qn][j] * (OpT)sW[(3 + i) * M + j][el + 2];
-    const double x = (double)xo;
+    for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)sB[qn][j] * (OpT)sW[(3 + i) * M + j][el + 2];
+    const double x = kMixed ? sW[(3 + i) * M][el + 2] + (double)xo : (double)xo;
     const double T = sT[p];
     const double lnT = log(T);
     const double *c = mk->a[i];
@@ -481,15 +510,25 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   for (int idx = t; idx < V * M * nloc; idx += kThreads) {
     const int c = idx / nloc, el = idx % nloc;
     const int v = c / M, j = c % M;
-    OpT vol = 0, srcs = 0;
+    OpT vol = 0;
+    double srcs = 0.0;
+    const double gref = kMixed ? sG[v][el * Q] : 0.0;
 #pragma unroll
     for (int qn = 0; qn < Q; ++qn) {
-      vol += (OpT)sWG[qn][j] * (OpT)sG[v][el * Q + qn];
-      if (v >= 3) srcs += (OpT)sWB[qn][j] * (OpT)sS[v >= 3 ? v - 3 : 0][el * Q + qn];
+      if constexpr (kMixed) vol += (OpT)sWG[qn][j] * (OpT)(sG[v][el * Q + qn] - gref);
+      else vol += (OpT)sWG[qn][j] * (OpT)sG[v][el * Q + qn];
+      if (v >= 3) srcs += sWB[qn][j] * sS[v >= 3 ? v - 3 : 0][el * Q + qn];
     }
-    const double src = (double)srcs;
+    const double src = srcs;
     const double half2j1 = 0.5 * (2 * j + 1);
-    const double b = (double)vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
+    double b;
+    if constexpr (kMixed) {
+      // sum_q w_q P_j'(xi_q) gref = (1 - (-1)^j) gref, folded into the face terms
+      const double fr = sF[v][el + 1] - gref, fl = sF[v][el] - gref;
+      b = (double)vol - fr + ((j & 1) ? -fl : fl);
+    } else {
+      b = (double)vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
+    }
     const double L = 2.0 * a.inv_dx * (half2j1 * b) + half2j1 * src;
     const double y = sW[c][el + 2] + a.dt * L;
     const size_t gi = sidx(e0 + el, c, V * M);
@@ -524,6 +563,7 @@ __global__ __launch_bounds__(kThreads) void ns_batch_kernel(const NsArgs *__rest
   __shared__ NsMech smech;
   const int2 tl = tiles[blockIdx.x];
   const NsArgs &a = insts[tl.x];
+  if (*a.step >= a.target) return;
   const int in_buf = stage, out_buf = stage == 2 ? 0 : stage + 1;
   const double *ws = a.W[in_buf];
   const double *w0 = a.W[0];

@@ -48,6 +48,7 @@ struct NsArgs {
   unsigned *done;       // workgroups finished in the step's last kernel
   int advance;          // this launch ends the time step
   int *err;
+  long long target;     // batched launches skip the instance once *step reaches it
   const NsMech *mech;
   int E;
   int stage;

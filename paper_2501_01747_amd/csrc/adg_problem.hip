@@ -250,6 +250,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
     a.step = P.step;
     a.done = P.done;
     a.err = P.err;
+    a.target = kNoTarget;
     a.E = L.E;
     a.periodic = periodic;
     a.store_U = disc->limiter && L.nif > 0;
@@ -268,6 +269,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
       l.step = P.step;
       l.done = P.done;
       l.err = P.err;
+      l.target = kNoTarget;
       l.E = L.E;
       l.periodic = periodic;
       l.kx_h = std::pow(dx, 0.5 * (disc->order_p + 1));
@@ -284,6 +286,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
                              (NsMech *)(base + L.mech));
     if (rc != ADG_OK) return rc;
     for (int b = 0; b < 3; ++b) P.na.W[b] = P.W[b];
+    P.na.target = kNoTarget;
   }
   return ADG_OK;
 }

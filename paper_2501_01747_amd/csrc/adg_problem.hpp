@@ -12,6 +12,8 @@
 
 namespace adg {
 
+constexpr long long kNoTarget = 0x7fffffffffffffffLL;
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {

@@ -45,3 +45,18 @@ def test_workspace_sizing_and_argument_checks():
     assert adg.Problem(bad).workspace_bytes() == 0
     bad = dict(case, **{"async": dict(case["async"], n_pe=600)})
     assert adg.Problem(bad).workspace_bytes() == 0
+
+
+def test_batch_sizing():
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    h1 = adg.adg_batch_header_bytes(16, 10_000)
+    h2 = adg.adg_batch_header_bytes(32, 10_000)
+    assert 0 < h1 < h2 and h1 % 256 == 0
+    assert adg.adg_batch_header_bytes(0, 10) == 0 and adg.adg_batch_header_bytes(4, 0) == 0
+    case, _ = gen.case_c0(E=512, n_pe=8)
+    nb = adg.Batch.instance_bytes(case)
+    assert nb % 256 == 0 and nb >= adg.Problem(case).workspace_bytes()
+    bad = dict(case, disc=dict(case["disc"], order_p=0))
+    assert adg.Batch.instance_bytes(bad) == 0

@@ -1,0 +1,256 @@
+"""Batched instances (adg_batch_*): FP64 batch against the single-instance solver and the
+oracle, alone-vs-in-the-mix identity, the FP32-operator path's error against the FP64
+oracle, admission by workspace footprint, per-instance step targets and graph replay."""
+import numpy as np
+import pytest
+
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+CFL = {1: 0.1, 2: 0.08, 3: 0.04, 4: 0.02}
+
+
+@pytest.fixture(scope="module")
+def adg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_01747_amd import adg as lib
+
+    return lib
+
+
+@pytest.fixture(scope="module")
+def mech():
+    return gen.c1_mechanism()
+
+
+def var_errors(a, b):
+    """Per-variable L2 error against the variable's physical scale (momentum: sqrt(||rho|| ||rho E||))."""
+    V = a.shape[1]
+    num = np.linalg.norm((a - b).transpose(1, 0, 2).reshape(V, -1), axis=1)
+    nrm = np.linalg.norm(b.transpose(1, 0, 2).reshape(V, -1), axis=1)
+    scale = np.full(V, nrm[0])
+    scale[1] = np.sqrt(nrm[0] * nrm[2])
+    scale[2] = nrm[2]
+    return num / scale
+
+
+def ns_case(mech, E, P, n_pe, mode, seed):
+    case, w0 = gen.case_c1(E=E, order_p=P, n_pe=n_pe, mode=mode, mech=mech, seed=seed, cfl=CFL[P],
+                           Lx=0.01 * E / 2048)
+    return case, w0
+
+
+def mixed_cases(mech):
+    """Detailed-chemistry instances of every order, delay model, ragged tile tail and PE count."""
+    spec = [(40, 1, 3, "saa", 11), (64, 2, 4, "caa", 12), (29, 3, 5, "saa", 13), (48, 4, 2, "sync", 14),
+            (100, 3, 7, "saa", 15), (8, 2, 1, "saa", 16)]
+    return [ns_case(mech, *s) for s in spec]
+
+
+def onestep_cases():
+    c0, w0 = gen.case_c0(E=100, n_pe=5)
+    c0b, w0b = gen.case_c0(E=37, order_p=3, n_pe=4, mode="caa", cfl=0.04)
+    c0b["async"]["L"] = 2
+    c2, w2 = gen.case_c2(E=256, n_pe=8, length=8.0, shock_x=2.0)
+    c2h, w2h = gen.case_c2(E=128, order_p=1, n_pe=3, length=4.0, shock_x=1.0)   # shock on a face
+    return [(c0, w0), (c0b, w0b), (c2, w2), (c2h, w2h)]
+
+
+def make_batch(adg, cases, precision="fp64", spare=0):
+    heap = sum(adg.Batch.instance_bytes(c) for c, _ in cases) + spare
+    elems = sum(c["disc"]["n_elem"] for c, _ in cases) + 1
+    return adg.Batch(len(cases) + 2, elems, heap, precision=precision)
+
+
+def single(adg, case, w0, steps):
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(steps)
+    out = s.state()
+    s.close()
+    return out
+
+
+def test_fp64_batch_equals_single_solver(adg, mech):
+    """Every instance of a mixed batch (both models, all orders, limiter on and off) gives the
+    single-instance solver's result."""
+    cases = mixed_cases(mech) + onestep_cases()
+    b = make_batch(adg, cases)
+    slots = [b.add(c, w) for c, w in cases]
+    b.step(9)
+    steps, errs = b.poll()
+    for (c, w), sl in zip(cases, slots):
+        print(f"[batch-fp64] {c['name']} E={c['disc']['n_elem']} Np={c['disc']['order_p']} slot={sl}", flush=True)
+        assert steps[sl] == 9 and errs[sl] == 0
+        got = b.state(sl)
+        ref = single(adg, c, w, 9)
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(got - ref)) <= 1e-13 * scale, np.max(np.abs(got - ref)) / scale
+    b.close()
+
+
+def test_fp64_batch_against_oracle(adg, orc, mech):
+    cases = mixed_cases(mech)[:3] + onestep_cases()[:1]
+    b = make_batch(adg, cases)
+    slots = [b.add(c, w) for c, w in cases]
+    b.step(10)
+    for (c, w), sl in zip(cases, slots):
+        o = orc.OracleSolver(c, w, 11)
+        o.step(10)
+        ref = o.state()
+        err = float(np.max(var_errors(b.state(sl), ref))) if c["physics"]["model"] == "detailed" else \
+            float(np.linalg.norm(b.state(sl) - ref) / np.linalg.norm(ref))
+        print(f"[batch-oracle] {c['name']} E={c['disc']['n_elem']} err={err:.2e}", flush=True)
+        assert err < 1e-10
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_alone_equals_in_the_mix(adg, mech, precision):
+    """An instance's result does not depend on the batch around it (bitwise)."""
+    cases = mixed_cases(mech) + onestep_cases()
+    probe = 4  # E=100, N_p=3, 7 PEs
+    alone = make_batch(adg, [cases[probe]], precision)
+    sa = alone.add(*cases[probe])
+    alone.step(7)
+    wa = alone.state(sa)
+    alone.close()
+    mix = make_batch(adg, cases, precision)
+    order = [1, 0, 5, 7, 3, 4, 2, 6, 8, 9]
+    slots = {i: mix.add(*cases[i], n_steps=(3 if i == 0 else 0)) for i in order}
+    mix.step(7)
+    wm = mix.state(slots[probe])
+    mix.close()
+    print(f"[alone-vs-mix] {precision} max|diff| = {np.max(np.abs(wa - wm)):.3e}", flush=True)
+    np.testing.assert_array_equal(wa, wm)
+
+
+def restrict_to_coarse(w_fine, order_p):
+    """L2 projection of a piecewise polynomial on 2E elements onto E elements (modal, P_j(1) = 1)."""
+    from numpy.polynomial import legendre as npleg
+
+    E2, V, M = w_fine.shape
+    E = E2 // 2
+    xi, wq = npleg.leggauss(M + 2)
+    P = np.stack([npleg.legval(xi, np.eye(M)[j]) for j in range(M)])          # [M, nq]
+    out = np.zeros((E, V, M))
+    for half, sgn in ((0, -1.0), (1, 1.0)):
+        # coarse xi in the half [sgn-1, sgn+1]/2 ... map: coarse x = (xi_f + sgn) / 2
+        xc = 0.5 * (xi + sgn)
+        Pc = np.stack([npleg.legval(xc, np.eye(M)[j]) for j in range(M)])     # [M, nq]
+        vals = np.einsum("evj,jn->evn", w_fine[half::2], P)                   # fine values at its nodes
+        out += 0.5 * np.einsum("evn,jn,n->evj", vals, Pc, wq)
+    return out * ((2 * np.arange(M) + 1) / 2.0)[None, None, :]
+
+
+def test_mixed_precision_error_budget(adg, orc, mech):
+    """Error of the FP32-operator path against the FP64 oracle, next to the FP64 path's and
+    next to the oracle's own discretisation error (solution on E against 2E elements)."""
+    E, P, steps = 64, 3, 120
+    case, w0 = ns_case(mech, E, P, 8, "saa", 21)
+    # the same run on twice the elements; both use the finer mesh's time step
+    case2, w02 = gen.case_c1(E=2 * E, order_p=P, n_pe=8, mode="saa", mech=mech, seed=21, cfl=CFL[P],
+                             Lx=0.01 * E / 2048)
+    case["disc"]["dt"] = case2["disc"]["dt"]
+    b64 = make_batch(adg, [(case, w0)], "fp64")
+    s64 = b64.add(case, w0)
+    bmx = make_batch(adg, [(case, w0)], "mixed")
+    smx = bmx.add(case, w0)
+    b64.step(steps)
+    bmx.step(steps)
+    o = orc.OracleSolver(case, w0, steps + 1)
+    o.step(steps)
+    ref = o.state()
+    e64 = float(np.max(var_errors(b64.state(s64), ref)))
+    emx = float(np.max(var_errors(bmx.state(smx), ref)))
+    o2 = orc.OracleSolver(case2, w02, steps + 1)
+    o2.step(steps)
+    edisc = float(np.max(var_errors(ref, restrict_to_coarse(o2.state(), P))))
+    print(f"[mixed-budget] fp64 {e64:.2e}  mixed {emx:.2e}  discretisation(E vs 2E) {edisc:.2e}", flush=True)
+    print("[mixed-budget] mixed per variable", np.array2string(var_errors(bmx.state(smx), ref), precision=2))
+    print("[mixed-budget] discretisation per variable",
+          np.array2string(var_errors(ref, restrict_to_coarse(o2.state(), P)), precision=2), flush=True)
+    assert e64 < 1e-10
+    assert emx < 0.1 * edisc
+    b64.close()
+    bmx.close()
+
+
+def test_admission_by_footprint(adg, mech):
+    (c1, w1), (c2, w2) = ns_case(mech, 64, 3, 4, "saa", 31), ns_case(mech, 48, 2, 3, "saa", 32)
+    need = adg.Batch.instance_bytes(c1)
+    assert need > 0
+    b = adg.Batch(4, 10_000, 2 * need)
+    a = b.add(c1, w1)
+    b.add(c1, w1)
+    with pytest.raises(adg.AdgError) as ei:
+        b.add(c1, w1)
+    assert ei.value.code == adg.ADG_ERR_NOMEM
+    b.remove(a)
+    assert b.free_bytes >= need
+    s = b.add(c2, w2)
+    b.step(2)
+    st, _ = b.poll()
+    assert st[s] == 2 and b.active == 2
+    b.close()
+
+
+def test_step_targets(adg, mech):
+    """An instance admitted for n steps stops there while the rest of the batch runs on."""
+    (ca, wa), (cb, wb) = ns_case(mech, 40, 2, 4, "saa", 41), ns_case(mech, 24, 3, 3, "caa", 42)
+    cb["async"]["L"] = 3
+    b = make_batch(adg, [(ca, wa), (cb, wb)])
+    sa = b.add(ca, wa, n_steps=5)
+    sb = b.add(cb, wb)
+    b.step(9)
+    st, er = b.poll()
+    assert st[sa] == 5 and st[sb] == 9 and not er[sa] and not er[sb]
+    np.testing.assert_array_equal(b.state(sa), single(adg, ca, wa, 5))
+    b.close()
+
+
+def test_graph_replay_matches_plain_launches(adg, mech):
+    cases = mixed_cases(mech)[:3] + onestep_cases()[2:3]
+    res = []
+    for graph in (0, 4):
+        b = make_batch(adg, cases)
+        slots = [b.add(c, w) for c, w in cases]
+        b.set_graph(graph)
+        b.step(8)
+        b.step(3)
+        res.append([b.state(s) for s in slots])
+        b.close()
+    for x, y in zip(*res):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_batched_ignition_full_size_sampled(adg, orc):
+    """The full batched workload (4096 instances, mixed precision) for a few steps; sampled
+    instances (smallest, largest, one of each order) against the FP64 oracle."""
+    mech = gen.c1_mechanism()
+    cases = list(gen.case_c3(mech=mech))
+    heap = sum(adg.Batch.instance_bytes(c) for c, _ in cases)
+    elems = sum(c["disc"]["n_elem"] for c, _ in cases)
+    print(f"[c3] {len(cases)} instances, {elems} elements, heap {heap / 2**30:.2f} GiB", flush=True)
+    b = adg.Batch(len(cases), elems, heap, precision="mixed")
+    slots = [b.add(c, w) for c, w in cases]
+    b.set_graph(2)
+    b.step(2)
+    steps, errs = b.poll()
+    assert (steps[: len(cases)] == 2).all() and not errs.any()
+    E = np.array([c["disc"]["n_elem"] for c, _ in cases])
+    pick = {int(np.argmin(E)), int(np.argmax(E))}
+    pick |= {next(i for i, (c, _) in enumerate(cases) if c["disc"]["order_p"] == p) for p in (2, 3)}
+    for i in sorted(pick):
+        c, w = cases[i]
+        o = orc.OracleSolver(c, w, 3)
+        o.step(2)
+        err = float(np.max(var_errors(b.state(slots[i]), o.state())))
+        print(f"[c3] instance {i} E={c['disc']['n_elem']} Np={c['disc']['order_p']} mixed err {err:.2e}",
+              flush=True)
+        assert err < 1e-6
+    b.close()

@@ -382,6 +382,33 @@ def case_c1(E=2048, order_p=3, steps=200, n_pe=16, mode="saa", pmf=(0.3, 0.4, 0.
     return case, _fix_density_modes(w0)
 
 
+def c1_mechanism(cfl=0.04, Lx=0.01):
+    """The mechanism of the ignition workload (screened against its time step)."""
+    return synthetic_mechanism(1747, dt=default_dt(cfl, Lx / 2048, 750.0, 3))
+
+
+def case_c3(n_inst=4096, seed=42, e_range=(128, 4096), orders=(2, 3), pe_range=(4, 32), pmf=(0.3, 0.4, 0.3),
+            cfl=0.04, Lx=0.01, steps=200, delay_seed=2504, mech=None):
+    """Batched ignition instances: element counts log-uniform in e_range, N_p uniform over `orders`,
+    PE counts uniform in pe_range, SAA delays k in {0, 1, 2} with `pmf`, IC phase uniform in
+    [0, 2 pi).  Every instance uses the ignition mechanism; its time step is the Courant step of its
+    own mesh, capped at the step the mechanism was screened against.  Yields (case, w0)."""
+    rng = np.random.default_rng(seed)
+    mech = mech if mech is not None else c1_mechanism(cfl, Lx)
+    dt_chem = default_dt(cfl, Lx / 2048, 750.0, 3)
+    lo, hi = math.log(e_range[0]), math.log(e_range[1])
+    for i in range(n_inst):
+        E = int(round(math.exp(rng.uniform(lo, hi))))
+        order_p = int(rng.choice(orders))
+        n_pe = min(int(rng.integers(pe_range[0], pe_range[1] + 1)), E)
+        phase = float(rng.uniform(0.0, 2.0 * math.pi))
+        case, w0 = case_c1(E=E, order_p=order_p, steps=steps, n_pe=n_pe, pmf=pmf,
+                           seed=(delay_seed << 20) + i, Lx=Lx, cfl=cfl, mech=mech, phase=phase)
+        case["disc"]["dt"] = min(case["disc"]["dt"], dt_chem)
+        case["name"] = "c3_batched_ignition"
+        yield case, w0
+
+
 def dof(case: dict) -> int:
     d = case["disc"]
     return d["n_elem"] * (d["order_p"] + 1) * (3 + case["physics"]["n_species"])
