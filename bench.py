@@ -213,6 +213,49 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
     }
 
 
+# Arrival rate of the served stream: 0.7 x the saturation throughput of the server
+# (all requests queued at t = 0), measured once with --calibrate and then fixed.
+C4_RATE = 6.25   # 0.7 x 8.93 requests/s measured with --calibrate --requests 300
+
+
+def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, precision: str):
+    """Served stream of n_req requests (half ignition, half reacting shock; E log-uniform in
+    [256, 65536], N_p in {1..4}, 100-2000 steps) arriving as a Poisson process at `rate`
+    requests/s (all at t = 0 when rate is None: the saturation measurement)."""
+    import numpy as np
+    import torch
+
+    from paper_2501_01747_amd import adg
+    from paper_2501_01747_amd.serve import Request, Server, summarize
+    from workloads import gen
+
+    t_gen = time.perf_counter()
+    raw = list(gen.c4_requests(n_req, rate))
+    reqs = [Request(r["rid"], r["case"], r["w0"], r["steps"], r["arrival"]) for r in raw]
+    t_gen = time.perf_counter() - t_gen
+    b = adg.Batch(slots, 1 << 27, int(heap_gib * 2**30), precision=precision)
+    srv = Server(b, chunk=chunk)
+    torch.cuda.synchronize()
+    res = srv.run(reqs)
+    b.close()
+    out = summarize(res)
+    fails = {}
+    for q, r in zip(raw, res):
+        if not r.ok:
+            key = f"{q['kind']}_p{q['case']['disc']['order_p']}"
+            fails[key] = fails.get(key, 0) + 1
+    by_kind = {}
+    for kind in ("ignition", "shock"):
+        lat = [r.latency for q, r in zip(raw, res) if r.ok and q["kind"] == kind]
+        if lat:
+            by_kind[kind] = {"n": len(lat), "p50_latency_s": float(np.percentile(lat, 50)),
+                             "p99_latency_s": float(np.percentile(lat, 99))}
+    out.update({"failed_by_kind_order": fails, "latency_by_kind": by_kind, "rate_req_per_s": rate, "heap_gib": heap_gib, "slots": slots, "chunk": chunk,
+                "precision": precision, "rounds": srv.rounds, "max_active": srv.max_active,
+                "input_generation_s": t_gen})
+    return out
+
+
 def sweep_euler(sizes, steps=20):
     """Size sweep of the one-step Euler stage kernel (C0 physics, N_p = 2, 8 PEs, SAA) into the
     HBM-bound regime: per size, the stage kernel's mean launch time and its algorithmic bandwidth."""
@@ -261,6 +304,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision measurement")
     ap.add_argument("--batch-steps", type=int, default=60, help="timed steps of the batched workload")
     ap.add_argument("--precision", default="mixed", help="batched workload precision: mixed | fp64")
+    ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
+    ap.add_argument("--rate", type=float, default=None, help="served stream: arrival rate (requests/s)")
+    ap.add_argument("--calibrate", action="store_true", help="served stream: saturation run (all arrive at t=0)")
+    ap.add_argument("--serve-heap-gib", type=float, default=16.0)
+    ap.add_argument("--serve-slots", type=int, default=1024)
+    ap.add_argument("--serve-chunk", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -278,6 +327,18 @@ def main():
         out.update({"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
                     "vs_baseline": None, "dtype": "f64+f32" if args.precision == "mixed" else "f64",
                     "data": "synthetic"})
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "c4":
+        rate = None if args.calibrate else (args.rate or C4_RATE)
+        if rate is None and not args.calibrate:
+            raise SystemExit("no arrival rate: run with --calibrate first or pass --rate")
+        out = bench_serve(args.requests, rate, args.serve_heap_gib, args.serve_slots, args.serve_chunk,
+                          args.precision)
+        out.update({"metric": METRIC, "workload": "c4_served_stream", "n_gpus": 1, "data": "synthetic",
+                    "saturation_run": bool(args.calibrate)})
+        if args.calibrate:
+            out["calibrated_rate_req_per_s"] = 0.7 * out["requests_per_s"]
         print(json.dumps(out), flush=True)
         return
     if args.pmc_probe:

@@ -1,0 +1,55 @@
+"""Served stream on the GPU: requests of both models, all orders and different sizes arrive
+while others run; each served result equals the same request solved alone (bitwise, same
+precision), and admission waits when the workspace is full."""
+import numpy as np
+import pytest
+
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def adg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_01747_amd import adg as lib
+
+    return lib
+
+
+def small_stream(n=16, rate=400.0):
+    from paper_2501_01747_amd.serve import Request
+
+    reqs = []
+    for r in gen.c4_requests(n, rate, e_range=(256, 640), steps_range=(8, 30)):
+        reqs.append(Request(r["rid"], r["case"], r["w0"], r["steps"], r["arrival"]))
+    return reqs
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_equals_alone(adg, precision):
+    from paper_2501_01747_amd.serve import Server, summarize
+
+    reqs = small_stream()
+    foot = [adg.Batch.instance_bytes(r.case) for r in reqs]
+    # room for about a third of the stream at once: admission has to wait
+    b = adg.Batch(8, 1 << 20, sum(foot) // 3, precision=precision)
+    srv = Server(b, chunk=6, keep_states=True)
+    res = srv.run(reqs)
+    b.close()
+    s = summarize(res)
+    print(f"[serve] {precision} {s} rounds={srv.rounds} max_active={srv.max_active}", flush=True)
+    assert s["failed"] == 0 and 1 < srv.max_active < len(reqs)
+    assert any(r.admitted > r.arrival + 1e-3 for r in res)        # someone queued
+    for q, r in zip(reqs, res):
+        alone = adg.Batch(1, q.case["disc"]["n_elem"], adg.Batch.instance_bytes(q.case), precision=precision)
+        sl = alone.add(q.case, q.w0, n_steps=q.steps)
+        alone.step(q.steps + 3)
+        w = alone.state(sl)
+        st, _ = alone.poll()
+        alone.close()
+        assert st[sl] == q.steps
+        np.testing.assert_array_equal(r.state, w, err_msg=f"request {q.rid} ({q.case['name']})")

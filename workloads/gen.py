@@ -387,12 +387,24 @@ def c1_mechanism(cfl=0.04, Lx=0.01):
     return synthetic_mechanism(1747, dt=default_dt(cfl, Lx / 2048, 750.0, 3))
 
 
+def diffusive_dt(mech, dx, order_p, c_visc=0.05, T=1050.0):
+    """Explicit time-step limit of the LDG diffusion terms: c_visc dx^2 / (D (N_p+1)^4), with D the
+    largest of the momentum and heat diffusivities (4/3 nu, nu/Pr) of the premix at T and 1 atm."""
+    Y = premix_mass_fractions(mech)
+    Wmix = 1.0 / np.sum(Y / mech["W"])
+    rho = P_ATM * Wmix / (RU * T)
+    mu = mech["mu_ref"] * (T / mech["T_ref"]) ** mech["mu_exp"]
+    D = mu / rho * max(4.0 / 3.0, 1.0 / mech["prandtl"])
+    return c_visc * dx * dx / (D * (order_p + 1) ** 4)
+
+
 def case_c3(n_inst=4096, seed=42, e_range=(128, 4096), orders=(2, 3), pe_range=(4, 32), pmf=(0.3, 0.4, 0.3),
             cfl=0.04, Lx=0.01, steps=200, delay_seed=2504, mech=None):
     """Batched ignition instances: element counts log-uniform in e_range, N_p uniform over `orders`,
     PE counts uniform in pe_range, SAA delays k in {0, 1, 2} with `pmf`, IC phase uniform in
     [0, 2 pi).  Every instance uses the ignition mechanism; its time step is the Courant step of its
-    own mesh, capped at the step the mechanism was screened against.  Yields (case, w0)."""
+    own mesh, capped at the step the mechanism was screened against and at the diffusive limit.
+    Yields (case, w0)."""
     rng = np.random.default_rng(seed)
     mech = mech if mech is not None else c1_mechanism(cfl, Lx)
     dt_chem = default_dt(cfl, Lx / 2048, 750.0, 3)
@@ -404,9 +416,55 @@ def case_c3(n_inst=4096, seed=42, e_range=(128, 4096), orders=(2, 3), pe_range=(
         phase = float(rng.uniform(0.0, 2.0 * math.pi))
         case, w0 = case_c1(E=E, order_p=order_p, steps=steps, n_pe=n_pe, pmf=pmf,
                            seed=(delay_seed << 20) + i, Lx=Lx, cfl=cfl, mech=mech, phase=phase)
-        case["disc"]["dt"] = min(case["disc"]["dt"], dt_chem)
+        case["disc"]["dt"] = min(case["disc"]["dt"], dt_chem, diffusive_dt(mech, Lx / E, order_p))
         case["name"] = "c3_batched_ignition"
         yield case, w0
+
+
+IGNITION_CFL = {1: 0.1, 2: 0.08, 3: 0.04, 4: 0.01}
+SHOCK_CFL = {1: 0.1, 2: 0.05, 3: 0.0125, 4: 0.00625}
+
+
+def case_shock(E, order_p, n_pe=64, L=4, seed=2503):
+    """Reacting shock of the detonation workload at its resolution (dx = 1/32): domain E/32 long,
+    shock one sixteenth of the way in (on an element face: E a multiple of 16).  The Courant
+    number shrinks with the order (no positivity limiter: the high orders need the margin)."""
+    if E % 16:
+        raise ValueError("E must be a multiple of 16")
+    length = E / 32.0
+    return case_c2(E=E, order_p=order_p, n_pe=min(n_pe, E), L=L, seed=seed, length=length,
+                   shock_x=length / 16.0, cfl=SHOCK_CFL[order_p])
+
+
+def c4_requests(n, rate, seed=42, arrival_seed=7, e_range=(256, 65536), steps_range=(100, 2000),
+                mech=None, delay_seed=2505):
+    """Served stream: Poisson arrivals at `rate` requests/s (all at t = 0 when rate is None), half
+    ignition requests (Navier-Stokes, detailed chemistry, 1 cm, 16 PEs, SAA k <= 2) and half reacting
+    shocks (one-step Euler with the limiter, 64 PEs, k <= 3); element counts log-uniform in e_range,
+    N_p uniform in {1..4}, step counts uniform in steps_range.  Yields dicts with keys
+    rid, kind, case, w0, steps, arrival."""
+    rng = np.random.default_rng(seed)
+    arr = np.random.default_rng(arrival_seed)
+    mech = mech if mech is not None else c1_mechanism()
+    dt_chem = default_dt(0.04, 0.01 / 2048, 750.0, 3)
+    lo, hi = math.log(e_range[0]), math.log(e_range[1])
+    t = 0.0
+    for i in range(n):
+        if rate:
+            t += float(arr.exponential(1.0 / rate))
+        kind = "ignition" if rng.random() < 0.5 else "shock"
+        E = int(round(math.exp(rng.uniform(lo, hi))))
+        order_p = int(rng.integers(1, 5))
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        if kind == "ignition":
+            case, w0 = case_c1(E=E, order_p=order_p, steps=steps, n_pe=min(16, E), seed=(delay_seed << 20) + i,
+                               cfl=IGNITION_CFL[order_p], mech=mech, phase=float(rng.uniform(0.0, 2.0 * math.pi)))
+            case["disc"]["dt"] = min(case["disc"]["dt"], dt_chem, diffusive_dt(mech, 0.01 / E, order_p))
+        else:
+            E = max(e_range[0], 16 * int(round(E / 16)))
+            case, w0 = case_shock(E, order_p, seed=(delay_seed << 20) + i)
+        case["name"] = "c4_" + kind
+        yield {"rid": i, "kind": kind, "case": case, "w0": w0, "steps": steps, "arrival": t}
 
 
 def dof(case: dict) -> int:
