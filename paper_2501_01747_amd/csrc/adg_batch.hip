@@ -165,6 +165,12 @@ void rebuild_tiles(adg_batch *b) {
   };
   add_group(0, 0, 0, [](const Slot &s) { return s.P.phys.model == ADG_DETAILED; },
             [](const Slot &s) { return (s.P.lay.E + kNsTile - 1) / kNsTile; });
+  if (!b->groups.empty() && b->groups[0].kind == 0) {
+    int mm = 2;
+    for (const Slot &s : b->slots)
+      if (s.used && s.P.phys.model == ADG_DETAILED) mm = std::max(mm, s.P.lay.M);
+    b->groups[0].M = mm;
+  }
   for (int kind = 1; kind <= 3; ++kind)
     for (int M = 2; M <= kMaxM; ++M)
       for (int flux = 0; flux <= (kind == 1 ? 1 : 0); ++flux)
@@ -185,7 +191,7 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
         BHIP(b, hipEventRecord(e0, st));
       }
       if (g.kind == 0) {
-        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->precision == ADG_MIXED_FP32, st));
+        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->precision == ADG_MIXED_FP32, g.M, st));
       } else {
         BHIP(b, launch_euler_batch(g.kind - 1, g.M, g.flux, b->d_eu, b->d_tiles + g.off, g.n, stage, st));
       }

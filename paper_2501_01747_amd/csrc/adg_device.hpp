@@ -52,16 +52,17 @@ __device__ __forceinline__ double at_weight(int q, int k, int j) {
 // End of a time step, called by every one of the `nblocks` workgroups that work
 // on one problem in the step's last kernel, after its work: the last one to
 // finish advances the problem's step counter.  Every workgroup has read the
-// counter at its start, before it signs in here.
+// counter at its start, before it signs in here.  No memory fence: nothing in
+// this kernel reads what the others wrote (the stage's outputs are read by
+// later launches, after the kernel boundary), and a device-scope release here
+// would write back the whole L2 of the workgroup's XCD once per workgroup.
 __device__ __forceinline__ void finish_step(long long *step, unsigned *done, unsigned nblocks) {
-  __syncthreads();
+  __syncthreads();   // every wavefront of this workgroup has read the step counter
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned prev = atomicAdd(done, 1u);
     if (prev == nblocks - 1) {
       atomicAdd((unsigned long long *)step, 1ull);
       atomicExch(done, 0u);
-      __threadfence();
     }
   }
 }

@@ -88,6 +88,9 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, int blk, in
   bool ok = true;
 
   double u[V][M], wn[V][M];
+  // w^n of an owned element is loaded together with the stage input, so both loads are in
+  // flight at once (the last stage overwrites w^n in place; only this lane reads it)
+  if (own && a.stage != 0) load_elem<M>(a.w0, E, x, wn);
   if (loads) {
     load_elem<M>(a.ws, E, x, u);
   } else {
@@ -153,7 +156,6 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, int blk, in
         srcR[j] += a.tb.WB[q][j] * (-rate);
       }
     }
-    if (a.stage != 0) load_elem<M>(a.w0, E, x, wn);
     const bool st_last = a.stage == 2;
     double *recR = (a.store_U && if_left >= 0)   // this element is right of interface if_left
                        ? ring_rec(a.ring, n, a.stage, a.dl.nif, if_left) + a.ring.off_U + V * M : nullptr;

@@ -28,163 +28,32 @@ namespace adg {
 constexpr int kTile = kNsTile;
 constexpr int kThreads = 256;
 
-struct Thermo {
-  double T, cp, cv, p, a;
-};
+// Sum over the four lanes of a quad (every lane receives the same value: the
+// pairwise sums are formed in the same order on every lane).
+__device__ __forceinline__ double quad_sum(double x) {
+  x += __shfl_xor(x, 1, 4);
+  x += __shfl_xor(x, 2, 4);
+  return x;
+}
 
-// Temperature from the internal energy by Newton's method from the fixed start
-// T_guess, |dT| <= 1e-12 T; then cp, cv, p and the frozen sound speed at that T.
-// The mixture energy sum_i Y_i e_i(T) is linear in the species, so its
-// polynomial coefficients are formed once per point and the iteration runs on
-// one quintic: e(T) = T (c0 + T (c1 + T (c2 + T (c3 + T c4)))) + c5.
-template <int NS>
-__device__ __forceinline__ bool ns_thermo(const NsMech *__restrict__ mk, const double *w, int st, double rho_inv,
-                                          double estar, Thermo &th) {
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0, c5 = 0.0, Rmix = 0.0;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const double yr = (w[(3 + i) * st] * rho_inv) * mk->Ri[i];
-    c0 += yr * (mk->a[i][0] - 1.0);
-    c1 += yr * mk->h2[i][0];
-    c2 += yr * mk->h2[i][1];
-    c3 += yr * mk->h2[i][2];
-    c4 += yr * mk->h2[i][3];
-    c5 += yr * mk->a[i][5];
-    Rmix += yr;
-  }
-  // de/dT = c0 + 2 c1 T + 3 c2 T^2 + 4 c3 T^3 + 5 c4 T^4 = cv
-  const double d1 = 2.0 * c1, d2 = 3.0 * c2, d3 = 4.0 * c3, d4 = 5.0 * c4;
-  double T = mk->T_guess;
+// Temperature from the internal energy e* by Newton's method from the fixed
+// start T_guess, |dT| <= 1e-12 T, at most 50 iterations.  The mixture energy
+// sum_i Y_i e_i(T) is linear in the species, so it is one quintic
+// e(T) = T (c0 + T (c1 + T (c2 + T (c3 + T c4)))) + c5; returns cv(T) too.
+__device__ __forceinline__ bool newton_T(const double (&c)[6], double T0, double estar, double &T, double &cv) {
+  const double d1 = 2.0 * c[1], d2 = 3.0 * c[2], d3 = 4.0 * c[3], d4 = 5.0 * c[4];
+  T = T0;
   bool conv = false;
   for (int it = 0; it < 50; ++it) {
-    const double e = T * (c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)))) + c5;
-    const double cv = c0 + T * (d1 + T * (d2 + T * (d3 + T * d4)));
-    const double dT = (e - estar) / cv;
+    const double e = T * (c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * c[4])))) + c[5];
+    const double cvi = c[0] + T * (d1 + T * (d2 + T * (d3 + T * d4)));
+    const double dT = (e - estar) * __builtin_amdgcn_rcp(cvi);   // the correction needs no IEEE quotient
     T -= dT;
     if (!(T > 0.0) || !isfinite(T)) break;
     if (fabs(dT) <= 1e-12 * T) { conv = true; break; }
   }
-  th.T = T;
-  th.cv = c0 + T * (d1 + T * (d2 + T * (d3 + T * d4)));
-  th.cp = th.cv + Rmix;
-  th.p = w[0] * Rmix * T;
-  th.a = sqrt(th.cp / th.cv * th.p * rho_inv);
-  return conv && th.p > 0.0 && isfinite(th.p) && w[0] > 0.0;
-}
-
-// Subtracts f^d of Eq. (2)-(3) from g (stride gs): tau = 4/3 mu u_x,
-// q = -k T_x + sum_i h_i J_i, unit Lewis number J_i = -rho D dY_i/dx with
-// rho D = mu/Pr.  Species enthalpies are re-evaluated at T (no arrays kept).
-template <int NS>
-__device__ __forceinline__ void ns_diffusive_sub(const NsMech *__restrict__ mk, const double *w, int st,
-                                                 double rho_inv, double u, const Thermo &th, double mu,
-                                                 const double *dw, double *g, int gs) {
-  const double T = th.T;
-  const double kappa = mu * th.cp * mk->inv_prandtl;
-  const double rhoD = mu * mk->inv_prandtl;
-  const double dw0 = dw[0];
-  const double u_x = (dw[st] - u * dw0) * rho_inv;
-  const double E = w[2 * st] * rho_inv;
-  const double e_x = (dw[2 * st] - E * dw0) * rho_inv - u * u_x;
-  double sum_eY = 0.0, sum_hJ = 0.0;
-#pragma unroll 1
-  for (int i = 0; i < NS; ++i) {
-    const double *a = mk->a[i];
-    const double *h2 = mk->h2[i];
-    const double hT = T * (a[0] + T * (h2[0] + T * (h2[1] + T * (h2[2] + T * h2[3])))) + a[5];  // h_i/R_i
-    const double Yx = (dw[(3 + i) * st] - (w[(3 + i) * st] * rho_inv) * dw0) * rho_inv;
-    sum_eY += mk->Ri[i] * (hT - T) * Yx;
-    const double J = -rhoD * Yx;
-    sum_hJ += mk->Ri[i] * hT * J;
-    g[(3 + i) * gs] += J;            // f^d_i = -J_i
-  }
-  const double T_x = (e_x - sum_eY) / th.cv;
-  const double tau = (4.0 / 3.0) * mu * u_x;
-  const double qh = -kappa * T_x + sum_hJ;
-  g[1 * gs] -= tau;
-  g[2 * gs] -= tau * u - qh;
-}
-
-// Mass-action source W_i omega_i of the reversible mechanism.
-template <int NS>
-__device__ __forceinline__ void ns_source(const NsMech *__restrict__ mk, const double *rhoY, double T, double *src) {
-  const double lnT = log(T);
-  const double invT = 1.0 / T;
-  double gRT[NS], conc[NS], wdot[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const double *a = mk->a[i];
-    const double *h2 = mk->h2[i];
-    const double *s2 = mk->s2[i];
-    const double hRT = a[0] + T * (h2[0] + T * (h2[1] + T * (h2[2] + T * h2[3]))) + a[5] * invT;
-    const double sR = a[0] * lnT + T * (a[1] + T * (s2[0] + T * (s2[1] + T * s2[2]))) + a[6];
-    gRT[i] = hRT - sR;
-    conc[i] = rhoY[i] * mk->invW[i];
-    wdot[i] = 0.0;
-  }
-  const double ln_pRT = mk->ln_p_over_Ru - lnT;   // ln(p_ref / (Ru T))
-  for (int r = 0; r < mk->nr; ++r) {
-    const double lnkf = mk->lnA[r] + mk->b[r] * lnT - mk->EaR[r] * invT;
-    double dG = 0.0;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      const int nu = mk->nur[r][i] - mk->nuf[r][i];
-      if (nu != 0) dG += (double)nu * gRT[i];
-    }
-    const double lnKc = -dG + (double)mk->dnu[r] * ln_pRT;
-    double fwd = exp(lnkf), rev = exp(lnkf - lnKc);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      const int f = mk->nuf[r][i], b = mk->nur[r][i];
-      if (f >= 1) fwd *= conc[i];
-      if (f >= 2) fwd *= conc[i];
-      if (b >= 1) rev *= conc[i];
-      if (b >= 2) rev *= conc[i];
-    }
-    const double q = fwd - rev;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      const int nu = mk->nur[r][i] - mk->nuf[r][i];
-      if (nu != 0) wdot[i] += (double)nu * q;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NS; ++i) src[i] = mk->W[i] * wdot[i];
-}
-
-// Everything but the chemistry evaluated at one point, written to LDS:
-// g = f^c - f^d (stride gs), and when `sync` also g_sync with the synchronous
-// gradient dw_sync; returns the spectral radius |u| + a and the temperature.
-template <int NS>
-__device__ __forceinline__ bool ns_point(const NsMech *__restrict__ mk, int viscous, const double *w,
-                                         const double *dw, bool sync, const double *dw_sync, int st, double *g,
-                                         double *g_sync, int gs, double &lam, double &T) {
-  const double rho_inv = 1.0 / w[0];
-  const double u = w[st] * rho_inv;
-  const double estar = w[2 * st] * rho_inv - 0.5 * u * u;
-  Thermo th;
-  const bool ok = ns_thermo<NS>(mk, w, st, rho_inv, estar, th);
-  lam = fabs(u) + th.a;
-  T = th.T;
-  const double fc0 = w[st], fc1 = w[st] * u + th.p, fc2 = u * (w[2 * st] + th.p);
-  g[0] = fc0;
-  g[gs] = fc1;
-  g[2 * gs] = fc2;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) g[(3 + i) * gs] = w[(3 + i) * st] * u;
-  if (sync) {
-    g_sync[0] = fc0;
-    g_sync[gs] = fc1;
-    g_sync[2 * gs] = fc2;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) g_sync[(3 + i) * gs] = w[(3 + i) * st] * u;
-  }
-  if (viscous) {
-    const double mu = mk->mu_ref * exp(mk->mu_exp * log(th.T * mk->inv_T_ref));
-    ns_diffusive_sub<NS>(mk, w, st, rho_inv, u, th, mu, dw, g, gs);
-    if (sync) ns_diffusive_sub<NS>(mk, w, st, rho_inv, u, th, mu, dw_sync, g_sync, gs);
-  }
-  return ok;
+  cv = c[0] + T * (d1 + T * (d2 + T * (d3 + T * d4)));
+  return conv;
 }
 
 // LDS arena of one tile.
@@ -198,17 +67,23 @@ struct NsLds {
   static constexpr int NR = kNsMaxReactions;
   double sW[V * M][NH];
   double sTm[V][NH], sTp[V][NH];
-  double sWc[V][NF], sWa[V][NF];
-  double sQ[V * M][NQ];
   double sG[V][NN];
   double sS[NS][NN];
   double sT[NN];
   double sConc[NS][NN], sGRT[NS][NN];
-  double sRate[NR][NN];
+  // the reaction rates of the chemistry phase reuse the storage of the central traces and
+  // LDG gradients, which are dead once the point phase has ended
+  union {
+    struct {
+      double sWc[V][NF], sWa[V][NF];
+      double sQ[V * M][NQ];
+    } early;
+    double sRate[NR][NN];
+  } u;
   double sGf[2][V][TE + 1], sGs[2][V][TE + 1];
   double sLam[2][TE + 1];
   static constexpr int NP = NN + 2 * (TE + 1);   // points: the nodes, then the face traces
-  double sPw[V][NP], sPd[V][NP], sPs[V][NP];   // value, gradient, synchronous gradient (PE traces)
+  double sLnT[NN], sInvT[NN];
   double sF[V][TE + 1], sFat[V][TE + 1];
   double sB[Q][M], sWG[Q][M], sWB[Q][M], sD[M][M];   // tables, indexed at run time
   int sI[NF], sK[NF];
@@ -241,18 +116,20 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   auto &sW = Ls.sW;
   auto &sTm = Ls.sTm;
   auto &sTp = Ls.sTp;
-  auto &sWc = Ls.sWc;
-  auto &sWa = Ls.sWa;
-  auto &sQ = Ls.sQ;
+  auto &sWc = Ls.u.early.sWc;
+  auto &sWa = Ls.u.early.sWa;
+  auto &sQ = Ls.u.early.sQ;
   auto &sG = Ls.sG;
   auto &sS = Ls.sS;
   auto &sT = Ls.sT;
   auto &sConc = Ls.sConc;
   auto &sGRT = Ls.sGRT;
-  auto &sRate = Ls.sRate;
+  auto &sRate = Ls.u.sRate;
   auto &sGf = Ls.sGf;
   auto &sGs = Ls.sGs;
   auto &sLam = Ls.sLam;
+  auto &sLnT = Ls.sLnT;
+  auto &sInvT = Ls.sInvT;
   auto &sF = Ls.sF;
   auto &sFat = Ls.sFat;
   auto &sB = Ls.sB;
@@ -261,9 +138,6 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   auto &sD = Ls.sD;
   auto &sI = Ls.sI;
   auto &sK = Ls.sK;
-  auto &sPw = Ls.sPw;
-  auto &sPd = Ls.sPd;
-  auto &sPs = Ls.sPs;
   constexpr int NP = NsLds<M, NS>::NP;
   constexpr bool kMixed = !std::is_same<OpT, double>::value;
 
@@ -275,33 +149,68 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const int q_at = a.dl.q;
   bool ok = true;
 
-  // 0. mechanism, state of the tile and its halo, tables, PE-interface data of the faces
+  // 0. mechanism, state of the tile and its halo, tables, PE-interface data of the faces.
+  //    Every global load is issued before the first LDS store, so the phase costs about one
+  //    memory latency.
+  constexpr int kOut = (V * M * TE + kThreads - 1) / kThreads;
+  double w0pre[kOut];   // w^n of the outputs this thread writes in the last phase
   {
+    constexpr int nwords = (int)(sizeof(NsMech) / 8);
+    constexpr int kMw = (nwords + kThreads - 1) / kThreads;
+    constexpr int kSw = (V * M * NH + kThreads - 1) / kThreads;
     const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.mech);
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(&smech);
-    constexpr int nwords = (int)(sizeof(NsMech) / 8);
-    for (int idx = t; idx < nwords; idx += kThreads) dst[idx] = src[idx];
-  }
-#pragma unroll 3
-  for (int idx = t; idx < V * M * NH; idx += kThreads) {
-    const int c = idx / NH, l = idx % NH;
-    int e = (e0 - 2 + l) % E;
-    if (e < 0) e += E;
-    sW[c][l] = ws[sidx(e, c, V * M)];
-  }
-  for (int idx = t; idx < Q * M; idx += kThreads) {
-    const int qn = idx / M, j = idx % M;
-    sB[qn][j] = a.tb.B[qn][j];
-    sWG[qn][j] = a.tb.WG[qn][j];
-    sWB[qn][j] = a.tb.WB[qn][j];
-    if (qn < M) sD[qn][j] = a.tb.Dm[qn][j];
-  }
-  for (int fl = t; fl < NF; fl += kThreads) {
-    int f = (e0 - 1 + fl) % E;
-    if (f < 0) f += E;
-    const int i = a.face_if[f];
-    sI[fl] = i;
-    sK[fl] = i >= 0 ? eff_delay(a.dl, n, i) : 0;
+    unsigned long long mw[kMw];
+    double sw[kSw];
+#pragma unroll
+    for (int m = 0; m < kMw; ++m) {
+      const int idx = t + m * kThreads;
+      mw[m] = idx < nwords ? src[idx] : 0ull;
+    }
+#pragma unroll
+    for (int m = 0; m < kSw; ++m) {
+      const int idx = t + m * kThreads;
+      sw[m] = 0.0;
+      if (idx < V * M * NH) {
+        const int c = idx / NH, l = idx % NH;
+        int e = (e0 - 2 + l) % E;
+        if (e < 0) e += E;
+        sw[m] = ws[sidx(e, c, V * M)];
+      }
+    }
+    int fi = -1;
+    if (t < NF) {
+      int f = (e0 - 1 + t) % E;
+      if (f < 0) f += E;
+      fi = a.face_if[f];
+    }
+#pragma unroll
+    for (int m = 0; m < kOut; ++m) {
+      const int idx = t + m * kThreads;
+      w0pre[m] = 0.0;
+      if (stage != 0 && idx < V * M * nloc) w0pre[m] = w0[sidx(e0 + idx % nloc, idx / nloc, V * M)];
+    }
+#pragma unroll
+    for (int m = 0; m < kMw; ++m) {
+      const int idx = t + m * kThreads;
+      if (idx < nwords) dst[idx] = mw[m];
+    }
+#pragma unroll
+    for (int m = 0; m < kSw; ++m) {
+      const int idx = t + m * kThreads;
+      if (idx < V * M * NH) sW[idx / NH][idx % NH] = sw[m];
+    }
+    if (t < NF) {
+      sI[t] = fi;
+      sK[t] = fi >= 0 ? eff_delay(a.dl, n, fi) : 0;
+    }
+    for (int idx = t; idx < Q * M; idx += kThreads) {
+      const int qn = idx / M, j = idx % M;
+      sB[qn][j] = a.tb.B[qn][j];
+      sWG[qn][j] = a.tb.WG[qn][j];
+      sWB[qn][j] = a.tb.WB[qn][j];
+      if (qn < M) sD[qn][j] = a.tb.Dm[qn][j];
+    }
   }
   __syncthreads();
   const int nr = mk->nr;
@@ -377,92 +286,200 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   }
   __syncthreads();
 
-  // 4a. values and gradients at every point (quadrature nodes of the tile, then both traces
-  //     of faces e0 .. e0+TE) into LDS, one lane per (point, variable)
-  for (int idx = t; idx < V * NP; idx += kThreads) {
-    const int v = idx / NP, p = idx % NP;
-    if (p < NN) {
-      const int el = p / Q, qn = p % Q;
-      OpT x = 0, d = 0;
-#pragma unroll
-      for (int j = kMixed ? 1 : 0; j < M; ++j) {
-        x += (OpT)sB[qn][j] * (OpT)sW[v * M + j][el + 2];
-        d += (OpT)sB[qn][j] * (OpT)sQ[v * M + j][el + 1];
-      }
-      sPw[v][p] = kMixed ? sW[v * M][el + 2] + (double)x : (double)x;
-      sPd[v][p] = kMixed ? sQ[v * M][el + 1] + (double)d : (double)d;
+  // 4. point physics, one quad of lanes per point (the quadrature nodes of the tile, then both
+  //    traces of faces e0 .. e0+TE).  Every lane of a quad forms rho, rho u, rho E and their
+  //    gradients; lane k owns the species k, k+4, k+8.  Species sums (mixture energy polynomial,
+  //    gas constant, diffusive enthalpy terms) are reduced over the quad; the temperature Newton,
+  //    pressure, sound speed and viscosity are evaluated on every lane of the quad alike.
+  //    At the nodes the lanes also form the Gibbs energies and concentrations of their species.
+  {
+    constexpr int NO = (NS + 3) / 4;
+    const int k = t & 3;
+    const int p = min(t >> 2, NP - 1);          // spare quads redo the last point and write nothing
+    const bool writer = (t >> 2) < NP;
+    const bool node = p < NN;
+    int qn = 0, ff = 0, side = 0, l, lq;
+    if (node) {
+      qn = p % Q;
+      l = p / Q + 2;
+      lq = p / Q + 1;
     } else {
       const int pp = p - NN;
-      const int ff = pp >> 1, side = pp & 1;  // face e0 + ff; side 0 = element left of it (at xi = +1)
-      const int l = ff + 1 + side;            // local element
-      const int lq = ff + side;               // its gradient slot; faces lq (left), lq + 1 (right)
-      const OpT sgn = side ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
-      OpT d = 0, pj = kMixed ? sgn : (OpT)1;
+      ff = pp >> 1;                             // face e0 + ff
+      side = pp & 1;                            // 0: the element left of the face (its xi = +1)
+      l = ff + 1 + side;
+      lq = ff + side;                           // gradient slot; its faces are lq and lq + 1
+    }
+    const bool pe = !node && sI[ff + 1] >= 0;
+    // value, gradient and synchronous gradient (PE-interface traces) of variable v
+    auto eval = [&](int v, double &x, double &d, double &ds) {
+      if (node) {
+        OpT xo = 0, dO = 0;
 #pragma unroll
-      for (int j = kMixed ? 1 : 0; j < M; ++j) {
-        d += pj * (OpT)sQ[v * M + j][lq];
-        pj *= sgn;
-      }
-      const double dtr = kMixed ? sQ[v * M][lq] + (double)d : (double)d;
-      sPw[v][p] = side ? sTm[v][l] : sTp[v][l];
-      sPd[v][p] = dtr;
-      if (sI[ff + 1] >= 0) {
-        // synchronous gradient trace at a PE interface: undo the AT central traces of the element's faces
-        const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
-        double corr = 0.0, pk = 1.0;
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
-          pk *= side ? -1.0 : 1.0;
+        for (int j = kMixed ? 1 : 0; j < M; ++j) {
+          xo += (OpT)sB[qn][j] * (OpT)sW[v * M + j][l];
+          dO += (OpT)sB[qn][j] * (OpT)sQ[v * M + j][lq];
         }
-        sPs[v][p] = dtr + corr;
+        x = kMixed ? sW[v * M][l] + (double)xo : (double)xo;
+        d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
+        ds = d;
+      } else {
+        const OpT sgn = side ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
+        OpT dO = 0, pj = kMixed ? sgn : (OpT)1;
+#pragma unroll
+        for (int j = kMixed ? 1 : 0; j < M; ++j) {
+          dO += pj * (OpT)sQ[v * M + j][lq];
+          pj *= sgn;
+        }
+        x = side ? sTm[v][l] : sTp[v][l];
+        d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
+        ds = d;
+        if (pe) {
+          // synchronous gradient trace at a PE interface: undo the AT central traces of the element's faces
+          const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
+          double corr = 0.0, pk = 1.0;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
+            pk *= side ? -1.0 : 1.0;
+          }
+          ds = d + corr;
+        }
+      }
+    };
+    double wr, dr0, sr0, wm, dm, sm, we, de, se;
+    eval(0, wr, dr0, sr0);
+    eval(1, wm, dm, sm);
+    eval(2, we, de, se);
+    double wy[NO], dy[NO], sy[NO];
+#pragma unroll
+    for (int m = 0; m < NO; ++m) {
+      const int i = k + 4 * m;
+      if (i < NS) eval(3 + i, wy[m], dy[m], sy[m]);
+      else wy[m] = dy[m] = sy[m] = 0.0;
+    }
+    const double rho_inv = 1.0 / wr;
+    const double u = wm * rho_inv;
+    const double estar = we * rho_inv - 0.5 * u * u;
+    double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Rmix = 0.0;
+#pragma unroll
+    for (int m = 0; m < NO; ++m) {
+      const int i = k + 4 * m;
+      if (i >= NS) continue;
+      const double yr = (wy[m] * rho_inv) * mk->Ri[i];
+      c[0] += yr * (mk->a[i][0] - 1.0);
+      c[1] += yr * mk->h2[i][0];
+      c[2] += yr * mk->h2[i][1];
+      c[3] += yr * mk->h2[i][2];
+      c[4] += yr * mk->h2[i][3];
+      c[5] += yr * mk->a[i][5];
+      Rmix += yr;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c[q] = quad_sum(c[q]);
+    Rmix = quad_sum(Rmix);
+    double T, cv;
+    const bool conv = newton_T(c, mk->T_guess, estar, T, cv);
+    const double cp = cv + Rmix;
+    const double pr = wr * Rmix * T;
+    const double snd = sqrt(cp / cv * pr * rho_inv);
+    if (writer) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
+    double g0 = wm, g1 = wm * u + pr, g2 = u * (we + pr);
+    double gs1 = g1, gs2 = g2;
+    double gy[NO], gsy[NO];
+#pragma unroll
+    for (int m = 0; m < NO; ++m) gy[m] = gsy[m] = wy[m] * u;
+    if (a.viscous) {
+      const double mu = mk->mu_ref * exp(mk->mu_exp * log(T * mk->inv_T_ref));
+      const double kappa = mu * cp * mk->inv_prandtl;
+      const double rhoD = mu * mk->inv_prandtl;
+      const double En = we * rho_inv;
+      // f^d of Eq. (2)-(3) for one gradient: tau = 4/3 mu u_x, heat flux -k T_x + sum_i h_i J_i,
+      // unit Lewis number J_i = -rho D dY_i/dx with rho D = mu/Pr
+      auto diffusive = [&](double d0, double d1, double d2, const double (&dyy)[NO], double (&gyy)[NO],
+                           double &h1, double &h2) {
+        const double u_x = (d1 - u * d0) * rho_inv;
+        const double e_x = (d2 - En * d0) * rho_inv - u * u_x;
+        double sum_eY = 0.0, sum_hJ = 0.0;
+#pragma unroll
+        for (int m = 0; m < NO; ++m) {
+          const int i = k + 4 * m;
+          if (i >= NS) continue;
+          const double *ai = mk->a[i];
+          const double *h2i = mk->h2[i];
+          const double hT = T * (ai[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3])))) + ai[5];  // h_i/R_i
+          const double Yx = (dyy[m] - (wy[m] * rho_inv) * d0) * rho_inv;
+          sum_eY += mk->Ri[i] * (hT - T) * Yx;
+          const double J = -rhoD * Yx;
+          sum_hJ += mk->Ri[i] * hT * J;
+          gyy[m] += J;                  // f^d_i = -J_i
+        }
+        sum_eY = quad_sum(sum_eY);
+        sum_hJ = quad_sum(sum_hJ);
+        const double T_x = (e_x - sum_eY) / cv;
+        const double tau = (4.0 / 3.0) * mu * u_x;
+        const double qh = -kappa * T_x + sum_hJ;
+        h1 -= tau;
+        h2 -= tau * u - qh;
+      };
+      diffusive(dr0, dm, de, dy, gy, g1, g2);
+      if (pe) diffusive(sr0, sm, se, sy, gsy, gs1, gs2);
+    }
+    if (writer) {
+      if (node) {
+        if (k == 0) {
+          sG[0][p] = g0;
+          sG[1][p] = g1;
+          sG[2][p] = g2;
+          sT[p] = T;
+        }
+        const double lnT = log(T), invT = 1.0 / T;
+        if (k == 1) {
+          sLnT[p] = lnT;
+          sInvT[p] = invT;
+        }
+#pragma unroll
+        for (int m = 0; m < NO; ++m) {
+          const int i = k + 4 * m;
+          if (i >= NS) continue;
+          sG[3 + i][p] = gy[m];
+          const double *ci = mk->a[i];
+          const double *h2i = mk->h2[i];
+          const double *s2i = mk->s2[i];
+          const double hRT = ci[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3]))) + ci[5] * invT;
+          const double sR = ci[0] * lnT + T * (ci[1] + T * (s2i[0] + T * (s2i[1] + T * s2i[2]))) + ci[6];
+          sGRT[i][p] = hRT - sR;
+          sConc[i][p] = wy[m] * mk->invW[i];
+        }
+      } else {
+        if (k == 0) {
+          sGf[side][0][ff] = g0;
+          sGf[side][1][ff] = g1;
+          sGf[side][2][ff] = g2;
+          sLam[side][ff] = fabs(u) + snd;
+          if (pe) {
+            sGs[side][0][ff] = g0;
+            sGs[side][1][ff] = gs1;
+            sGs[side][2][ff] = gs2;
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < NO; ++m) {
+          const int i = k + 4 * m;
+          if (i >= NS) continue;
+          sGf[side][3 + i][ff] = gy[m];
+          if (pe) sGs[side][3 + i][ff] = gsy[m];
+        }
       }
     }
   }
   __syncthreads();
 
-  // 4b. point physics: wavefront 0 takes the quadrature nodes, wavefront 1 the face traces
-  if (t < NN) {
-    double lam, T;
-    ok = ns_point<NS>(mk, a.viscous, &sPw[0][t], &sPd[0][t], false, &sPd[0][t], NP, &sG[0][t], &sG[0][t], NN,
-                      lam, T) && ok;
-    sT[t] = T;
-  } else if (t >= 64 && t < 64 + NT) {
-    const int pp = t - 64;
-    const int ff = pp >> 1, side = pp & 1;
-    const bool pe = sI[ff + 1] >= 0;
-    double lam, T;
-    ok = ns_point<NS>(mk, a.viscous, &sPw[0][NN + pp], &sPd[0][NN + pp], pe, &sPs[0][NN + pp], NP, &sGf[side][0][ff],
-                      &sGs[side][0][ff], TE + 1, lam, T) && ok;
-    sLam[side][ff] = lam;
-  }
-  __syncthreads();
-
-  // 4c. chemistry (Sec. 2: W_i omega_i), one lane per (node, species), then one lane per
-  //     (node, reaction), then one lane per (node, species) again
-  for (int idx = t; idx < NS * NN; idx += kThreads) {
-    const int i = idx / NN, p = idx % NN;
-    const int el = p / Q, qn = p % Q;
-    OpT xo = 0;
-#pragma unroll
-    for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)sB[qn][j] * (OpT)sW[(3 + i) * M + j][el + 2];
-    const double x = kMixed ? sW[(3 + i) * M][el + 2] + (double)xo : (double)xo;
-    const double T = sT[p];
-    const double lnT = log(T);
-    const double *c = mk->a[i];
-    const double *h2 = mk->h2[i];
-    const double *s2 = mk->s2[i];
-    const double hRT = c[0] + T * (h2[0] + T * (h2[1] + T * (h2[2] + T * h2[3]))) + c[5] / T;
-    const double sR = c[0] * lnT + T * (c[1] + T * (s2[0] + T * (s2[1] + T * s2[2]))) + c[6];
-    sGRT[i][p] = hRT - sR;
-    sConc[i][p] = x * mk->invW[i];
-  }
-  __syncthreads();
+  // chemistry (Sec. 2: W_i omega_i): one lane per (node, reaction), then one lane per (node, species)
   for (int idx = t; idx < nr * NN; idx += kThreads) {
     const int r = idx / NN, p = idx % NN;
-    const double T = sT[p];
-    const double lnT = log(T);
-    const double lnkf = mk->lnA[r] + mk->b[r] * lnT - mk->EaR[r] / T;
+    const double lnT = sLnT[p];
+    const double lnkf = mk->lnA[r] + mk->b[r] * lnT - mk->EaR[r] * sInvT[p];
     double dG = 0.0;
     for (int g = 0; g < mk->ng[r]; ++g) dG += mk->gnu[r][g] * sGRT[mk->gidx[r][g]][p];
     const double lnKc = -dG + (double)mk->dnu[r] * (mk->ln_p_over_Ru - lnT);
@@ -479,10 +496,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   for (int idx = t; idx < NS * NN; idx += kThreads) {
     const int i = idx / NN, p = idx % NN;
     double wdot = 0.0;
-    for (int r = 0; r < nr; ++r) {
-      const double nu = mk->nud[r][i];
-      if (nu != 0.0) wdot += nu * sRate[r][p];
-    }
+    const int cnt = mk->spn[i];
+    for (int m = 0; m < cnt; ++m) wdot += (double)mk->spnu[i][m] * sRate[mk->spr[i][m]][p];
     sS[i][p] = mk->W[i] * wdot;
   }
 
@@ -507,7 +522,10 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   __syncthreads();
 
   // 6. lift, source projection, SSP-RK3 combination
-  for (int idx = t; idx < V * M * nloc; idx += kThreads) {
+#pragma unroll
+  for (int m = 0; m < kOut; ++m) {
+    const int idx = t + m * kThreads;
+    if (idx >= V * M * nloc) break;
     const int c = idx / nloc, el = idx % nloc;
     const int v = c / M, j = c % M;
     OpT vol = 0;
@@ -534,8 +552,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const size_t gi = sidx(e0 + el, c, V * M);
     double o;
     if (stage == 0) o = y;
-    else if (stage == 1) o = 0.75 * w0[gi] + 0.25 * y;
-    else o = (1.0 / 3.0) * w0[gi] + (2.0 / 3.0) * y;
+    else if (stage == 1) o = 0.75 * w0pre[m] + 0.25 * y;
+    else o = (1.0 / 3.0) * w0pre[m] + (2.0 / 3.0) * y;
     wout[gi] = o;
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
@@ -549,17 +567,40 @@ __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   ns_tile<M, NS, double>(a, a.ws, a.w0, a.wout, a.stage, a.advance, blockIdx.x * kTile, gridDim.x, L, smech);
 }
 
+// LDS of the batched kernel: room for the largest order it serves.
+template <int MMAX>
+union NsBatchLds;
+template <>
+union NsBatchLds<2> {
+  NsLds<2, kNsMaxSpecies> m2;
+};
+template <>
+union NsBatchLds<3> {
+  NsLds<2, kNsMaxSpecies> m2;
+  NsLds<3, kNsMaxSpecies> m3;
+};
+template <>
+union NsBatchLds<4> {
+  NsLds<2, kNsMaxSpecies> m2;
+  NsLds<3, kNsMaxSpecies> m3;
+  NsLds<4, kNsMaxSpecies> m4;
+};
+template <>
+union NsBatchLds<5> {
+  NsLds<2, kNsMaxSpecies> m2;
+  NsLds<3, kNsMaxSpecies> m3;
+  NsLds<4, kNsMaxSpecies> m4;
+  NsLds<5, kNsMaxSpecies> m5;
+};
+
 // Batched stage kernel: one workgroup per (instance, tile) entry of the work
-// list; instances differ in size, order, PE layout and delays.
-template <typename OpT>
+// list; instances differ in size, order (up to MMAX modes), PE layout and
+// delays.  Sizing the LDS for the largest order present keeps more workgroups
+// resident when the batch holds only low orders.
+template <typename OpT, int MMAX>
 __global__ __launch_bounds__(kThreads) void ns_batch_kernel(const NsArgs *__restrict__ insts,
                                                             const int2 *__restrict__ tiles, int stage) {
-  __shared__ union {
-    NsLds<2, kNsMaxSpecies> m2;
-    NsLds<3, kNsMaxSpecies> m3;
-    NsLds<4, kNsMaxSpecies> m4;
-    NsLds<5, kNsMaxSpecies> m5;
-  } L;
+  __shared__ NsBatchLds<MMAX> L;
   __shared__ NsMech smech;
   const int2 tl = tiles[blockIdx.x];
   const NsArgs &a = insts[tl.x];
@@ -569,11 +610,19 @@ __global__ __launch_bounds__(kThreads) void ns_batch_kernel(const NsArgs *__rest
   const double *w0 = a.W[0];
   double *wout = a.W[out_buf];
   const int ntiles = (a.E + kTile - 1) / kTile;
-  switch (a.M) {
-    case 2: ns_tile<2, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech); break;
-    case 3: ns_tile<3, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech); break;
-    case 4: ns_tile<4, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech); break;
-    default: ns_tile<5, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech); break;
+  const int M = a.M;
+  if (M == 2) {
+    ns_tile<2, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech);
+  } else if constexpr (MMAX >= 3) {
+    if (M == 3) {
+      ns_tile<3, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech);
+    } else if constexpr (MMAX >= 4) {
+      if (M == 4) {
+        ns_tile<4, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech);
+      } else if constexpr (MMAX >= 5) {
+        ns_tile<5, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech);
+      }
+    }
   }
 }
 
@@ -624,25 +673,26 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
     for (int i = 0; i < hm.ns; ++i) {
       const int f = m->nu_f[r * hm.ns + i], b = m->nu_r[r * hm.ns + i];
       if (f < 0 || f > 2 || b < 0 || b > 2) return ADG_ERR_UNSUPPORTED;
-      hm.nuf[r][i] = f;
-      hm.nur[r][i] = b;
       dnu += b - f;
     }
     hm.dnu[r] = dnu;
     int nf = 0, nb = 0, g = 0;
     hm.rf[r][0] = hm.rf[r][1] = hm.rr[r][0] = hm.rr[r][1] = -1;
     for (int i = 0; i < hm.ns; ++i) {
-      for (int c = 0; c < hm.nuf[r][i]; ++c) {
+      const int fi = m->nu_f[r * hm.ns + i], bi = m->nu_r[r * hm.ns + i];
+      for (int c = 0; c < fi; ++c) {
         if (nf == 2) return ADG_ERR_UNSUPPORTED;   // at most two reactant molecules
         hm.rf[r][nf++] = i;
       }
-      for (int c = 0; c < hm.nur[r][i]; ++c) {
+      for (int c = 0; c < bi; ++c) {
         if (nb == 2) return ADG_ERR_UNSUPPORTED;
         hm.rr[r][nb++] = i;
       }
-      const int nu = hm.nur[r][i] - hm.nuf[r][i];
-      hm.nud[r][i] = nu;
+      const int nu = bi - fi;
       if (nu != 0) {
+        hm.spr[i][hm.spn[i]] = (unsigned char)r;
+        hm.spnu[i][hm.spn[i]] = (signed char)nu;
+        hm.spn[i] += 1;
         if (g == 4) return ADG_ERR_UNSUPPORTED;
         hm.gidx[r][g] = i;
         hm.gnu[r][g] = nu;
@@ -675,10 +725,22 @@ static hipError_t ns_M(const NsArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, hipStream_t s) {
+template <typename OpT>
+static void batch_launch(int max_m, const NsArgs *insts, const int2 *tiles, int ntiles, int stage, hipStream_t s) {
+  switch (max_m) {
+    case 2: hipLaunchKernelGGL((ns_batch_kernel<OpT, 2>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
+    case 3: hipLaunchKernelGGL((ns_batch_kernel<OpT, 3>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
+    case 4: hipLaunchKernelGGL((ns_batch_kernel<OpT, 4>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
+    default: hipLaunchKernelGGL((ns_batch_kernel<OpT, 5>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
+  }
+}
+
+hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, int max_m,
+                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (mixed) hipLaunchKernelGGL(ns_batch_kernel<float>, dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage);
-  else hipLaunchKernelGGL(ns_batch_kernel<double>, dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage);
+  if (max_m < 2 || max_m > kMaxM) return hipErrorInvalidValue;
+  if (mixed) batch_launch<float>(max_m, insts, tiles, ntiles, stage, s);
+  else batch_launch<double>(max_m, insts, tiles, ntiles, stage, s);
   return hipGetLastError();
 }
 

@@ -26,15 +26,17 @@ struct NsMech {
   double s2[kNsMaxSpecies][3];      // a2/2, a3/3, a4/4
   double lnA[kNsMaxReactions], b[kNsMaxReactions], EaR[kNsMaxReactions];
   int dnu[kNsMaxReactions];
-  int nuf[kNsMaxReactions][kNsMaxSpecies];
-  int nur[kNsMaxReactions][kNsMaxSpecies];
   // compact per-reaction form for one lane per (point, reaction): the species
   // multiplied into the forward and reverse rates (-1 = none) and the nonzero
   // net coefficients nu_i = nu''_i - nu'_i
   int rf[kNsMaxReactions][2], rr[kNsMaxReactions][2];
   int ng[kNsMaxReactions], gidx[kNsMaxReactions][4];
   double gnu[kNsMaxReactions][4];
-  double nud[kNsMaxReactions][kNsMaxSpecies];
+  // per species, the reactions with a nonzero net coefficient (increasing r) and that coefficient
+  int spn[kNsMaxSpecies];
+  unsigned char spr[kNsMaxSpecies][kNsMaxReactions];
+  signed char spnu[kNsMaxSpecies][kNsMaxReactions];
+  int pad_;
 };
 
 struct NsArgs {
@@ -65,8 +67,10 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
                     long long *step, unsigned *done, int *err, NsMech *dev_mech);
 hipError_t launch_ns_stage(int M, const NsArgs &a, hipStream_t s);
-// One stage for every (instance, tile) entry of `tiles` (device); mixed = FP32 modal operators.
-hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, hipStream_t s);
+// One stage for every (instance, tile) entry of `tiles` (device); mixed = FP32 modal operators;
+// max_m = the largest N_p + 1 among the listed instances.
+hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, int max_m,
+                           hipStream_t s);
 constexpr int kNsTile = 8;
 
 }  // namespace adg

@@ -20,7 +20,7 @@ def adg():
     return lib
 
 
-def small_stream(n=16, rate=400.0):
+def small_stream(n=16, rate=None):
     from paper_2501_01747_amd.serve import Request
 
     reqs = []
@@ -35,7 +35,7 @@ def test_served_equals_alone(adg, precision):
 
     reqs = small_stream()
     foot = [adg.Batch.instance_bytes(r.case) for r in reqs]
-    # room for about a third of the stream at once: admission has to wait
+    # every request arrives at t = 0 and there is room for about a third of them at once
     b = adg.Batch(8, 1 << 20, sum(foot) // 3, precision=precision)
     srv = Server(b, chunk=6, keep_states=True)
     res = srv.run(reqs)
@@ -43,7 +43,7 @@ def test_served_equals_alone(adg, precision):
     s = summarize(res)
     print(f"[serve] {precision} {s} rounds={srv.rounds} max_active={srv.max_active}", flush=True)
     assert s["failed"] == 0 and 1 < srv.max_active < len(reqs)
-    assert any(r.admitted > r.arrival + 1e-3 for r in res)        # someone queued
+    assert any(r.admitted > r.arrival for r in res[3:])           # all arrive at once: some wait for space
     for q, r in zip(reqs, res):
         alone = adg.Batch(1, q.case["disc"]["n_elem"], adg.Batch.instance_bytes(q.case), precision=precision)
         sl = alone.add(q.case, q.w0, n_steps=q.steps)
