@@ -34,7 +34,13 @@ struct Slot {
   Problem P;
   size_t off = 0, bytes = 0;  // heap region
   long long target = kNoTarget;
+  int mech = -1;              // shared mechanism slot (detailed chemistry)
 };
+
+// Distinct mechanisms a batch holds at once: instances with byte-identical
+// mechanisms share one device copy (all the tiles of a batch of one mechanism
+// then read the same few kilobytes, which stay in every L2).
+constexpr int kBatchMechs = 16;
 
 struct Group {
   int kind;  // 0 detailed stage, 1 one-step stage, 2 limiter, 3 scatter
@@ -56,6 +62,9 @@ struct adg_batch {
   long long max_tiles = 0;
   NsArgs *d_ns = nullptr;
   EulerSet *d_eu = nullptr;
+  NsMech *d_mech = nullptr;
+  std::vector<NsMech> mech_host = std::vector<NsMech>(kBatchMechs);
+  std::vector<int> mech_ref = std::vector<int>(kBatchMechs, 0);
   int2 *d_tiles = nullptr;
   long long *d_step = nullptr;
   int *d_err = nullptr;
@@ -81,7 +90,7 @@ struct adg_batch {
 namespace {
 
 struct Header {
-  size_t ns, eu, tiles, step, err, done, total;
+  size_t ns, eu, mech, tiles, step, err, done, total;
 };
 
 Header header_layout(int max_inst, long long max_tiles) {
@@ -89,6 +98,7 @@ Header header_layout(int max_inst, long long max_tiles) {
   size_t off = 0;
   h.ns = off;    off += align256(sizeof(NsArgs) * (size_t)max_inst);
   h.eu = off;    off += align256(sizeof(EulerSet) * (size_t)max_inst);
+  h.mech = off;  off += align256(sizeof(NsMech) * (size_t)kBatchMechs);
   h.tiles = off; off += align256(sizeof(int2) * (size_t)max_tiles);
   h.step = off;  off += align256(sizeof(long long) * (size_t)max_inst);
   h.err = off;   off += align256(sizeof(int) * (size_t)max_inst);
@@ -161,6 +171,10 @@ void rebuild_tiles(adg_batch *b) {
       for (int k = 0; k < nb; ++k) b->h_tiles.push_back(make_int2(i, k * (kind == 0 ? kNsTile : 1)));
     }
     g.n = (int)b->h_tiles.size() - g.off;
+    // XCD-aware order: workgroup p of the launch takes work item xcd_item(p, n), so each XCD
+    // works through a contiguous run of tiles (same instances, shared halos, one L2)
+    std::vector<int2> run(b->h_tiles.begin() + g.off, b->h_tiles.end());
+    for (int p = 0; p < g.n; ++p) b->h_tiles[g.off + p] = run[xcd_item(p, g.n)];
     if (g.n > 0) b->groups.push_back(g);
   };
   add_group(0, 0, 0, [](const Slot &s) { return s.P.phys.model == ADG_DETAILED; },
@@ -284,6 +298,7 @@ adg_status adg_batch_create(int32_t max_instances, int64_t max_elements, int32_t
   b->max_tiles = max_tiles;
   b->d_ns = (NsArgs *)(b->ws + h.ns);
   b->d_eu = (EulerSet *)(b->ws + h.eu);
+  b->d_mech = (NsMech *)(b->ws + h.mech);
   b->d_tiles = (int2 *)(b->ws + h.tiles);
   b->d_step = (long long *)(b->ws + h.step);
   b->d_err = (int *)(b->ws + h.err);
@@ -335,7 +350,28 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
     return bfail(b, ADG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
   };
   if (P.phys.model == ADG_DETAILED) {
+    NsMech hm;
+    if (ns_build_mech(phys, hm) != ADG_OK) {
+      heap_give(b, off, need);
+      return bfail(b, ADG_ERR_UNSUPPORTED, "unsupported mechanism");
+    }
+    int ms = -1;
+    for (int j = 0; j < kBatchMechs && ms < 0; ++j)
+      if (b->mech_ref[j] > 0 && std::memcmp(&b->mech_host[j], &hm, sizeof hm) == 0) ms = j;
+    if (ms < 0) {
+      for (int j = 0; j < kBatchMechs && ms < 0; ++j)
+        if (b->mech_ref[j] == 0) ms = j;
+      if (ms < 0) {
+        heap_give(b, off, need);
+        return bfail(b, ADG_ERR_NOMEM, "too many distinct mechanisms in the batch");
+      }
+      he = hipMemcpy(b->d_mech + ms, &hm, sizeof hm, hipMemcpyHostToDevice);
+      if (he != hipSuccess) return fail_release(he, "mechanism upload");
+      b->mech_host[ms] = hm;
+    }
+    s.mech = ms;
     NsArgs na = P.na;
+    na.mech = b->d_mech + ms;
     na.step = P.step;
     na.err = P.err;
     na.done = P.done;
@@ -383,6 +419,7 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   if (he == hipSuccess) he = hipStreamSynchronize(b->stream);
   if (he != hipSuccess) return fail_release(he, "initial state");
   b->slots[slot] = s;
+  if (s.mech >= 0) b->mech_ref[s.mech] += 1;
   b->elems += L.E;
   b->active += 1;
   b->dirty = true;
@@ -395,6 +432,7 @@ adg_status adg_batch_remove(adg_batch *b, int32_t slot) {
   BHIP(b, hipStreamSynchronize(b->stream));
   Slot &s = b->slots[slot];
   heap_give(b, s.off, s.bytes);
+  if (s.mech >= 0) b->mech_ref[s.mech] -= 1;
   b->elems -= s.P.lay.E;
   b->active -= 1;
   s = Slot();

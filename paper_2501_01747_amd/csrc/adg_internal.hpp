@@ -114,6 +114,18 @@ struct LimiterArgs {
   double Tr[kMaxM][kMaxM];    // re-expansion of the right neighbour
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8), each with its own L2.  This maps workgroup b of n to a work item
+// so that XCD x gets the contiguous range [x q + min(x, r), ...) of the n items
+// (q = n / 8, r = n mod 8): neighbouring items, which share halo data, then meet
+// in the same L2.  A bijection of [0, n).
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_item(int b, int n) {
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return x * q + (x < r ? x : r) + i;
+}
+
 enum ErrBits { kErrState = 1, kErrNewton = 2 };
 
 constexpr int kLimBlock = 128;

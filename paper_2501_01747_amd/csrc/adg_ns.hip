@@ -564,7 +564,8 @@ template <int M, int NS>
 __global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
   __shared__ NsLds<M, NS> L;
   __shared__ NsMech smech;
-  ns_tile<M, NS, double>(a, a.ws, a.w0, a.wout, a.stage, a.advance, blockIdx.x * kTile, gridDim.x, L, smech);
+  ns_tile<M, NS, double>(a, a.ws, a.w0, a.wout, a.stage, a.advance, xcd_item(blockIdx.x, gridDim.x) * kTile,
+                         gridDim.x, L, smech);
 }
 
 // LDS of the batched kernel: room for the largest order it serves.
@@ -636,9 +637,29 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
                     long long *step, unsigned *done, int *err, NsMech *dev_mech) {
   if (!periodic) return ADG_ERR_UNSUPPORTED;
+  NsMech hm;
+  const adg_status rc = ns_build_mech(ph, hm);
+  if (rc != ADG_OK) return rc;
+  if (hipMemcpy(dev_mech, &hm, sizeof hm, hipMemcpyHostToDevice) != hipSuccess) return ADG_ERR_HIP;
+  a.face_if = face_if;
+  a.step = step;
+  a.done = done;
+  a.err = err;
+  a.mech = dev_mech;
+  a.E = E;
+  a.viscous = ph->viscous;
+  a.dt = d->dt;
+  a.inv_dx = 1.0 / dx;
+  a.dl = dl;
+  a.ring = rp;
+  a.tb = tb;
+  a.M = M;
+  return ADG_OK;
+}
+
+adg_status ns_build_mech(const adg_physics *ph, NsMech &hm) {
   const adg_mechanism *m = ph->mech;
   if (!ns_supported(m->n_species, m->n_reactions)) return ADG_ERR_UNSUPPORTED;
-  NsMech hm;
   std::memset(&hm, 0, sizeof hm);
   hm.ns = m->n_species;
   hm.nr = m->n_reactions;
@@ -701,20 +722,6 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
     }
     hm.ng[r] = g;
   }
-  if (hipMemcpy(dev_mech, &hm, sizeof hm, hipMemcpyHostToDevice) != hipSuccess) return ADG_ERR_HIP;
-  a.face_if = face_if;
-  a.step = step;
-  a.done = done;
-  a.err = err;
-  a.mech = dev_mech;
-  a.E = E;
-  a.viscous = ph->viscous;
-  a.dt = d->dt;
-  a.inv_dx = 1.0 / dx;
-  a.dl = dl;
-  a.ring = rp;
-  a.tb = tb;
-  a.M = M;
   return ADG_OK;
 }
 

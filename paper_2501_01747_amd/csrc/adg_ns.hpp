@@ -66,6 +66,8 @@ bool ns_supported(int n_species, int n_reactions);
 adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *d, int E, int M, bool periodic,
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
                     long long *step, unsigned *done, int *err, NsMech *dev_mech);
+// The device form of a mechanism (host side; validates it).
+adg_status ns_build_mech(const adg_physics *ph, NsMech &hm);
 hipError_t launch_ns_stage(int M, const NsArgs &a, hipStream_t s);
 // One stage for every (instance, tile) entry of `tiles` (device); mixed = FP32 modal operators;
 // max_m = the largest N_p + 1 among the listed instances.
