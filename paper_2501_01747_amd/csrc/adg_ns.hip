@@ -26,13 +26,15 @@
 namespace adg {
 
 constexpr int kTile = kNsTile;
-constexpr int kThreads = 256;
+constexpr int kThreadsBatch = 256;   // batched kernel: more resident workgroups per CU
+constexpr int kThreadsSingle = 512;  // one problem: more lanes per tile, shorter phases
 
-// Sum over the four lanes of a quad (every lane receives the same value: the
-// pairwise sums are formed in the same order on every lane).
-__device__ __forceinline__ double quad_sum(double x) {
-  x += __shfl_xor(x, 1, 4);
-  x += __shfl_xor(x, 2, 4);
+// Sum over the LP lanes of a point group (every lane receives the same value:
+// the pairwise sums are formed in the same order on every lane).
+template <int LP>
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+  for (int m = 1; m < LP; m <<= 1) x += __shfl_xor(x, m, LP);
   return x;
 }
 
@@ -105,7 +107,7 @@ struct NsLds {
 // the magnitude of the state (pressure-sized fluxes would otherwise lose about
 // 4 digits of their element-to-element differences).  Gradients at nodes and
 // traces are likewise mode 0 plus the FP32 sum of the higher modes.
-template <int M, int NS, typename OpT>
+template <int M, int NS, typename OpT, int NTH>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
                                         double *wout, int stage, int advance, int e0, int ntiles,
                                         NsLds<M, NS> &Ls, NsMech &smech) {
@@ -152,24 +154,24 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   // 0. mechanism, state of the tile and its halo, tables, PE-interface data of the faces.
   //    Every global load is issued before the first LDS store, so the phase costs about one
   //    memory latency.
-  constexpr int kOut = (V * M * TE + kThreads - 1) / kThreads;
+  constexpr int kOut = (V * M * TE + NTH - 1) / NTH;
   double w0pre[kOut];   // w^n of the outputs this thread writes in the last phase
   {
     constexpr int nwords = (int)(sizeof(NsMech) / 8);
-    constexpr int kMw = (nwords + kThreads - 1) / kThreads;
-    constexpr int kSw = (V * M * NH + kThreads - 1) / kThreads;
+    constexpr int kMw = (nwords + NTH - 1) / NTH;
+    constexpr int kSw = (V * M * NH + NTH - 1) / NTH;
     const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.mech);
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(&smech);
     unsigned long long mw[kMw];
     double sw[kSw];
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
-      const int idx = t + m * kThreads;
+      const int idx = t + m * NTH;
       mw[m] = idx < nwords ? src[idx] : 0ull;
     }
 #pragma unroll
     for (int m = 0; m < kSw; ++m) {
-      const int idx = t + m * kThreads;
+      const int idx = t + m * NTH;
       sw[m] = 0.0;
       if (idx < V * M * NH) {
         const int c = idx / NH, l = idx % NH;
@@ -186,25 +188,25 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     }
 #pragma unroll
     for (int m = 0; m < kOut; ++m) {
-      const int idx = t + m * kThreads;
+      const int idx = t + m * NTH;
       w0pre[m] = 0.0;
       if (stage != 0 && idx < V * M * nloc) w0pre[m] = w0[sidx(e0 + idx % nloc, idx / nloc, V * M)];
     }
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
-      const int idx = t + m * kThreads;
+      const int idx = t + m * NTH;
       if (idx < nwords) dst[idx] = mw[m];
     }
 #pragma unroll
     for (int m = 0; m < kSw; ++m) {
-      const int idx = t + m * kThreads;
+      const int idx = t + m * NTH;
       if (idx < V * M * NH) sW[idx / NH][idx % NH] = sw[m];
     }
     if (t < NF) {
       sI[t] = fi;
       sK[t] = fi >= 0 ? eff_delay(a.dl, n, fi) : 0;
     }
-    for (int idx = t; idx < Q * M; idx += kThreads) {
+    for (int idx = t; idx < Q * M; idx += NTH) {
       const int qn = idx / M, j = idx % M;
       sB[qn][j] = a.tb.B[qn][j];
       sWG[qn][j] = a.tb.WG[qn][j];
@@ -217,7 +219,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 
   // 1. traces of w; meanwhile the AT combinations of past levels (Eq. (7)) of the central
   //    traces and of the fluxes at delayed PE interfaces are gathered from the ring
-  for (int idx = t; idx < V * NH; idx += kThreads) {
+  for (int idx = t; idx < V * NH; idx += NTH) {
     const int v = idx / NH, l = idx % NH;
     OpT sm = 0, sp = 0;
 #pragma unroll
@@ -234,7 +236,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       sTp[v][l] = (double)sp;
     }
   }
-  for (int idx = t; idx < V * NF; idx += kThreads) {
+  for (int idx = t; idx < V * NF; idx += NTH) {
     const int v = idx / NF, fl = idx % NF;
     const int i = sI[fl], k = sK[fl];
     if (i < 0 || k == 0) continue;
@@ -252,7 +254,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 
   // 2. central traces; face fl sits between local elements fl (left) and fl + 1 (right).
   //    The synchronous value of a PE interface is published for this level.
-  for (int idx = t; idx < V * NF; idx += kThreads) {
+  for (int idx = t; idx < V * NF; idx += NTH) {
     const int v = idx / NF, fl = idx % NF;
     const double wc = kMixed ? 0.5 * (sTp[v][fl] + sTm[v][fl + 1])
                              : (double)((OpT)0.5 * ((OpT)sTp[v][fl] + (OpT)sTm[v][fl + 1]));
@@ -266,7 +268,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 
   // 3. LDG gradient q_j = (2j+1)/dx [w*_R - (-1)^j w*_L - sum_k D_jk w_k] of the element
   //    with gradient slot lq (left face lq, right face lq + 1)
-  for (int idx = t; idx < V * M * NQ; idx += kThreads) {
+  for (int idx = t; idx < V * M * NQ; idx += NTH) {
     const int c = idx / NQ, lq = idx % NQ;
     const int v = c / M, j = c % M;
     OpT vol = 0;
@@ -286,17 +288,19 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   }
   __syncthreads();
 
-  // 4. point physics, one quad of lanes per point (the quadrature nodes of the tile, then both
-  //    traces of faces e0 .. e0+TE).  Every lane of a quad forms rho, rho u, rho E and their
-  //    gradients; lane k owns the species k, k+4, k+8.  Species sums (mixture energy polynomial,
-  //    gas constant, diffusive enthalpy terms) are reduced over the quad; the temperature Newton,
-  //    pressure, sound speed and viscosity are evaluated on every lane of the quad alike.
+  // 4. point physics, one group of LP lanes per point (the quadrature nodes of the tile, then
+  //    both traces of faces e0 .. e0+TE).  Every lane of a group forms rho, rho u, rho E and their
+  //    gradients; lane k owns the species k, k+LP, ....  Species sums (mixture energy polynomial,
+  //    gas constant, diffusive enthalpy terms) are reduced over the group; the temperature Newton,
+  //    pressure, sound speed and viscosity are evaluated on every lane of the group alike.
   //    At the nodes the lanes also form the Gibbs energies and concentrations of their species.
   {
-    constexpr int NO = (NS + 3) / 4;
-    const int k = t & 3;
-    const int p = min(t >> 2, NP - 1);          // spare quads redo the last point and write nothing
-    const bool writer = (t >> 2) < NP;
+    constexpr int LP = NTH / 64;                 // lanes per point: 64 point slots per workgroup
+    static_assert(NP <= NTH / LP, "every point has a lane group");
+    constexpr int NO = (NS + LP - 1) / LP;
+    const int k = t % LP;
+    const int p = min(t / LP, NP - 1);          // spare groups redo the last point and write nothing
+    const bool writer = t / LP < NP;
     const bool node = p < NN;
     int qn = 0, ff = 0, side = 0, l, lq;
     if (node) {
@@ -354,7 +358,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     double wy[NO], dy[NO], sy[NO];
 #pragma unroll
     for (int m = 0; m < NO; ++m) {
-      const int i = k + 4 * m;
+      const int i = k + LP * m;
       if (i < NS) eval(3 + i, wy[m], dy[m], sy[m]);
       else wy[m] = dy[m] = sy[m] = 0.0;
     }
@@ -364,7 +368,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Rmix = 0.0;
 #pragma unroll
     for (int m = 0; m < NO; ++m) {
-      const int i = k + 4 * m;
+      const int i = k + LP * m;
       if (i >= NS) continue;
       const double yr = (wy[m] * rho_inv) * mk->Ri[i];
       c[0] += yr * (mk->a[i][0] - 1.0);
@@ -376,8 +380,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       Rmix += yr;
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) c[q] = quad_sum(c[q]);
-    Rmix = quad_sum(Rmix);
+    for (int q = 0; q < 6; ++q) c[q] = group_sum<LP>(c[q]);
+    Rmix = group_sum<LP>(Rmix);
     double T, cv;
     const bool conv = newton_T(c, mk->T_guess, estar, T, cv);
     const double cp = cv + Rmix;
@@ -403,7 +407,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
         double sum_eY = 0.0, sum_hJ = 0.0;
 #pragma unroll
         for (int m = 0; m < NO; ++m) {
-          const int i = k + 4 * m;
+          const int i = k + LP * m;
           if (i >= NS) continue;
           const double *ai = mk->a[i];
           const double *h2i = mk->h2[i];
@@ -414,8 +418,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
           sum_hJ += mk->Ri[i] * hT * J;
           gyy[m] += J;                  // f^d_i = -J_i
         }
-        sum_eY = quad_sum(sum_eY);
-        sum_hJ = quad_sum(sum_hJ);
+        sum_eY = group_sum<LP>(sum_eY);
+        sum_hJ = group_sum<LP>(sum_hJ);
         const double T_x = (e_x - sum_eY) / cv;
         const double tau = (4.0 / 3.0) * mu * u_x;
         const double qh = -kappa * T_x + sum_hJ;
@@ -440,7 +444,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
         }
 #pragma unroll
         for (int m = 0; m < NO; ++m) {
-          const int i = k + 4 * m;
+          const int i = k + LP * m;
           if (i >= NS) continue;
           sG[3 + i][p] = gy[m];
           const double *ci = mk->a[i];
@@ -465,7 +469,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
         }
 #pragma unroll
         for (int m = 0; m < NO; ++m) {
-          const int i = k + 4 * m;
+          const int i = k + LP * m;
           if (i >= NS) continue;
           sGf[side][3 + i][ff] = gy[m];
           if (pe) sGs[side][3 + i][ff] = gsy[m];
@@ -476,7 +480,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   __syncthreads();
 
   // chemistry (Sec. 2: W_i omega_i): one lane per (node, reaction), then one lane per (node, species)
-  for (int idx = t; idx < nr * NN; idx += kThreads) {
+  for (int idx = t; idx < nr * NN; idx += NTH) {
     const int r = idx / NN, p = idx % NN;
     const double lnT = sLnT[p];
     const double lnkf = mk->lnA[r] + mk->b[r] * lnT - mk->EaR[r] * sInvT[p];
@@ -493,7 +497,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     sRate[r][p] = fwd - rev;
   }
   __syncthreads();
-  for (int idx = t; idx < NS * NN; idx += kThreads) {
+  for (int idx = t; idx < NS * NN; idx += NTH) {
     const int i = idx / NN, p = idx % NN;
     double wdot = 0.0;
     const int cnt = mk->spn[i];
@@ -503,7 +507,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 
   // 5. Rusanov total flux f = (g- + g+)/2 - lambda (w+ - w-)/2 at faces e0 + ff; at PE
   //    interfaces the synchronous flux is published and the AT combination is used
-  for (int idx = t; idx < V * (TE + 1); idx += kThreads) {
+  for (int idx = t; idx < V * (TE + 1); idx += NTH) {
     const int v = idx / (TE + 1), ff = idx % (TE + 1);
     const double wm = sTp[v][ff + 1], wp = sTm[v][ff + 2];
     const double lam = fmax(sLam[0][ff], sLam[1][ff]);
@@ -524,7 +528,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   // 6. lift, source projection, SSP-RK3 combination
 #pragma unroll
   for (int m = 0; m < kOut; ++m) {
-    const int idx = t + m * kThreads;
+    const int idx = t + m * NTH;
     if (idx >= V * M * nloc) break;
     const int c = idx / nloc, el = idx % nloc;
     const int v = c / M, j = c % M;
@@ -561,10 +565,10 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 }
 
 template <int M, int NS>
-__global__ __launch_bounds__(kThreads) void ns_stage_kernel(NsArgs a) {
+__global__ __launch_bounds__(kThreadsSingle) void ns_stage_kernel(NsArgs a) {
   __shared__ NsLds<M, NS> L;
   __shared__ NsMech smech;
-  ns_tile<M, NS, double>(a, a.ws, a.w0, a.wout, a.stage, a.advance, xcd_item(blockIdx.x, gridDim.x) * kTile,
+  ns_tile<M, NS, double, kThreadsSingle>(a, a.ws, a.w0, a.wout, a.stage, a.advance, xcd_item(blockIdx.x, gridDim.x) * kTile,
                          gridDim.x, L, smech);
 }
 
@@ -599,7 +603,7 @@ union NsBatchLds<5> {
 // delays.  Sizing the LDS for the largest order present keeps more workgroups
 // resident when the batch holds only low orders.
 template <typename OpT, int MMAX>
-__global__ __launch_bounds__(kThreads) void ns_batch_kernel(const NsArgs *__restrict__ insts,
+__global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *__restrict__ insts,
                                                             const int2 *__restrict__ tiles, int stage) {
   __shared__ NsBatchLds<MMAX> L;
   __shared__ NsMech smech;
@@ -613,15 +617,15 @@ __global__ __launch_bounds__(kThreads) void ns_batch_kernel(const NsArgs *__rest
   const int ntiles = (a.E + kTile - 1) / kTile;
   const int M = a.M;
   if (M == 2) {
-    ns_tile<2, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech);
+    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech);
   } else if constexpr (MMAX >= 3) {
     if (M == 3) {
-      ns_tile<3, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech);
+      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech);
     } else if constexpr (MMAX >= 4) {
       if (M == 4) {
-        ns_tile<4, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech);
+        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech);
       } else if constexpr (MMAX >= 5) {
-        ns_tile<5, kNsMaxSpecies, OpT>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech);
+        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech);
       }
     }
   }
@@ -728,17 +732,17 @@ adg_status ns_build_mech(const adg_physics *ph, NsMech &hm) {
 template <int M>
 static hipError_t ns_M(const NsArgs &a, hipStream_t s) {
   const int blocks = (a.E + kTile - 1) / kTile;
-  hipLaunchKernelGGL((ns_stage_kernel<M, kNsMaxSpecies>), dim3(blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((ns_stage_kernel<M, kNsMaxSpecies>), dim3(blocks), dim3(kThreadsSingle), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename OpT>
 static void batch_launch(int max_m, const NsArgs *insts, const int2 *tiles, int ntiles, int stage, hipStream_t s) {
   switch (max_m) {
-    case 2: hipLaunchKernelGGL((ns_batch_kernel<OpT, 2>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
-    case 3: hipLaunchKernelGGL((ns_batch_kernel<OpT, 3>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
-    case 4: hipLaunchKernelGGL((ns_batch_kernel<OpT, 4>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
-    default: hipLaunchKernelGGL((ns_batch_kernel<OpT, 5>), dim3(ntiles), dim3(kThreads), 0, s, insts, tiles, stage); break;
+    case 2: hipLaunchKernelGGL((ns_batch_kernel<OpT, 2>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    case 3: hipLaunchKernelGGL((ns_batch_kernel<OpT, 3>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    case 4: hipLaunchKernelGGL((ns_batch_kernel<OpT, 4>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    default: hipLaunchKernelGGL((ns_batch_kernel<OpT, 5>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
   }
 }
 

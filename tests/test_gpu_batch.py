@@ -209,7 +209,9 @@ def test_step_targets(adg, mech):
     b.step(9)
     st, er = b.poll()
     assert st[sa] == 5 and st[sb] == 9 and not er[sa] and not er[sb]
-    np.testing.assert_array_equal(b.state(sa), single(adg, ca, wa, 5))
+    ref = single(adg, ca, wa, 5)
+    # the single-problem kernel splits species sums over 8 lanes per point, the batched one over 4
+    assert np.max(np.abs(b.state(sa) - ref)) <= 1e-13 * np.abs(ref).max()
     b.close()
 
 
