@@ -123,8 +123,9 @@ def src_hash(files) -> str:
 
 
 def read_traffic(name: str, kernel_src: list[str]):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None when
-    missing or taken on a different version of the kernel source."""
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 --pmc summary
+    (2 x FETCH_SIZE + WRITE_SIZE: FETCH_SIZE reads half of a plain copy's read bytes on this
+    part), or None when missing or taken on a different version of the kernel source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.md")
     if not os.path.exists(path):
         return None
@@ -208,7 +209,8 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
                    "order_p": [2, 3], "graph_steps": graph},
         "state_errors": int(er.sum()), "steps_done_min": int(st[st >= 0].min()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "ns_batch_kernel",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": read_traffic("c3", ["adg_ns.hip", "adg_ns.hpp"]), "kernel": "ns_batch_kernel",
                      "launch_ms": stage_ms, "flops_per_launch": flops},
     }
 
@@ -370,17 +372,18 @@ def main():
     stage_ms = prof["stage"][0]
     detailed = case["physics"]["model"] == "detailed"
     kernel_src = ["adg_ns.hip", "adg_ns.hpp"] if detailed else ["adg_euler.hip", "adg_device.hpp"]
+    traffic_key = args.workload if args.n_elem is None else f"{args.workload}_{args.n_elem}"
     if detailed:
         flops = detailed_stage_flops(case)
         achieved = flops / (stage_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": read_traffic(args.workload, kernel_src),
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": read_traffic(traffic_key, kernel_src),
                 "kernel": "ns_stage_kernel", "launch_ms": stage_ms, "flops_per_launch": flops}
     else:
         nbytes = euler_stage_bytes(case)
         achieved = nbytes / (stage_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(args.workload, kernel_src),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(traffic_key, kernel_src),
                 "kernel": "euler_stage_kernel", "launch_ms": stage_ms, "bytes_per_launch": nbytes}
     d = case["disc"]
     out = {
