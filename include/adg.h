@@ -55,6 +55,7 @@ enum { ADG_PERIODIC = 0, ADG_TRANSMISSIVE = 1 };
 enum { ADG_RUSANOV = 0, ADG_HLLC = 1 };
 enum { ADG_SYNC = 0, ADG_CAA = 1, ADG_SAA = 2, ADG_SCHEDULE = 3 };
 enum { ADG_HOST = 0, ADG_DEVICE = 1 };
+enum { ADG_KXRCF = 0, ADG_MINMOD = 1 };
 
 /* Detailed reaction mechanism (Sec. 2: mass-action kinetics with species
    molecular weights W_i and molar production rates omega_i).  Reversible
@@ -96,7 +97,12 @@ typedef struct {
   double x_left, x_right;
   int32_t bc;             /* ADG_PERIODIC | ADG_TRANSMISSIVE (ghost trace = interior trace) */
   int32_t flux;           /* ADG_RUSANOV | ADG_HLLC (HLLC with ADG_ONESTEP only) */
-  int32_t limiter;        /* 1 = KXRCF + characteristic (AT-)WENO after every stage (ADG_ONESTEP) */
+  int32_t limiter;        /* 1 = troubled-cell indicator + characteristic (AT-)WENO after every
+                             stage (ADG_ONESTEP) */
+  int32_t indicator;      /* ADG_KXRCF: Krivodonova et al. on rho and rho E at inflow faces;
+                             ADG_MINMOD: the TVB minmod test of the conserved variables (the
+                             TVD slope-limiter indicator of Sec. 3.3 when tvb_m = 0) */
+  double tvb_m;           /* TVB constant M (>= 0) of ADG_MINMOD: face deviations up to M dx^2 pass */
   double weno_gamma[3];   /* linear weights of Eq. (10) */
   double weno_eps;        /* epsilon of Eq. (10) */
   double dt;              /* fixed time step (> 0); the AT weights of Eq. (8) assume it constant */

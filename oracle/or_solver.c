@@ -420,6 +420,43 @@ static int kxrcf_flag(or_solver *s, const double *we, const double *nbL_tr, cons
   return flag;
 }
 
+/* minmod of three numbers: the one of least magnitude if all share a sign, else 0. */
+static double minmod3(double a, double b, double c) {
+  if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+  if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+  return 0.0;
+}
+
+/* TVB minmod troubled-cell test (the TVD slope-limiter indicator of Sec. 3.3 when
+   M = 0), on every conserved variable.  With the cell mean a (mode 0), the face
+   deviations d+ = w(+1) - a and d- = a - w(-1) and the mean differences
+   D+ = a_{e+1} - a, D- = a - a_{e-1}: the cell is troubled when, for either face,
+   the modified value (d itself if |d| <= M dx^2, else minmod(d, D+, D-)) differs
+   from d by more than 1e-10 of the largest |mean| of any variable in the stencil
+   (round-off in a constant state is not a slope; a variable that is zero there,
+   such as the momentum of gas at rest, takes the scale of the others).
+   Neighbours are the unlimited data (Eq. (11) at delayed PE faces); a ghost
+   neighbour repeats the cell's own mean. */
+static int minmod_flag(or_solver *s, const double *we, const double *nbL, const double *nbR) {
+  int V = s->V, M = s->M;
+  double mh2 = s->cfg.tvb_m * s->dx * s->dx;
+  double tm[OR_MAXV], tp[OR_MAXV];
+  trace_of(s, we, 0, tm);
+  trace_of(s, we, 1, tp);
+  double scale = 0.0;
+  for (int v = 0; v < V; ++v)
+    scale = fmax(scale, fmax(fabs(we[v * M]), fmax(fabs(nbL[v * M]), fabs(nbR[v * M]))));
+  double tol = 1e-10 * scale;
+  for (int v = 0; v < V; ++v) {
+    double a = we[v * M], aL = nbL[v * M], aR = nbR[v * M];
+    double dp = tp[v] - a, dm = a - tm[v], Dp = aR - a, Dm = a - aL;
+    double mp = fabs(dp) <= mh2 ? dp : minmod3(dp, Dp, Dm);
+    double mm = fabs(dm) <= mh2 ? dm : minmod3(dm, Dp, Dm);
+    if (fabs(mp - dp) > tol || fabs(mm - dm) > tol) return 1;
+  }
+  return 0;
+}
+
 /* Limiter over the unlimited stage output wu -> wl (Jacobi: every stencil reads
    unlimited data; across a delayed PE interface the neighbour is Eq. (11)). */
 static int apply_limiter(or_solver *s, int st, const double *wu, double *wl) {
@@ -451,7 +488,7 @@ static int apply_limiter(or_solver *s, int st, const double *wu, double *wl) {
     double trL[OR_MAXV], trR[OR_MAXV];
     trace_of(s, nbL, 1, trL);
     trace_of(s, nbR, 0, trR);
-    int fl = kxrcf_flag(s, we, trL, trR, ghostL, ghostR);
+    int fl = s->cfg.indicator == OR_MINMOD ? minmod_flag(s, we, nbL, nbR) : kxrcf_flag(s, we, trL, trR, ghostL, ghostR);
     s->flags[e] = (int8_t)fl;
     if (fl) {
       s->nflag_total++;

@@ -22,6 +22,7 @@ enum { OR_ONESTEP = 0, OR_DETAILED = 1 };
 enum { OR_PERIODIC = 0, OR_TRANSMISSIVE = 1 };
 enum { OR_RUSANOV = 0, OR_HLLC = 1 };
 enum { OR_SYNC = 0, OR_CAA = 1, OR_SAA = 2, OR_SCHEDULE = 3 };
+enum { OR_KXRCF = 0, OR_MINMOD = 1 };
 
 typedef struct {
   /* ---- physics, Sec. 2 ---- */
@@ -46,7 +47,9 @@ typedef struct {
   double x_left, x_right;
   int32_t bc;             /* OR_PERIODIC | OR_TRANSMISSIVE */
   int32_t flux;           /* OR_RUSANOV | OR_HLLC */
-  int32_t limiter;        /* 1 = KXRCF indicator + characteristic (AT-)WENO, Sec. 3.3 */
+  int32_t limiter;        /* 1 = troubled-cell indicator + characteristic (AT-)WENO, Sec. 3.3 */
+  int32_t indicator;      /* OR_KXRCF | OR_MINMOD (TVB minmod on the conserved variables) */
+  double tvb_m;           /* TVB constant M of the minmod test (0 = TVD) */
   double weno_gamma[3];   /* linear weights gamma_{-1}, gamma_0, gamma_{+1} */
   double weno_eps;
   double dt;

@@ -52,6 +52,7 @@ class OrConfig(C.Structure):
         ("order_p", C.c_int32), ("n_quad", C.c_int32), ("n_elem", C.c_int32),
         ("x_left", C.c_double), ("x_right", C.c_double),
         ("bc", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
+        ("indicator", C.c_int32), ("tvb_m", C.c_double),
         ("weno_gamma", C.c_double * 3), ("weno_eps", C.c_double),
         ("dt", C.c_double),
         ("n_pe", C.c_int32), ("pe_offsets", C.POINTER(C.c_int32)),
@@ -159,6 +160,8 @@ class Config:
         c.bc = TRANSMISSIVE if disc.get("bc", "periodic") == "transmissive" else PERIODIC
         c.flux = HLLC if disc.get("flux", "rusanov") == "hllc" else RUSANOV
         c.limiter = int(disc.get("limiter", 0))
+        c.indicator = {"kxrcf": 0, "minmod": 1}[disc.get("indicator", "kxrcf")]
+        c.tvb_m = float(disc.get("tvb_m", 0.0))
         g = disc.get("weno_gamma", (0.001, 0.998, 0.001))
         c.weno_gamma[0], c.weno_gamma[1], c.weno_gamma[2] = g
         c.weno_eps = float(disc.get("weno_eps", 1e-6))

@@ -22,6 +22,7 @@ RUSANOV, HLLC = 0, 1
 SYNC, CAA, SAA, SCHEDULE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FP64, MIXED_FP32 = 0, 1
+KXRCF, MINMOD = 0, 1
 PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter")
 BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage", "limiter", "limiter_scatter")
 
@@ -55,6 +56,7 @@ class Discretization(C.Structure):
         ("order_p", C.c_int32), ("n_quad", C.c_int32), ("n_elem", C.c_int32),
         ("x_left", C.c_double), ("x_right", C.c_double),
         ("bc", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
+        ("indicator", C.c_int32), ("tvb_m", C.c_double),
         ("weno_gamma", C.c_double * 3), ("weno_eps", C.c_double),
         ("dt", C.c_double),
     ]
@@ -153,6 +155,8 @@ class Problem:
         d.bc = TRANSMISSIVE if disc.get("bc", "periodic") == "transmissive" else PERIODIC
         d.flux = HLLC if disc.get("flux", "rusanov") == "hllc" else RUSANOV
         d.limiter = int(disc.get("limiter", 0))
+        d.indicator = {"kxrcf": KXRCF, "minmod": MINMOD}[disc.get("indicator", "kxrcf")]
+        d.tvb_m = float(disc.get("tvb_m", 0.0))
         g = disc.get("weno_gamma", (0.001, 0.998, 0.001))
         d.weno_gamma[0], d.weno_gamma[1], d.weno_gamma[2] = g
         d.weno_eps = float(disc.get("weno_eps", 1e-6))

@@ -300,6 +300,13 @@ __device__ void neighbour_modes(const LimiterArgs &a, long long n, int e, int si
   load_elem<M>(a.w, E, en, nb);
 }
 
+// minmod of three numbers: the one of least magnitude if all share a sign, else 0
+__device__ __forceinline__ double minmod3(double x, double y, double z) {
+  if (x > 0.0 && y > 0.0 && z > 0.0) return fmin(x, fmin(y, z));
+  if (x < 0.0 && y < 0.0 && z < 0.0) return fmax(x, fmax(y, z));
+  return 0.0;
+}
+
 template <int M>
 __device__ __forceinline__ double trace_at(const double (&c)[M], int side) {
   double s = 0.0;
@@ -320,12 +327,30 @@ __device__ __forceinline__ void limiter_body(const LimiterArgs &a, int blk) {
   neighbour_modes<M>(a, n, e, 1, u, nbR);
   const bool ghostL = !a.periodic && e == 0, ghostR = !a.periodic && e == a.E - 1;
 
+  bool flag = false;
+  if (a.indicator == 1) {
+    // TVB minmod: the face deviations from the mean against the mean differences, every
+    // variable; differences within 1e-10 of the largest |mean| of any variable in the
+    // stencil count as equal (round-off in a constant state is not a slope)
+    double scale = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) scale = fmax(scale, fmax(fabs(u[v][0]), fmax(fabs(nbL[v][0]), fabs(nbR[v][0]))));
+    const double tol = 1e-10 * scale;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double m = u[v][0], mL = nbL[v][0], mR = nbR[v][0];
+      const double dp = trace_at<M>(u[v], 1) - m, dm = m - trace_at<M>(u[v], 0);
+      const double Dp = mR - m, Dm = m - mL;
+      const double mp = fabs(dp) <= a.tvb_mh2 ? dp : minmod3(dp, Dp, Dm);
+      const double mm = fabs(dm) <= a.tvb_mh2 ? dm : minmod3(dm, Dp, Dm);
+      if (fabs(mp - dp) > tol || fabs(mm - dm) > tol) flag = true;
+    }
+  } else {
   // KXRCF: jumps at inflow faces against h^((N_p+1)/2) max_q |w(xi_q)|, on rho and rho E.
   const double uL_e = trace_at<M>(u[1], 0) / trace_at<M>(u[0], 0);
   const double uR_e = trace_at<M>(u[1], 1) / trace_at<M>(u[0], 1);
   const double uL_n = ghostL ? uL_e : trace_at<M>(nbL[1], 1) / trace_at<M>(nbL[0], 1);
   const double uR_n = ghostR ? uR_e : trace_at<M>(nbR[1], 0) / trace_at<M>(nbR[0], 0);
-  bool flag = false;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int v = t == 0 ? 0 : 2;
@@ -341,6 +366,7 @@ __device__ __forceinline__ void limiter_body(const LimiterArgs &a, int blk) {
       norm = fmax(norm, fabs(val));
     }
     if (fabs(jump) / (a.kx_h * norm) > 1.0) flag = true;
+  }
   }
   a.flags[e] = flag ? 1 : 0;
   if (!flag) return;

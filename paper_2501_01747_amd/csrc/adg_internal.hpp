@@ -103,6 +103,8 @@ struct LimiterArgs {
   int periodic;
   int stage;
   double kx_h;          // dx^((N_p+1)/2)
+  int indicator;        // ADG_KXRCF | ADG_MINMOD
+  double tvb_mh2;       // M dx^2 of the TVB minmod test
   double gam[3];
   double eps;
   OneStep ph;

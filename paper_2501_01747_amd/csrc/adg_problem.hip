@@ -139,6 +139,8 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   } else {
     return bad("unknown model");
   }
+  if (d->limiter && d->indicator != ADG_KXRCF && d->indicator != ADG_MINMOD) return bad("unknown indicator");
+  if (d->limiter && !(d->tvb_m >= 0.0)) return bad("tvb_m must be >= 0");
   if (as->mode == ADG_SAA) {
     if (!as->pmf) return bad("SAA needs pmf");
     double s = 0.0;
@@ -273,6 +275,8 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
       l.E = L.E;
       l.periodic = periodic;
       l.kx_h = std::pow(dx, 0.5 * (disc->order_p + 1));
+      l.indicator = disc->indicator;
+      l.tvb_mh2 = disc->tvb_m * dx * dx;
       for (int k = 0; k < 3; ++k) l.gam[k] = disc->weno_gamma[k];
       l.eps = disc->weno_eps;
       l.ph = a.ph;

@@ -165,3 +165,62 @@ def test_c2_full_size_limiter(adg, orc):
         assert tot == o.total_flags()
         assert r < 1e-10, (k, r)
     print(f"[parity] c2 full size: worst rel L2 {worst:.2e}, troubled cells so far {tot}")
+
+
+@pytest.mark.parametrize("order_p,mode", [(1, "saa"), (2, "caa"), (3, "saa")])
+def test_minmod_indicator_limiter(adg, orc, order_p, mode):
+    """The TVB minmod (TVD) indicator with AT-WENO on a reacting shock: states and flags."""
+    case, w0 = gen.case_shock(256, order_p, n_pe=8)
+    case["disc"]["indicator"] = "minmod"
+    if mode == "caa":
+        case["async"].update(mode="caa", L=3)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, 41)
+    for k in range(4):
+        s.step(10)
+        o.step(10)
+        r = rel_l2(s.state(), o.state())
+        fg, tot = s.flags()
+        assert np.array_equal(fg, o.flags()), k
+        assert tot == o.total_flags() and tot > 0
+        assert r < 1e-10, (k, r)
+
+
+def front_position(w, dx, thr=4.0):
+    """Where the element-mean density falls through `thr` (ambient 1, shocked about 8) for the
+    last time, by linear interpolation between element centres."""
+    rho = w[:, 0, 0]
+    i = int(np.nonzero(rho > thr)[0].max())
+    return (i + 0.5 + (rho[i] - thr) / (rho[i] - rho[i + 1])) * dx
+
+
+@pytest.mark.parametrize("indicator", ["minmod", "kxrcf"])
+def test_detonation_front_speed_under_delays(adg, indicator):
+    """Analogue of the paper's comparison of synchronous and asynchronous detonation runs
+    (Sec. 5.2, Table 2): the reacting front's speed under no delays, CAA (k = n mod 3) and SAA
+    (k uniform in {0, 1, 2}) agrees to a fraction of a percent."""
+    E, order_p, steps, every = 2048, 2, 40000, 500
+    speeds = {}
+    for mode in ("sync", "caa", "saa"):
+        case, w0 = gen.case_shock(E, order_p, n_pe=64, L=3)
+        case["disc"]["indicator"] = indicator
+        case["async"]["mode"] = mode
+        dx = (case["disc"]["x_right"] - case["disc"]["x_left"]) / E
+        dt = case["disc"]["dt"]
+        s = adg.Solver(case)
+        s.set_state(w0)
+        s.set_graph(100)
+        t, x = [], []
+        for n in range(every, steps + 1, every):
+            s.step(every)
+            t.append(n * dt)
+            x.append(front_position(s.state(), dx))
+        s.close()
+        h = len(t) // 2
+        speeds[mode] = float(np.polyfit(t[h:], x[h:], 1)[0])
+    print(f"[front-speed] {indicator}: " + ", ".join(f"{m} {v:.4f}" for m, v in speeds.items())
+          + f" (CJ {gen.cj_speed(1.2, 50.0):.4f})", flush=True)
+    for m in ("caa", "saa"):
+        assert abs(speeds[m] / speeds["sync"] - 1.0) < 5e-3
+    assert 4.0 < speeds["sync"] < 9.0

@@ -136,3 +136,40 @@ def test_weno_reproduces_a_global_polynomial(orc):
         rc = orc.lib().or_weno_cell(cfg.ref(), *[orc._dptr(a) for a in args], orc._dptr(out))
         assert rc == 0
         np.testing.assert_allclose(out.reshape(V, M), w0[e], rtol=1e-11, atol=1e-11)
+
+
+# ---- the TVB minmod indicator (the TVD slope-limiter test of Sec. 3.3 when M = 0)
+
+def minmod_case(E, fn, order_p=2, tvb_m=0.0, bc="transmissive"):
+    case, _ = gen.case_c0(E=E, order_p=order_p)
+    case["disc"].update(limiter=1, bc=bc, indicator="minmod", tvb_m=tvb_m, x_left=0.0, x_right=1.0, flux="hllc")
+    case["async"].update(mode="sync", n_pe=1)
+    w0 = gen._fix_density_modes(gen.project(fn, E, order_p, 0.0, 1.0))
+    return case, w0
+
+
+def test_minmod_passes_linear_data(orc):
+    """A global linear state: every face deviation is half of both mean differences."""
+    phys = gen.case_c0()[0]["physics"]
+    case, w0 = minmod_case(40, lambda x: gen.onestep_conserved(1.0 + 0.5 * x, 0.3 + 0.2 * x, 1.0 + x, 0.8, phys))
+    _, flags, _ = run_limiter_once(orc, case, w0)
+    assert not flags[1:-1].any()      # the ends see a ghost with their own mean (no slope allowed)
+
+
+def test_minmod_flags_a_jump_and_smooth_extrema_only_when_tvd(orc):
+    phys = gen.case_c0()[0]["physics"]
+    # a jump inside cell 20 (a jump on a face between two constant cells is already monotone)
+    case, w0 = minmod_case(40, lambda x: gen.onestep_conserved(np.where(x < 0.512, 2.0, 1.0), 0.0, 1.0, 1.0, phys))
+    _, flags, total = run_limiter_once(orc, case, w0)
+    assert total > 0            # troubled in the first stage; limited, it passes the later ones
+    # a smooth periodic wave: with M = 0 the cells around its extrema are troubled (TVD clips them),
+    # with a large M none is
+    wave = lambda x: gen.onestep_conserved(1.0 + 0.2 * np.sin(2 * np.pi * x), 1.0, 1.0, 1.0, phys)
+    case, w0 = minmod_case(64, wave, bc="periodic")
+    _, flags, total = run_limiter_once(orc, case, w0)
+    assert flags[15] or flags[16]      # the maximum sits at x = 0.25 (between cells 15 and 16)
+    assert flags[47] or flags[48]      # the minimum at x = 0.75
+    assert not flags[30:34].any()      # no cell near the zero crossing at x = 0.5 (monotone there)
+    case, w0 = minmod_case(64, wave, bc="periodic", tvb_m=1e4)
+    _, flags, total = run_limiter_once(orc, case, w0)
+    assert total == 0
