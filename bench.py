@@ -187,6 +187,7 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
 
     b, cases = build_c3_batch(precision, n_inst)
     elems = sum(c["disc"]["n_elem"] for c, _ in cases)
+    tuned = b.autotune()
     if graph:
         b.set_graph(graph)
     b.step(warmup)
@@ -206,7 +207,7 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
         "value": dof * 3 * steps / el, "unit": "DOF-updates/s", "ms_per_step": el * 1e3 / steps,
         "steps": steps, "warmup": warmup, "precision": precision,
         "config": {"workload": "c3_batched_ignition", "instances": len(cases), "elements": elems, "dof": dof,
-                   "order_p": [2, 3], "graph_steps": graph},
+                   "order_p": [2, 3], "graph_steps": graph, "tile_elems": (8, 4)[tuned]},
         "state_errors": int(er.sum()), "steps_done_min": int(st[st >= 0].min()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -353,6 +354,7 @@ def main():
     case, w0 = workload(args.workload, args.n_elem)
     s = adg.Solver(case)
     s.set_state(w0)
+    tuned = s.autotune()
     if args.graph:
         s.set_graph(args.graph)
     s.step(args.warmup)
@@ -393,7 +395,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": case["name"], "n_elem": d["n_elem"], "order_p": d["order_p"],
                    "n_vars": 3 + case["physics"]["n_species"], "n_pe": case["async"]["n_pe"],
-                   "delays": case["async"]["mode"], "dof": dof, "graph_steps": args.graph},
+                   "delays": case["async"]["mode"], "dof": dof, "graph_steps": args.graph,
+                   "kernel_config": tuned},
         "roofline": roof,
         "kernel_ms": {k: v[0] for k, v in prof.items()},
     }

@@ -172,6 +172,17 @@ adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *
    (0 = plain launches, the default).  Takes effect at the next adg_step. */
 adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph);
 
+/* Choose the stage kernel's work decomposition by measurement: for the
+   detailed-chemistry model, the tile size (4 or 8 elements) and workgroup size
+   (256 or 512 threads) of the stage kernel, each candidate timed over n_reps
+   launches of the first RK stage on the current state; later steps use the
+   fastest.  The timed launches only rewrite the first stage buffer and the
+   current level's first-stage history, which the next step recomputes, so the
+   solution is unchanged.  *choice (optional) receives the chosen candidate
+   (0: 8/512, 1: 8/256, 2: 4/256, 3: 4/512; always 0 for the one-step model,
+   whose kernel has one decomposition).  Synchronises. */
+adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice);
+
 /* Release the solver (the caller's workspace is not freed). */
 void adg_destroy(adg_solver *s);
 
@@ -255,6 +266,12 @@ adg_status adg_batch_set_graph(adg_batch *b, int32_t steps_per_graph);
    2 limiter, 3 limiter scatter) and launches_out[c] its count.  Synchronises. */
 adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int64_t *launches_out,
                              int32_t n_classes);
+
+/* Choose the tile size (8 or 4 elements) of the batched detailed-chemistry
+   kernel by timing n_reps launches of its first RK stage for the current batch
+   (state unchanged, as for adg_autotune); kept until the next call.  *choice
+   (optional): 0 = 8 elements, 1 = 4.  Synchronises. */
+adg_status adg_batch_autotune(adg_batch *b, int32_t n_reps, int32_t *choice);
 
 /* Number of admitted instances. */
 int32_t adg_batch_active(const adg_batch *b);

@@ -86,6 +86,7 @@ _sig = {
     "adg_n_interfaces": (C.c_int32, [C.c_void_p]),
     "adg_profile": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_int64), C.c_int32]),
     "adg_set_graph": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "adg_autotune": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_int32)]),
     "adg_destroy": (None, [C.c_void_p]),
     "adg_last_error": (C.c_char_p, [C.c_void_p]),
     "adg_batch_header_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
@@ -100,6 +101,7 @@ _sig = {
     "adg_batch_get_state": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32]),
     "adg_batch_set_graph": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_int64), C.c_int32]),
+    "adg_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_int32)]),
     "adg_batch_active": (C.c_int32, [C.c_void_p]),
     "adg_batch_free_bytes": (C.c_int64, [C.c_void_p]),
     "adg_batch_destroy": (None, [C.c_void_p]),
@@ -265,6 +267,12 @@ class Solver:
     def set_graph(self, steps_per_graph: int):
         self._check(adg_set_graph(self.h, int(steps_per_graph)))
 
+    def autotune(self, n_reps: int = 20) -> int:
+        """Pick the stage kernel's work decomposition by timing (state unchanged)."""
+        c = C.c_int32(0)
+        self._check(adg_autotune(self.h, int(n_reps), C.byref(c)))
+        return c.value
+
     def profile(self, n_steps: int) -> dict:
         k = len(PROFILE_CLASSES)
         ms = (C.c_double * k)()
@@ -365,6 +373,12 @@ class Batch:
 
     def set_graph(self, steps_per_graph: int):
         self._check(adg_batch_set_graph(self.h, int(steps_per_graph)))
+
+    def autotune(self, n_reps: int = 5) -> int:
+        """Pick the batched kernel's tile size by timing (state unchanged)."""
+        c = C.c_int32(0)
+        self._check(adg_batch_autotune(self.h, int(n_reps), C.byref(c)))
+        return c.value
 
     def profile(self, n_steps: int) -> dict:
         k = len(BATCH_PROFILE_CLASSES)

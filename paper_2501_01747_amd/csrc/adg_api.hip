@@ -22,6 +22,7 @@ using namespace adg;
 struct adg_solver {
   Problem P;
   hipStream_t stream = nullptr;
+  int ns_cfg = 0;   // work decomposition of the detailed-chemistry stage kernel
   int graph_steps = 0;
   int graph_built_for = 0;
   hipGraph_t graph = nullptr;
@@ -87,7 +88,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       a.stage = stage;
       a.advance = stage == 2;
       if (timer) timer(s, 0, true);
-      HIP_TRY(s, launch_ns_stage(M, a, st));
+      HIP_TRY(s, launch_ns_stage(M, s->ns_cfg, a, st));
       if (timer) timer(s, 0, false);
     }
   }
@@ -270,6 +271,44 @@ adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *
     ms_out[c] = cnt[c] ? sum[c] / cnt[c] : 0.0;
     launches_out[c] = cnt[c];
   }
+  return adg_sync(s);
+}
+
+adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
+  if (!s || n_reps < 1) return ADG_ERR_ARG;
+  if (choice) *choice = 0;
+  if (s->P.phys.model != ADG_DETAILED) return ADG_OK;   // one decomposition only
+  const int M = s->P.lay.M;
+  // stage-0 launches only: they read w^n and write the first stage buffer and the level's
+  // stage-0 history, which the next step recomputes; the state is untouched
+  NsArgs a = s->P.na;
+  a.w0 = s->P.W[0];
+  a.ws = s->P.W[0];
+  a.wout = s->P.W[1];
+  a.stage = 0;
+  a.advance = 0;
+  double best_ms = 0.0;
+  int best = 0;
+  hipEvent_t e0, e1;
+  HIP_TRY(s, hipEventCreate(&e0));
+  HIP_TRY(s, hipEventCreate(&e1));
+  for (int c = 0; c < kNsConfigs; ++c) {
+    HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));   // warm-up
+    HIP_TRY(s, hipEventRecord(e0, s->stream));
+    for (int r = 0; r < n_reps; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));
+    HIP_TRY(s, hipEventRecord(e1, s->stream));
+    HIP_TRY(s, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(s, hipEventElapsedTime(&ms, e0, e1));
+    if (c == 0 || ms < best_ms) { best_ms = ms; best = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best != s->ns_cfg) {
+    s->ns_cfg = best;
+    destroy_graph(s);
+  }
+  if (choice) *choice = best;
   return adg_sync(s);
 }
 

@@ -75,6 +75,7 @@ struct adg_batch {
   long long elems = 0;
   int active = 0;
   bool dirty = true;
+  int tile_elems = 8;        // elements per tile of the detailed-chemistry kernel (4 or 8)
   std::vector<Group> groups;
   std::vector<int2> h_tiles;
   int graph_steps = 0;
@@ -107,7 +108,9 @@ Header header_layout(int max_inst, long long max_tiles) {
   return h;
 }
 
-long long tile_bound(int max_inst, long long max_elem) { return (max_elem + kNsTile - 1) / kNsTile + 4LL * max_inst; }
+long long tile_bound(int max_inst, long long max_elem) {
+  return (max_elem + kNsMinTile - 1) / kNsMinTile + 4LL * max_inst;
+}
 
 adg_status bfail(adg_batch *b, adg_status code, const std::string &m) {
   if (b) b->msg = m;
@@ -149,14 +152,6 @@ void heap_give(adg_batch *b, size_t off, size_t bytes) {
   }
 }
 
-long long slot_tiles(const Slot &s) {
-  const Layout &L = s.P.lay;
-  if (s.P.phys.model == ADG_DETAILED) return (L.E + kNsTile - 1) / kNsTile;
-  long long t = euler_batch_blocks(0, L.E);
-  if (s.P.disc.limiter) t += euler_batch_blocks(1, L.E) + euler_batch_blocks(2, L.E);
-  return t;
-}
-
 // Work list: detailed instances first (one group), then one-step instances by
 // (kind, order, flux).  Entries of one instance are consecutive.
 void rebuild_tiles(adg_batch *b) {
@@ -168,7 +163,7 @@ void rebuild_tiles(adg_batch *b) {
       const Slot &s = b->slots[i];
       if (!s.used || !pick(s)) continue;
       const int nb = nblocks(s);
-      for (int k = 0; k < nb; ++k) b->h_tiles.push_back(make_int2(i, k * (kind == 0 ? kNsTile : 1)));
+      for (int k = 0; k < nb; ++k) b->h_tiles.push_back(make_int2(i, k * (kind == 0 ? b->tile_elems : 1)));
     }
     g.n = (int)b->h_tiles.size() - g.off;
     // XCD-aware order: workgroup p of the launch takes work item xcd_item(p, n), so each XCD
@@ -178,7 +173,7 @@ void rebuild_tiles(adg_batch *b) {
     if (g.n > 0) b->groups.push_back(g);
   };
   add_group(0, 0, 0, [](const Slot &s) { return s.P.phys.model == ADG_DETAILED; },
-            [](const Slot &s) { return (s.P.lay.E + kNsTile - 1) / kNsTile; });
+            [&](const Slot &s) { return (s.P.lay.E + b->tile_elems - 1) / b->tile_elems; });
   if (!b->groups.empty() && b->groups[0].kind == 0) {
     int mm = 2;
     for (const Slot &s : b->slots)
@@ -205,7 +200,8 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
         BHIP(b, hipEventRecord(e0, st));
       }
       if (g.kind == 0) {
-        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->precision == ADG_MIXED_FP32, g.M, st));
+        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->precision == ADG_MIXED_FP32, g.M,
+                                b->tile_elems, st));
       } else {
         BHIP(b, launch_euler_batch(g.kind - 1, g.M, g.flux, b->d_eu, b->d_tiles + g.off, g.n, stage, st));
       }
@@ -528,6 +524,47 @@ adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int6
     launches_out[c] = cnt[c];
   }
   return ADG_OK;
+}
+
+adg_status adg_batch_autotune(adg_batch *b, int32_t n_reps, int32_t *choice) {
+  if (!b || n_reps < 1) return ADG_ERR_ARG;
+  static const int kTiles[2] = {8, 4};
+  double best_ms = 0.0;
+  int best = 0;
+  bool any = false;
+  for (int c = 0; c < 2; ++c) {
+    b->tile_elems = kTiles[c];
+    b->dirty = true;
+    adg_status rc = prepare(b);
+    if (rc != ADG_OK) return rc;
+    const Group *g = nullptr;
+    for (const Group &x : b->groups)
+      if (x.kind == 0) g = &x;
+    if (!g) break;   // no detailed-chemistry instance: nothing to choose
+    any = true;
+    // stage-0 launches only: they read w^n and write the first stage buffer and the
+    // level's stage-0 history, which the next step recomputes; the state is untouched
+    hipEvent_t e0, e1;
+    BHIP(b, hipEventCreate(&e0));
+    BHIP(b, hipEventCreate(&e1));
+    BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->precision == ADG_MIXED_FP32, g->M,
+                            b->tile_elems, b->stream));   // warm-up
+    BHIP(b, hipEventRecord(e0, b->stream));
+    for (int r = 0; r < n_reps; ++r)
+      BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->precision == ADG_MIXED_FP32, g->M,
+                              b->tile_elems, b->stream));
+    BHIP(b, hipEventRecord(e1, b->stream));
+    BHIP(b, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (c == 0 || ms < best_ms) { best_ms = ms; best = c; }
+  }
+  b->tile_elems = kTiles[any ? best : 0];
+  b->dirty = true;
+  if (choice) *choice = any ? best : 0;
+  return prepare(b);
 }
 
 int32_t adg_batch_active(const adg_batch *b) { return b ? b->active : -1; }

@@ -1,7 +1,7 @@
 // Fused SSP-RK3 stage kernel for the detailed-chemistry Navier-Stokes model
 // (Sec. 2 Eq. (1)-(3), Sec. 3.1 LDG form of Eq. (5), Sec. 3.2 AT fluxes).
 //
-// One workgroup per tile of kTile elements, periodic domain.  The tile and a
+// One workgroup per tile of TE elements (4 or 8), periodic domain.  The tile and a
 // halo of two elements on each side are staged in LDS; every later phase reads
 // LDS only:
 //   1. face traces of w for the tile and halo;
@@ -25,7 +25,6 @@
 
 namespace adg {
 
-constexpr int kTile = kNsTile;
 constexpr int kThreadsBatch = 256;   // batched kernel: more resident workgroups per CU
 constexpr int kThreadsSingle = 512;  // one problem: more lanes per tile, shorter phases
 
@@ -59,9 +58,9 @@ __device__ __forceinline__ bool newton_T(const double (&c)[6], double T0, double
 }
 
 // LDS arena of one tile.
-template <int M, int NS>
+template <int M, int NS, int TE>
 struct NsLds {
-  static constexpr int V = 3 + NS, Q = M, TE = kTile;
+  static constexpr int V = 3 + NS, Q = M;
   static constexpr int NH = TE + 4;   // tile + 2 halo elements per side; local l <-> element e0 - 2 + l
   static constexpr int NF = TE + 3;   // faces e0-1 .. e0+TE+1; local fl <-> face e0 - 1 + fl
   static constexpr int NQ = TE + 2;   // gradients of elements e0-1 .. e0+TE; local lq <-> element e0 - 1 + lq
@@ -107,14 +106,14 @@ struct NsLds {
 // the magnitude of the state (pressure-sized fluxes would otherwise lose about
 // 4 digits of their element-to-element differences).  Gradients at nodes and
 // traces are likewise mode 0 plus the FP32 sum of the higher modes.
-template <int M, int NS, typename OpT, int NTH>
+template <int M, int NS, typename OpT, int NTH, int TE>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
                                         double *wout, int stage, int advance, int e0, int ntiles,
-                                        NsLds<M, NS> &Ls, NsMech &smech) {
-  constexpr int V = 3 + NS, Q = M, TE = kTile;
-  constexpr int NH = NsLds<M, NS>::NH, NF = NsLds<M, NS>::NF, NQ = NsLds<M, NS>::NQ, NN = NsLds<M, NS>::NN;
+                                        NsLds<M, NS, TE> &Ls, NsMech &smech) {
+  constexpr int V = 3 + NS, Q = M;
+  using Lds = NsLds<M, NS, TE>;
+  constexpr int NH = Lds::NH, NF = Lds::NF, NQ = Lds::NQ, NN = Lds::NN;
   constexpr int NT = 2 * (TE + 1);  // face traces; trace pp <-> face e0 + pp/2, side pp%2
-  static_assert(NN <= 64 && NT <= 64, "node and trace lanes each fit one wavefront");
   auto &sW = Ls.sW;
   auto &sTm = Ls.sTm;
   auto &sTp = Ls.sTp;
@@ -140,7 +139,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   auto &sD = Ls.sD;
   auto &sI = Ls.sI;
   auto &sK = Ls.sK;
-  constexpr int NP = NsLds<M, NS>::NP;
+  constexpr int NP = Lds::NP;
   constexpr bool kMixed = !std::is_same<OpT, double>::value;
 
   const int t = threadIdx.x;
@@ -295,8 +294,9 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   //    pressure, sound speed and viscosity are evaluated on every lane of the group alike.
   //    At the nodes the lanes also form the Gibbs energies and concentrations of their species.
   {
-    constexpr int LP = NTH / 64;                 // lanes per point: 64 point slots per workgroup
-    static_assert(NP <= NTH / LP, "every point has a lane group");
+    constexpr int kSlots = NP <= 32 ? 32 : 64;   // point slots per workgroup
+    constexpr int LP = NTH / kSlots;             // lanes per point
+    static_assert(LP >= 1 && LP <= 64 && (LP & (LP - 1)) == 0 && NP <= NTH / LP, "every point has a lane group");
     constexpr int NO = (NS + LP - 1) / LP;
     const int k = t % LP;
     const int p = min(t / LP, NP - 1);          // spare groups redo the last point and write nothing
@@ -564,48 +564,48 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   if (advance) finish_step(a.step, a.done, ntiles);
 }
 
-template <int M, int NS>
-__global__ __launch_bounds__(kThreadsSingle) void ns_stage_kernel(NsArgs a) {
-  __shared__ NsLds<M, NS> L;
+template <int M, int NS, int TE, int NTH>
+__global__ __launch_bounds__(NTH) void ns_stage_kernel(NsArgs a) {
+  __shared__ NsLds<M, NS, TE> L;
   __shared__ NsMech smech;
-  ns_tile<M, NS, double, kThreadsSingle>(a, a.ws, a.w0, a.wout, a.stage, a.advance, xcd_item(blockIdx.x, gridDim.x) * kTile,
-                         gridDim.x, L, smech);
+  ns_tile<M, NS, double, NTH, TE>(a, a.ws, a.w0, a.wout, a.stage, a.advance, xcd_item(blockIdx.x, gridDim.x) * TE,
+                                  gridDim.x, L, smech);
 }
 
 // LDS of the batched kernel: room for the largest order it serves.
-template <int MMAX>
+template <int MMAX, int TE>
 union NsBatchLds;
-template <>
-union NsBatchLds<2> {
-  NsLds<2, kNsMaxSpecies> m2;
+template <int TE>
+union NsBatchLds<2, TE> {
+  NsLds<2, kNsMaxSpecies, TE> m2;
 };
-template <>
-union NsBatchLds<3> {
-  NsLds<2, kNsMaxSpecies> m2;
-  NsLds<3, kNsMaxSpecies> m3;
+template <int TE>
+union NsBatchLds<3, TE> {
+  NsLds<2, kNsMaxSpecies, TE> m2;
+  NsLds<3, kNsMaxSpecies, TE> m3;
 };
-template <>
-union NsBatchLds<4> {
-  NsLds<2, kNsMaxSpecies> m2;
-  NsLds<3, kNsMaxSpecies> m3;
-  NsLds<4, kNsMaxSpecies> m4;
+template <int TE>
+union NsBatchLds<4, TE> {
+  NsLds<2, kNsMaxSpecies, TE> m2;
+  NsLds<3, kNsMaxSpecies, TE> m3;
+  NsLds<4, kNsMaxSpecies, TE> m4;
 };
-template <>
-union NsBatchLds<5> {
-  NsLds<2, kNsMaxSpecies> m2;
-  NsLds<3, kNsMaxSpecies> m3;
-  NsLds<4, kNsMaxSpecies> m4;
-  NsLds<5, kNsMaxSpecies> m5;
+template <int TE>
+union NsBatchLds<5, TE> {
+  NsLds<2, kNsMaxSpecies, TE> m2;
+  NsLds<3, kNsMaxSpecies, TE> m3;
+  NsLds<4, kNsMaxSpecies, TE> m4;
+  NsLds<5, kNsMaxSpecies, TE> m5;
 };
 
 // Batched stage kernel: one workgroup per (instance, tile) entry of the work
 // list; instances differ in size, order (up to MMAX modes), PE layout and
 // delays.  Sizing the LDS for the largest order present keeps more workgroups
 // resident when the batch holds only low orders.
-template <typename OpT, int MMAX>
+template <typename OpT, int MMAX, int TE>
 __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *__restrict__ insts,
                                                             const int2 *__restrict__ tiles, int stage) {
-  __shared__ NsBatchLds<MMAX> L;
+  __shared__ NsBatchLds<MMAX, TE> L;
   __shared__ NsMech smech;
   const int2 tl = tiles[blockIdx.x];
   const NsArgs &a = insts[tl.x];
@@ -614,18 +614,18 @@ __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *_
   const double *ws = a.W[in_buf];
   const double *w0 = a.W[0];
   double *wout = a.W[out_buf];
-  const int ntiles = (a.E + kTile - 1) / kTile;
+  const int ntiles = (a.E + TE - 1) / TE;
   const int M = a.M;
   if (M == 2) {
-    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech);
+    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech);
   } else if constexpr (MMAX >= 3) {
     if (M == 3) {
-      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech);
+      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech);
     } else if constexpr (MMAX >= 4) {
       if (M == 4) {
-        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech);
+        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech);
       } else if constexpr (MMAX >= 5) {
-        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech);
+        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech);
       }
     }
   }
@@ -729,38 +729,54 @@ adg_status ns_build_mech(const adg_physics *ph, NsMech &hm) {
   return ADG_OK;
 }
 
-template <int M>
-static hipError_t ns_M(const NsArgs &a, hipStream_t s) {
-  const int blocks = (a.E + kTile - 1) / kTile;
-  hipLaunchKernelGGL((ns_stage_kernel<M, kNsMaxSpecies>), dim3(blocks), dim3(kThreadsSingle), 0, s, a);
+template <int M, int TE, int NTH>
+static hipError_t ns_launch(const NsArgs &a, hipStream_t s) {
+  const int blocks = (a.E + TE - 1) / TE;
+  hipLaunchKernelGGL((ns_stage_kernel<M, kNsMaxSpecies, TE, NTH>), dim3(blocks), dim3(NTH), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename OpT>
+template <int M>
+static hipError_t ns_M(int cfg, const NsArgs &a, hipStream_t s) {
+  switch (cfg) {
+    case 0: return ns_launch<M, 8, 512>(a, s);
+    case 1: return ns_launch<M, 8, 256>(a, s);
+    case 2: return ns_launch<M, 4, 256>(a, s);
+    case 3: return ns_launch<M, 4, 512>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename OpT, int TE>
 static void batch_launch(int max_m, const NsArgs *insts, const int2 *tiles, int ntiles, int stage, hipStream_t s) {
   switch (max_m) {
-    case 2: hipLaunchKernelGGL((ns_batch_kernel<OpT, 2>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
-    case 3: hipLaunchKernelGGL((ns_batch_kernel<OpT, 3>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
-    case 4: hipLaunchKernelGGL((ns_batch_kernel<OpT, 4>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
-    default: hipLaunchKernelGGL((ns_batch_kernel<OpT, 5>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    case 2: hipLaunchKernelGGL((ns_batch_kernel<OpT, 2, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    case 3: hipLaunchKernelGGL((ns_batch_kernel<OpT, 3, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    case 4: hipLaunchKernelGGL((ns_batch_kernel<OpT, 4, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    default: hipLaunchKernelGGL((ns_batch_kernel<OpT, 5, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
   }
 }
 
 hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, int max_m,
-                           hipStream_t s) {
+                           int tile_elems, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (max_m < 2 || max_m > kMaxM) return hipErrorInvalidValue;
-  if (mixed) batch_launch<float>(max_m, insts, tiles, ntiles, stage, s);
-  else batch_launch<double>(max_m, insts, tiles, ntiles, stage, s);
+  if (max_m < 2 || max_m > kMaxM || (tile_elems != 4 && tile_elems != 8)) return hipErrorInvalidValue;
+  if (tile_elems == 8) {
+    if (mixed) batch_launch<float, 8>(max_m, insts, tiles, ntiles, stage, s);
+    else batch_launch<double, 8>(max_m, insts, tiles, ntiles, stage, s);
+  } else {
+    if (mixed) batch_launch<float, 4>(max_m, insts, tiles, ntiles, stage, s);
+    else batch_launch<double, 4>(max_m, insts, tiles, ntiles, stage, s);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_ns_stage(int M, const NsArgs &a, hipStream_t s) {
+hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, hipStream_t s) {
   switch (M) {
-    case 2: return ns_M<2>(a, s);
-    case 3: return ns_M<3>(a, s);
-    case 4: return ns_M<4>(a, s);
-    case 5: return ns_M<5>(a, s);
+    case 2: return ns_M<2>(cfg, a, s);
+    case 3: return ns_M<3>(cfg, a, s);
+    case 4: return ns_M<4>(cfg, a, s);
+    case 5: return ns_M<5>(cfg, a, s);
   }
   return hipErrorInvalidValue;
 }

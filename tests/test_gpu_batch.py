@@ -256,3 +256,21 @@ def test_batched_ignition_full_size_sampled(adg, orc):
               flush=True)
         assert err < 1e-6
     b.close()
+
+
+def test_batch_autotune_keeps_the_state(adg, orc, mech):
+    cases = mixed_cases(mech)[:4]
+    b = make_batch(adg, cases)
+    slots = [b.add(c, w) for c, w in cases]
+    b.step(2)
+    before = [b.state(sl) for sl in slots]
+    choice = b.autotune(2)
+    assert choice in (0, 1)
+    for sl, w in zip(slots, before):
+        np.testing.assert_array_equal(b.state(sl), w)
+    b.step(4)
+    for (c, w), sl in zip(cases, slots):
+        o = orc.OracleSolver(c, w, 8)
+        o.step(6)
+        assert float(np.max(var_errors(b.state(sl), o.state()))) < 1e-10
+    b.close()

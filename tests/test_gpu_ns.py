@@ -138,3 +138,23 @@ def test_conservation_on_gpu(adg, mech):
         tot = lambda ww: np.sum(ww[:, 3:, 0] / mech["W"] * comp[:, el])
         assert abs(tot(w) - tot(w0)) <= 1e-12 * abs(tot(w0))
     np.testing.assert_allclose(w[:, 3:, :].sum(1), w[:, 0, :], rtol=0, atol=1e-13 * np.abs(w[:, 0, 0]).max())
+
+
+def test_autotune_keeps_the_state_and_parity(adg, orc, mech):
+    """The autotuner times first-stage launches of every candidate decomposition on the live
+    state: the state is unchanged, and the chosen kernel still matches the oracle."""
+    case, w0 = gen.case_c1(E=96, n_pe=6, mech=mech, Lx=0.01 * 96 / 2048)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(3)
+    before = s.state()
+    choice = s.autotune(3)
+    print(f"[autotune] choice {choice}", flush=True)
+    assert 0 <= choice < 4
+    np.testing.assert_array_equal(s.state(), before)
+    o = orc.OracleSolver(case, w0, 20)
+    o.step(3)
+    s.step(9)
+    o.step(9)
+    assert rel_per_var(s.state(), o.state()) < 1e-10
+    s.close()
