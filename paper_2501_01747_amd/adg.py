@@ -23,8 +23,8 @@ SYNC, CAA, SAA, SCHEDULE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FP64, MIXED_FP32 = 0, 1
 KXRCF, MINMOD = 0, 1
-PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter")
-BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage", "limiter", "limiter_scatter")
+PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter", "weno")
+BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage", "limiter", "weno", "limiter_scatter")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")

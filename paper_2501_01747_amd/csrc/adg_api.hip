@@ -75,6 +75,9 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
         if (timer) timer(s, 1, true);
         HIP_TRY(s, launch_limiter(M, l, st));
         if (timer) timer(s, 1, false);
+        if (timer) timer(s, 3, true);
+        HIP_TRY(s, launch_weno(M, l, st));
+        if (timer) timer(s, 3, false);
         l.advance = stage == 2;
         if (timer) timer(s, 2, true);
         HIP_TRY(s, launch_limiter_scatter(M, l, st));
@@ -251,7 +254,11 @@ adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *
   std::vector<int> order;
   for (int stage = 0; stage < 3; ++stage) {
     order.push_back(0);
-    if (s->P.phys.model == ADG_ONESTEP && s->P.disc.limiter) { order.push_back(1); order.push_back(2); }
+    if (s->P.phys.model == ADG_ONESTEP && s->P.disc.limiter) {
+      order.push_back(1);
+      order.push_back(3);
+      order.push_back(2);
+    }
   }
   HIP_TRY(s, hipStreamSynchronize(s->stream));
   std::vector<double> sum(n_classes, 0.0);

@@ -43,12 +43,11 @@ struct Slot {
 constexpr int kBatchMechs = 16;
 
 struct Group {
-  int kind;  // 0 detailed stage, 1 one-step stage, 2 limiter, 3 scatter
+  int kind;  // 0 detailed stage, 1 one-step stage, 2 indicator, 3 WENO, 4 scatter
   int M, flux;
   int off, n;  // range of the work list
 };
 
-constexpr int kProfileClasses = 4;
 
 }  // namespace
 
@@ -180,7 +179,7 @@ void rebuild_tiles(adg_batch *b) {
       if (s.used && s.P.phys.model == ADG_DETAILED) mm = std::max(mm, s.P.lay.M);
     b->groups[0].M = mm;
   }
-  for (int kind = 1; kind <= 3; ++kind)
+  for (int kind = 1; kind <= 4; ++kind)
     for (int M = 2; M <= kMaxM; ++M)
       for (int flux = 0; flux <= (kind == 1 ? 1 : 0); ++flux)
         add_group(kind, M, flux,

@@ -1,5 +1,7 @@
 // Fused SSP-RK3 stage kernel for the one-step reactive Euler model and the
-// KXRCF + characteristic (AT-)WENO limiter.
+// troubled-cell indicator + characteristic (AT-)WENO limiter (three passes:
+// indicator over every element, WENO over the list of troubled elements,
+// write-back of the limited values).
 //
 // Stage kernel (Sec. 3.1 Eq. (5), Sec. 3.2 Eq. (7)): one thread per element;
 // each wavefront owns 62 consecutive elements and holds their two neighbours.
@@ -211,15 +213,21 @@ __global__ __launch_bounds__(kEulerBlock) void euler_batch_kernel(const EulerSet
 
 // ------------------------------------------------------------------- limiter
 
-// Characteristic left eigenvectors at the mean state (one-step model) and
-// R = L^-1 by Gauss-Jordan with partial pivoting.  Rows of L:
+// Characteristic left and right eigenvectors at the mean state (one-step model).
+// Rows of L (linear forms in the conserved variables):
 //   (dp - rho a du)/(2a^2), drho - dp/a^2, d(rho Y_R) - Y_R drho,
-//   d(rho Y_R + rho Y_P - rho), (dp + rho a du)/(2a^2).
+//   d(rho Y_R + rho Y_P - rho), (dp + rho a du)/(2a^2),
+// with dp and du the differentials of p and u.  R = L^-1 in closed form: column k
+// is the conserved perturbation whose characteristic variables are e_k, built from
+// the primitive perturbations (drho, du, dp, dY_R) that L maps to e_k.  L involves
+// Y_R only, so the product entry of the columns with drho = 1 is 1 - Y_R (not the
+// mean state's Y_P): R is then the exact inverse for any state, and the limiter
+// keeps rho Y_R + rho Y_P - rho at round-off instead of feeding its round-off back.
 __device__ bool char_matrices(const OneStep &ph, const double *wb, double (&Lm)[5][5], double (&Rm)[5][5]) {
   Prim1 pr;
-  bool ok = prim1(ph, wb, pr);
-  const double rho = pr.rho, u = pr.u, a = pr.a, g1 = ph.gamma - 1.0;
-  const double dp[5] = {g1 * 0.5 * u * u, -g1 * u, g1, -g1 * ph.q_heat, 0.0};
+  const bool ok = prim1(ph, wb, pr);
+  const double rho = pr.rho, u = pr.u, a = pr.a, g1 = ph.gamma - 1.0, q = ph.q_heat;
+  const double dp[5] = {g1 * 0.5 * u * u, -g1 * u, g1, -g1 * q, 0.0};
   const double du[5] = {-u / rho, 1.0 / rho, 0.0, 0.0, 0.0};
   const double a2 = a * a;
 #pragma unroll
@@ -229,37 +237,23 @@ __device__ bool char_matrices(const OneStep &ph, const double *wb, double (&Lm)[
     Lm[1][c] = drho - dp[c] / a2;
     Lm[4][c] = (dp[c] + rho * a * du[c]) / (2.0 * a2);
   }
-  const double Y0 = wb[3] / rho;
-  Lm[2][0] = -Y0; Lm[2][1] = 0.0; Lm[2][2] = 0.0; Lm[2][3] = 1.0; Lm[2][4] = 0.0;
+  const double YR = wb[3] / rho, YP = 1.0 - YR;
+  Lm[2][0] = -YR; Lm[2][1] = 0.0; Lm[2][2] = 0.0; Lm[2][3] = 1.0; Lm[2][4] = 0.0;
   Lm[3][0] = -1.0; Lm[3][1] = 0.0; Lm[3][2] = 0.0; Lm[3][3] = 1.0; Lm[3][4] = 1.0;
-  double A[5][5];
+  // columns: acoustic -, entropy, reactant, species sum, acoustic +
+  const double hk = 0.5 * u * u + q * YR;   // d(rho E)/d rho at fixed u, p, Y
+  const double ha = a2 / g1;
+  const double col[5][5] = {
+      {1.0, u - a, ha + hk - u * a, YR, YP},
+      {1.0, u, hk, YR, YP},
+      {0.0, 0.0, q, 1.0, -1.0},
+      {0.0, 0.0, 0.0, 0.0, 1.0},
+      {1.0, u + a, ha + hk + u * a, YR, YP}};
 #pragma unroll
-  for (int r = 0; r < 5; ++r)
+  for (int k = 0; k < 5; ++k)
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      A[r][c] = Lm[r][c];
-      Rm[r][c] = r == c ? 1.0 : 0.0;
-    }
-  for (int col = 0; col < 5; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < 5; ++r)
-      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
-    if (A[piv][col] == 0.0) return false;
-    if (piv != col)
-      for (int c = 0; c < 5; ++c) {
-        double x = A[col][c]; A[col][c] = A[piv][c]; A[piv][c] = x;
-        x = Rm[col][c]; Rm[col][c] = Rm[piv][c]; Rm[piv][c] = x;
-      }
-    const double p = A[col][col];
-    for (int c = 0; c < 5; ++c) { A[col][c] /= p; Rm[col][c] /= p; }
-    for (int r = 0; r < 5; ++r) {
-      if (r == col) continue;
-      const double f = A[r][col];
-      if (f == 0.0) continue;
-      for (int c = 0; c < 5; ++c) { A[r][c] -= f * A[col][c]; Rm[r][c] -= f * Rm[col][c]; }
-    }
-  }
-  return ok;
+    for (int r = 0; r < 5; ++r) Rm[r][k] = col[k][r];
+  return ok && a > 0.0;
 }
 
 // Modal data of a neighbour: loaded from the unlimited stage output, the
@@ -315,18 +309,21 @@ __device__ __forceinline__ double trace_at(const double (&c)[M], int side) {
   return s;
 }
 
+// Neighbour data of element e for the limiter: its two neighbours' modes (Eq. (11)
+// data across delayed PE faces, the constant ghost at transmissive ends).
 template <int M>
-__device__ __forceinline__ void limiter_body(const LimiterArgs &a, int blk) {
-  const int e = blk * kLimBlock + threadIdx.x;
-  if (e >= a.E) return;
-  const long long n = *a.step;
-  double u[5][M];
+__device__ __forceinline__ void limiter_stencil(const LimiterArgs &a, long long n, int e, double (&u)[5][M],
+                                                double (&nbL)[5][M], double (&nbR)[5][M]) {
   load_elem<M>(a.w, a.E, e, u);
-  double nbL[5][M], nbR[5][M];
   neighbour_modes<M>(a, n, e, 0, u, nbL);
   neighbour_modes<M>(a, n, e, 1, u, nbR);
-  const bool ghostL = !a.periodic && e == 0, ghostR = !a.periodic && e == a.E - 1;
+}
 
+// Troubled-cell indicator of element e (KXRCF or TVB minmod).
+template <int M>
+__device__ __forceinline__ bool troubled(const LimiterArgs &a, int e, const double (&u)[5][M],
+                                         const double (&nbL)[5][M], const double (&nbR)[5][M]) {
+  const bool ghostL = !a.periodic && e == 0, ghostR = !a.periodic && e == a.E - 1;
   bool flag = false;
   if (a.indicator == 1) {
     // TVB minmod: the face deviations from the mean against the mean differences, every
@@ -368,10 +365,31 @@ __device__ __forceinline__ void limiter_body(const LimiterArgs &a, int blk) {
     if (fabs(jump) / (a.kx_h * norm) > 1.0) flag = true;
   }
   }
-  a.flags[e] = flag ? 1 : 0;
-  if (!flag) return;
-  atomicAdd(a.flag_count, 1ull);
+  return flag;
+}
 
+// Pass 1 of the limiter, every element: the indicator; troubled elements are
+// appended to the stage's list (their order does not matter: each is limited on
+// its own in pass 2).
+template <int M>
+__device__ __forceinline__ void indicator_body(const LimiterArgs &a, int blk) {
+  const int e = blk * kLimBlock + threadIdx.x;
+  if (e >= a.E) return;
+  const long long n = *a.step;
+  double u[5][M], nbL[5][M], nbR[5][M];
+  limiter_stencil<M>(a, n, e, u, nbL, nbR);
+  const bool flag = troubled<M>(a, e, u, nbL, nbR);
+  a.flags[e] = flag ? 1 : 0;
+  if (flag) {
+    atomicAdd(a.flag_count, 1ull);
+    a.tlist[atomicAdd(a.tcount + a.stage, 1u)] = e;
+  }
+}
+
+// Characteristic WENO of Eq. (9)-(10) for a troubled element, into the side buffer.
+template <int M>
+__device__ __forceinline__ void weno_cell(const LimiterArgs &a, int e, const double (&u)[5][M],
+                                          const double (&nbL)[5][M], const double (&nbR)[5][M]) {
   double wb[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) wb[v] = u[v][0];
@@ -382,6 +400,7 @@ __device__ __forceinline__ void limiter_body(const LimiterArgs &a, int blk) {
   for (int v = 0; v < 5; ++v)
 #pragma unroll
     for (int j = 0; j < M; ++j) wl[v][j] = 0.0;
+#pragma unroll
   for (int c = 0; c < 5; ++c) {
     double vc[M], vL[M], vR[M];
 #pragma unroll
@@ -439,9 +458,24 @@ __device__ __forceinline__ void limiter_body(const LimiterArgs &a, int blk) {
     for (int j = 0; j < M; ++j) a.wlim[sidx(e, v * M + j, 5 * M)] = wl[v][j];
 }
 
+
+// Pass 2, the listed elements only (grid-stride over the list).
+template <int M>
+__device__ __forceinline__ void weno_body(const LimiterArgs &a, int blk, int nblk) {
+  const unsigned cnt = a.tcount[a.stage];
+  if ((unsigned)(blk * kWenoBlock) >= cnt) return;
+  const long long n = *a.step;
+  for (unsigned idx = blk * kWenoBlock + threadIdx.x; idx < cnt; idx += nblk * kWenoBlock) {
+    const int e = a.tlist[idx];
+    double u[5][M], nbL[5][M], nbR[5][M];
+    limiter_stencil<M>(a, n, e, u, nbL, nbR);
+    weno_cell<M>(a, e, u, nbL, nbR);
+  }
+}
+
 template <int M>
 __global__ __launch_bounds__(kLimBlock) void limiter_kernel(LimiterArgs a) {
-  limiter_body<M>(a, blockIdx.x);
+  indicator_body<M>(a, blockIdx.x);
 }
 
 template <int M>
@@ -450,23 +484,40 @@ __global__ __launch_bounds__(kLimBlock) void limiter_batch_kernel(const EulerSet
   const int2 tl = tiles[blockIdx.x];
   const LimiterArgs &a = sets[tl.x].lim[stage];
   if (*a.step >= a.target) return;
-  limiter_body<M>(a, tl.y);
+  indicator_body<M>(a, tl.y);
 }
 
-// Writes the limited values of troubled cells back (after every stencil has read
-// the unlimited data).
+template <int M>
+__global__ __launch_bounds__(kWenoBlock) void weno_kernel(LimiterArgs a) {
+  weno_body<M>(a, blockIdx.x, gridDim.x);
+}
+
+template <int M>
+__global__ __launch_bounds__(kWenoBlock) void weno_batch_kernel(const EulerSet *__restrict__ sets,
+                                                                const int2 *__restrict__ tiles, int stage) {
+  const int2 tl = tiles[blockIdx.x];
+  const LimiterArgs &a = sets[tl.x].lim[stage];
+  if (*a.step >= a.target) return;
+  weno_body<M>(a, tl.y, weno_blocks(a.E));
+}
+
+// Pass 3, after every stencil has read the unlimited data: the limited values of
+// the listed elements replace the unlimited ones.  The next stage's list starts
+// empty; the last kernel of a step advances the step counter.
 template <int M>
 __device__ __forceinline__ void scatter_body(const LimiterArgs &a, int blk, int nblk) {
-  const int e = blk * kScatterBlock + threadIdx.x;
-  if (e < a.E && a.flags[e]) {
+  const unsigned cnt = a.tcount[a.stage];
+  for (unsigned idx = blk * kScatterBlock + threadIdx.x; idx < cnt; idx += nblk * kScatterBlock) {
+    const int e = a.tlist[idx];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const size_t idx = sidx(e, v * M + j, 5 * M);
-        a.w[idx] = a.wlim[idx];
+        const size_t gi = sidx(e, v * M + j, 5 * M);
+        a.w[gi] = a.wlim[gi];
       }
   }
+  if (blk == 0 && threadIdx.x == 0) a.tcount[a.stage == 2 ? 0 : a.stage + 1] = 0u;
   if (a.advance) finish_step(a.step, a.done, nblk);
 }
 
@@ -481,7 +532,7 @@ __global__ __launch_bounds__(kScatterBlock) void scatter_batch_kernel(const Eule
   const int2 tl = tiles[blockIdx.x];
   const LimiterArgs &a = sets[tl.x].lim[stage];
   if (*a.step >= a.target) return;
-  scatter_body<M>(a, tl.y, (a.E + kScatterBlock - 1) / kScatterBlock);
+  scatter_body<M>(a, tl.y, scatter_blocks(a.E));
 }
 
 // caller layout [E][VM] <-> device layout (sidx)
@@ -530,8 +581,20 @@ hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_weno(int M, const LimiterArgs &a, hipStream_t s) {
+  const int blocks = weno_blocks(a.E);
+  switch (M) {
+    case 2: hipLaunchKernelGGL(weno_kernel<2>, dim3(blocks), dim3(kWenoBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(weno_kernel<3>, dim3(blocks), dim3(kWenoBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(weno_kernel<4>, dim3(blocks), dim3(kWenoBlock), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(weno_kernel<5>, dim3(blocks), dim3(kWenoBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s) {
-  const int blocks = (a.E + kScatterBlock - 1) / kScatterBlock;
+  const int blocks = scatter_blocks(a.E);
   switch (M) {
     case 2: hipLaunchKernelGGL(limiter_scatter_kernel<2>, dim3(blocks), dim3(kScatterBlock), 0, s, a); break;
     case 3: hipLaunchKernelGGL(limiter_scatter_kernel<3>, dim3(blocks), dim3(kScatterBlock), 0, s, a); break;
@@ -545,7 +608,8 @@ hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s) {
 int euler_batch_blocks(int kind, int E) {
   if (kind == 0) return euler_blocks(E);
   if (kind == 1) return (E + kLimBlock - 1) / kLimBlock;
-  return (E + kScatterBlock - 1) / kScatterBlock;
+  if (kind == 2) return weno_blocks(E);
+  return scatter_blocks(E);
 }
 
 template <int M>
@@ -558,6 +622,8 @@ static hipError_t batch_M(int kind, int flux, const EulerSet *sets, const int2 *
       hipLaunchKernelGGL((euler_batch_kernel<M, 0>), dim3(ntiles), dim3(kEulerBlock), 0, s, sets, tiles, stage);
   } else if (kind == 1) {
     hipLaunchKernelGGL(limiter_batch_kernel<M>, dim3(ntiles), dim3(kLimBlock), 0, s, sets, tiles, stage);
+  } else if (kind == 2) {
+    hipLaunchKernelGGL(weno_batch_kernel<M>, dim3(ntiles), dim3(kWenoBlock), 0, s, sets, tiles, stage);
   } else {
     hipLaunchKernelGGL(scatter_batch_kernel<M>, dim3(ntiles), dim3(kScatterBlock), 0, s, sets, tiles, stage);
   }

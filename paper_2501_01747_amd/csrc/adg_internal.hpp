@@ -92,6 +92,8 @@ struct LimiterArgs {
   double *w;            // unlimited stage output, limited in place by the scatter pass
   double *wlim;         // limited values of troubled cells
   int8_t *flags;        // [E]
+  int *tlist;           // [E] troubled elements of the current stage, in any order
+  unsigned *tcount;     // [3] list lengths, one per RK stage
   unsigned long long *flag_count;
   const int *face_if;
   long long *step;
@@ -131,7 +133,18 @@ __host__ __device__ inline int xcd_item(int b, int n) {
 enum ErrBits { kErrState = 1, kErrNewton = 2 };
 
 constexpr int kLimBlock = 128;
+constexpr int kWenoBlock = 64;
 constexpr int kScatterBlock = 256;
+// Workgroups of the WENO and scatter passes, which walk the list of troubled
+// elements with a grid stride.
+__host__ __device__ inline int weno_blocks(int E) {
+  const int b = (E + kWenoBlock - 1) / kWenoBlock;
+  return b < 256 ? b : 256;
+}
+__host__ __device__ inline int scatter_blocks(int E) {
+  const int b = (E + kScatterBlock - 1) / kScatterBlock;
+  return b < 128 ? b : 128;
+}
 
 // Argument blocks of one instance of the one-step model in a batch, per stage.
 struct EulerSet {
@@ -142,9 +155,11 @@ struct EulerSet {
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, hipStream_t s);
 hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s);
+hipError_t launch_weno(int M, const LimiterArgs &a, hipStream_t s);
 hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s);
 // Batched one-step launches over a work list of (instance, block) entries, all of
-// order M: kind 0 stage kernel (flux selects Rusanov/HLLC), 1 limiter, 2 scatter.
+// order M: kind 0 stage kernel (flux selects Rusanov/HLLC), 1 indicator, 2 WENO of
+// the troubled elements, 3 scatter.
 hipError_t launch_euler_batch(int kind, int M, int flux, const EulerSet *sets, const int2 *tiles, int ntiles,
                               int stage, hipStream_t s);
 // Workgroups per instance of E elements for each kind.

@@ -171,6 +171,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   L.state = off;  off += 3 * align256(nstate);
   L.wlim = off;   off += d->limiter ? align256(nstate) : 0;
   L.flags = off;  off += align256((size_t)L.E);
+  L.tlist = off;  off += d->limiter ? align256(sizeof(int) * (size_t)L.E) : 0;
   L.face_if = off; off += align256(sizeof(int) * (L.E + 1));
   L.counters = off; off += 256;
   L.ring = off;   off += align256(sizeof(double) * (size_t)L.D * 3 * (L.nif > 0 ? L.nif : 1) * L.rec);
@@ -267,6 +268,8 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
       l.wlim = P.Wlim;
       l.flags = P.flags;
       l.flag_count = P.flag_count;
+      l.tlist = (int *)(base + L.tlist);
+      l.tcount = (unsigned *)(base + L.counters + 224);
       l.face_if = P.face_if;
       l.step = P.step;
       l.done = P.done;

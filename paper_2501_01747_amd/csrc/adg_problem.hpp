@@ -17,7 +17,7 @@ constexpr long long kNoTarget = 0x7fffffffffffffffLL;
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t state, wlim, flags, face_if, counters, ring, sched, mech, total;
+  size_t state, wlim, flags, tlist, face_if, counters, ring, sched, mech, total;
   int nif, nfaces, D, rec, q, V, M, E;
   int off_F, off_Wc, off_U;
 };
