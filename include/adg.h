@@ -56,6 +56,7 @@ enum { ADG_RUSANOV = 0, ADG_HLLC = 1 };
 enum { ADG_SYNC = 0, ADG_CAA = 1, ADG_SAA = 2, ADG_SCHEDULE = 3 };
 enum { ADG_HOST = 0, ADG_DEVICE = 1 };
 enum { ADG_KXRCF = 0, ADG_MINMOD = 1 };
+enum { ADG_SSPRK3 = 0, ADG_RK2 = 1, ADG_LSERK4 = 2 };
 
 /* Detailed reaction mechanism (Sec. 2: mass-action kinetics with species
    molecular weights W_i and molar production rates omega_i).  Reversible
@@ -106,6 +107,12 @@ typedef struct {
   double weno_gamma[3];   /* linear weights of Eq. (10) */
   double weno_eps;        /* epsilon of Eq. (10) */
   double dt;              /* fixed time step (> 0); the AT weights of Eq. (8) assume it constant */
+  int32_t rk;             /* ADG_SSPRK3: three-stage SSP Runge-Kutta (Shu-Osher form);
+                             ADG_RK2: Heun's two-stage method and ADG_LSERK4: the five-stage
+                             fourth-order low-storage scheme of Carpenter and Kennedy, both in the
+                             2N-storage form k <- A_s k + dt L(u), u <- u + B_s k (the LSERK
+                             integrators of Sec. 3.1).  Stage s of step n reads the stage-s data of
+                             past levels (Eq. (7)); batches support ADG_SSPRK3 only. */
 } adg_discretization;
 
 /* Emulated PEs and delay model, Sec. 3.2 and 4. */
@@ -164,7 +171,8 @@ int32_t adg_n_interfaces(const adg_solver *s);
 /* Enqueue n_steps steps like adg_step and time every kernel launch with HIP
    events on the solver's stream.  ms_out[i] receives the mean duration in ms
    of kernel class i and launches_out[i] the launch count; n_classes is the
-   array length (classes: 0 stage kernel, 1 limiter, 2 limiter scatter).
+   array length (classes: 0 stage kernel, 1 troubled-cell indicator, 2 limiter
+   scatter, 3 WENO of the troubled cells).
    Synchronises. */
 adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *launches_out, int32_t n_classes);
 
@@ -263,7 +271,8 @@ adg_status adg_batch_set_graph(adg_batch *b, int32_t steps_per_graph);
 
 /* Enqueue n_steps steps with HIP events around every launch; ms_out[c] is the
    mean duration of launch class c (0 detailed stage, 1 one-step stage,
-   2 limiter, 3 limiter scatter) and launches_out[c] its count.  Synchronises. */
+   2 troubled-cell indicator, 3 WENO of the troubled cells, 4 limiter scatter)
+   and launches_out[c] its count.  Synchronises. */
 adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int64_t *launches_out,
                              int32_t n_classes);
 

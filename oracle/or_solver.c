@@ -62,6 +62,8 @@ struct or_solver {
   int *face_if, *if_face;
 
   double *w, *w1, *w2, *w3, *wu, *rhs;
+  int S;                           /* stages per time step */
+  double *kreg;                    /* 2N-storage register */
   double *tr_m, *tr_p;             /* traces at xi = -1, +1: [E][V] */
   double *fl;                      /* numerical flux per face [nfaces][V] */
   double *wc_sync, *wc_at;         /* central traces per face (LDG) */
@@ -93,13 +95,13 @@ static int right_face(const or_solver *s, int e) {
 }
 
 static double *hist_F(or_solver *s, int64_t m, int st, int i) {
-  return s->hF + (((size_t)m * 3 + st) * s->nif + i) * s->V;
+  return s->hF + (((size_t)m * s->S + st) * s->nif + i) * s->V;
 }
 static double *hist_Wc(or_solver *s, int64_t m, int st, int i) {
-  return s->hWc + (((size_t)m * 3 + st) * s->nif + i) * s->V;
+  return s->hWc + (((size_t)m * s->S + st) * s->nif + i) * s->V;
 }
 static double *hist_U(or_solver *s, int64_t m, int st, int i, int side) {
-  return s->hU + ((((size_t)m * 3 + st) * s->nif + i) * 2 + side) * (size_t)s->V * s->M;
+  return s->hU + ((((size_t)m * s->S + st) * s->nif + i) * 2 + side) * (size_t)s->V * s->M;
 }
 
 static int fail(or_solver *s, const char *m) {
@@ -119,7 +121,7 @@ void or_destroy(or_solver *s) {
   void *ptrs[] = {s->W, s->nasa7, s->A, s->b, s->Ea, s->pmf, s->nu_f, s->nu_r, s->pe_off, s->schedule,
                   s->face_if, s->if_face, s->w, s->w1, s->w2, s->w3, s->wu, s->rhs, s->tr_m, s->tr_p,
                   s->fl, s->wc_sync, s->wc_at, s->q_sync, s->q_at, s->kif, s->cif, s->hF, s->hWc,
-                  s->hU, s->flags};
+                  s->hU, s->flags, s->kreg};
   for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
   free(s);
 }
@@ -212,6 +214,9 @@ int or_create(const or_config *cfg, const double *w0, int32_t max_steps, or_solv
   s->w1 = malloc(sizeof(double) * nst);
   s->w2 = malloc(sizeof(double) * nst);
   s->w3 = malloc(sizeof(double) * nst);
+  if (cfg->rk < OR_SSPRK3 || cfg->rk > OR_LSERK4) { or_destroy(s); return -1; }
+  s->S = cfg->rk == OR_SSPRK3 ? 3 : cfg->rk == OR_RK2 ? 2 : 5;
+  s->kreg = calloc(nst, sizeof(double));
   s->wu = malloc(sizeof(double) * nst);
   s->rhs = malloc(sizeof(double) * nst);
   s->q_sync = calloc(nst, sizeof(double));
@@ -227,7 +232,7 @@ int or_create(const or_config *cfg, const double *w0, int32_t max_steps, or_solv
   memcpy(s->w, w0, sizeof(double) * nst);
   s->max_steps = max_steps;
   if (cfg->mode != OR_SYNC && s->nif > 0) {
-    size_t lv = (size_t)max_steps * 3 * s->nif;
+    size_t lv = (size_t)max_steps * s->S * s->nif;
     s->hF = calloc(lv * s->V, sizeof(double));
     s->hWc = calloc(lv * s->V, sizeof(double));
     s->hU = calloc(lv * 2 * s->V * s->M, sizeof(double));
@@ -500,8 +505,36 @@ static int apply_limiter(or_solver *s, int st, const double *wu, double *wl) {
   return 0;
 }
 
-/* One SSP-RK3 stage: w_out = a0 w_base + a1 (w_in + dt L(w_in)), then the
-   history record of the PE-interface elements, then the limiter. */
+/* 2N-storage low-storage Runge-Kutta schemes (Williamson's form): per stage
+   k <- A_s k + dt L(u), u <- u + B_s k.
+   RK2: A = (0, -1), B = (1, 1/2), which is Heun's two-stage second-order method
+   (u1 = u + dt L(u), u^{n+1} = (u + u1 + dt L(u1))/2).
+   LSERK4: the five-stage fourth-order scheme of Carpenter and Kennedy (NASA
+   TM-109112, 1994), the usual "LSERK" of DG solvers. */
+static const double kRK2A[2] = {0.0, -1.0};
+static const double kRK2B[2] = {1.0, 0.5};
+static const double kLSA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double kLSB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+/* History record of the PE-interface elements of a stage output, then the
+   limiter (which turns the unlimited output u into w_out). */
+static int finish_stage(or_solver *s, int st, double *u, double *w_out) {
+  if (s->hU) {
+    for (int i = 0; i < s->nif; ++i) {
+      int f = s->if_face[i];
+      int le = left_elem(s, f), re = right_elem(s, f);
+      memcpy(hist_U(s, s->n, st, i, 0), u + IDX(le, 0, 0), sizeof(double) * s->V * s->M);
+      memcpy(hist_U(s, s->n, st, i, 1), u + IDX(re, 0, 0), sizeof(double) * s->V * s->M);
+    }
+  }
+  if (s->cfg.limiter) return apply_limiter(s, st, u, w_out);
+  return 0;
+}
+
+/* One SSP-RK3 stage (Shu-Osher form): w_out = a0 w_base + a1 (w_in + dt L(w_in)). */
 static int do_stage(or_solver *s, int st, const double *w_in, const double *w_base, double *w_out) {
   size_t nst = (size_t)s->E * s->V * s->M;
   if (compute_rhs(s, st, w_in, s->rhs)) return -1;
@@ -513,16 +546,20 @@ static int do_stage(or_solver *s, int st, const double *w_in, const double *w_ba
     else if (st == 1) dst[t] = 0.75 * w_base[t] + 0.25 * y;
     else dst[t] = (1.0 / 3.0) * w_base[t] + (2.0 / 3.0) * y;
   }
-  if (s->hU) {
-    for (int i = 0; i < s->nif; ++i) {
-      int f = s->if_face[i];
-      int le = left_elem(s, f), re = right_elem(s, f);
-      memcpy(hist_U(s, s->n, st, i, 0), dst + IDX(le, 0, 0), sizeof(double) * s->V * s->M);
-      memcpy(hist_U(s, s->n, st, i, 1), dst + IDX(re, 0, 0), sizeof(double) * s->V * s->M);
-    }
+  return finish_stage(s, st, dst, w_out);
+}
+
+/* One stage of a 2N-storage scheme: k = A k + dt L(u_in); u_out = u_in + B k. */
+static int do_stage_2n(or_solver *s, int st, double A, double B, const double *u_in, double *u_out) {
+  size_t nst = (size_t)s->E * s->V * s->M;
+  if (compute_rhs(s, st, u_in, s->rhs)) return -1;
+  double dt = s->cfg.dt;
+  double *dst = s->cfg.limiter ? s->wu : u_out;
+  for (size_t t = 0; t < nst; ++t) {
+    s->kreg[t] = A * s->kreg[t] + dt * s->rhs[t];
+    dst[t] = u_in[t] + B * s->kreg[t];
   }
-  if (s->cfg.limiter) return apply_limiter(s, st, s->wu, w_out);
-  return 0;
+  return finish_stage(s, st, dst, u_out);
 }
 
 int or_step(or_solver *s, int32_t n_steps) {
@@ -533,10 +570,21 @@ int or_step(or_solver *s, int32_t n_steps) {
       s->kif[i] = or_eff_delay(&s->cfg, s->nif, s->n, i);
       if (or_at_coeffs(s->q, s->kif[i], s->cif + (size_t)i * s->q)) return fail(s, "AT weights");
     }
-    if (do_stage(s, 0, s->w, s->w, s->w1)) return -1;
-    if (do_stage(s, 1, s->w1, s->w, s->w2)) return -1;
-    if (do_stage(s, 2, s->w2, s->w, s->w3)) return -1;
-    memcpy(s->w, s->w3, sizeof(double) * nst);
+    if (s->cfg.rk == OR_SSPRK3) {
+      if (do_stage(s, 0, s->w, s->w, s->w1)) return -1;
+      if (do_stage(s, 1, s->w1, s->w, s->w2)) return -1;
+      if (do_stage(s, 2, s->w2, s->w, s->w3)) return -1;
+      memcpy(s->w, s->w3, sizeof(double) * nst);
+    } else {
+      const double *A = s->cfg.rk == OR_RK2 ? kRK2A : kLSA;
+      const double *B = s->cfg.rk == OR_RK2 ? kRK2B : kLSB;
+      double *u = s->w, *v = s->w1;
+      for (int st = 0; st < s->S; ++st) {
+        if (do_stage_2n(s, st, A[st], B[st], u, v)) return -1;
+        double *x = u; u = v; v = x;
+      }
+      if (u != s->w) memcpy(s->w, u, sizeof(double) * nst);
+    }
     s->n++;
   }
   return 0;

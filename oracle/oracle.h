@@ -23,6 +23,7 @@ enum { OR_PERIODIC = 0, OR_TRANSMISSIVE = 1 };
 enum { OR_RUSANOV = 0, OR_HLLC = 1 };
 enum { OR_SYNC = 0, OR_CAA = 1, OR_SAA = 2, OR_SCHEDULE = 3 };
 enum { OR_KXRCF = 0, OR_MINMOD = 1 };
+enum { OR_SSPRK3 = 0, OR_RK2 = 1, OR_LSERK4 = 2 };
 
 typedef struct {
   /* ---- physics, Sec. 2 ---- */
@@ -53,6 +54,7 @@ typedef struct {
   double weno_gamma[3];   /* linear weights gamma_{-1}, gamma_0, gamma_{+1} */
   double weno_eps;
   double dt;
+  int32_t rk;             /* OR_SSPRK3 (Shu-Osher) | OR_RK2 | OR_LSERK4 (2N-storage schemes) */
   /* ---- asynchrony, Sec. 3.2 and Sec. 4 ---- */
   int32_t n_pe;
   const int32_t *pe_offsets;   /* [n_pe + 1] element offsets, or NULL = floor(p E / P) */

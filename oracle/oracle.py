@@ -54,7 +54,7 @@ class OrConfig(C.Structure):
         ("bc", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
         ("indicator", C.c_int32), ("tvb_m", C.c_double),
         ("weno_gamma", C.c_double * 3), ("weno_eps", C.c_double),
-        ("dt", C.c_double),
+        ("dt", C.c_double), ("rk", C.c_int32),
         ("n_pe", C.c_int32), ("pe_offsets", C.POINTER(C.c_int32)),
         ("mode", C.c_int32), ("L", C.c_int32), ("pmf", C.POINTER(C.c_double)),
         ("seed", C.c_uint64),
@@ -160,6 +160,7 @@ class Config:
         c.bc = TRANSMISSIVE if disc.get("bc", "periodic") == "transmissive" else PERIODIC
         c.flux = HLLC if disc.get("flux", "rusanov") == "hllc" else RUSANOV
         c.limiter = int(disc.get("limiter", 0))
+        c.rk = {"ssprk3": 0, "rk2": 1, "lserk4": 2}[disc.get("rk", "ssprk3")]
         c.indicator = {"kxrcf": 0, "minmod": 1}[disc.get("indicator", "kxrcf")]
         c.tvb_m = float(disc.get("tvb_m", 0.0))
         g = disc.get("weno_gamma", (0.001, 0.998, 0.001))

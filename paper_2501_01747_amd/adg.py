@@ -23,6 +23,7 @@ SYNC, CAA, SAA, SCHEDULE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FP64, MIXED_FP32 = 0, 1
 KXRCF, MINMOD = 0, 1
+SSPRK3, RK2, LSERK4 = 0, 1, 2
 PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter", "weno")
 BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage", "limiter", "weno", "limiter_scatter")
 
@@ -58,7 +59,7 @@ class Discretization(C.Structure):
         ("bc", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
         ("indicator", C.c_int32), ("tvb_m", C.c_double),
         ("weno_gamma", C.c_double * 3), ("weno_eps", C.c_double),
-        ("dt", C.c_double),
+        ("dt", C.c_double), ("rk", C.c_int32),
     ]
 
 
@@ -163,6 +164,7 @@ class Problem:
         d.weno_gamma[0], d.weno_gamma[1], d.weno_gamma[2] = g
         d.weno_eps = float(disc.get("weno_eps", 1e-6))
         d.dt = float(disc["dt"])
+        d.rk = {"ssprk3": SSPRK3, "rk2": RK2, "lserk4": LSERK4}[disc.get("rk", "ssprk3")]
         a = Async()
         a.n_pe = int(asy["n_pe"])
         if asy.get("pe_offsets") is not None:

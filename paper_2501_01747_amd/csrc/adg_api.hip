@@ -22,6 +22,9 @@ using namespace adg;
 struct adg_solver {
   Problem P;
   hipStream_t stream = nullptr;
+  int cur = 0;            // state buffer at the start of the next step (2N schemes alternate 0 and 1)
+  int graph_cur = 0;      // state buffer the captured graph starts from
+  int graph_cur_after = 0;
   int ns_cfg = 0;   // work decomposition of the detailed-chemistry stage kernel
   int graph_steps = 0;
   int graph_built_for = 0;
@@ -54,22 +57,31 @@ adg_status hip_fail(adg_solver *s, hipError_t e, const char *where) {
 typedef void (*TimerFn)(adg_solver *, int cls, bool begin);
 
 adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
-  const int M = s->P.lay.M;
+  const int M = s->P.lay.M, S = s->P.lay.S;
+  const int rk = s->P.disc.rk;
   const int in_buf[3] = {0, 1, 2}, out_buf[3] = {1, 2, 0};
-  for (int stage = 0; stage < 3; ++stage) {
+  for (int stage = 0; stage < S; ++stage) {
+    const RkStage r = rk_stage(rk, stage);
+    // Shu-Osher SSP-RK3: w^n in buffer 0, stages in 1 and 2, the last stage back into 0.
+    // 2N schemes: the state alternates between buffers 0 and 1 (s->cur holds it at the
+    // start of the step), the register is buffer 2.
+    const int bi = r.two_n ? (s->cur + stage) % 2 : in_buf[stage];
+    const int bo = r.two_n ? (s->cur + stage + 1) % 2 : out_buf[stage];
+    const bool last = stage == S - 1;
     if (s->P.phys.model == ADG_ONESTEP) {
       EulerArgs a = s->P.ea;
       a.w0 = s->P.W[0];
-      a.ws = s->P.W[in_buf[stage]];
-      a.wout = s->P.W[out_buf[stage]];
+      a.ws = s->P.W[bi];
+      a.wout = s->P.W[bo];
       a.stage = stage;
-      a.advance = stage == 2 && !s->P.disc.limiter;
+      a.rk = r;
+      a.advance = last && !s->P.disc.limiter;
       if (timer) timer(s, 0, true);
       HIP_TRY(s, launch_euler_stage(M, s->P.disc.flux, a, st));
       if (timer) timer(s, 0, false);
       if (s->P.disc.limiter) {
         LimiterArgs l = s->P.la;
-        l.w = s->P.W[out_buf[stage]];
+        l.w = s->P.W[bo];
         l.stage = stage;
         l.advance = 0;
         if (timer) timer(s, 1, true);
@@ -78,7 +90,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
         if (timer) timer(s, 3, true);
         HIP_TRY(s, launch_weno(M, l, st));
         if (timer) timer(s, 3, false);
-        l.advance = stage == 2;
+        l.advance = last;
         if (timer) timer(s, 2, true);
         HIP_TRY(s, launch_limiter_scatter(M, l, st));
         if (timer) timer(s, 2, false);
@@ -86,15 +98,17 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
     } else {
       NsArgs a = s->P.na;
       a.w0 = s->P.W[0];
-      a.ws = s->P.W[in_buf[stage]];
-      a.wout = s->P.W[out_buf[stage]];
+      a.ws = s->P.W[bi];
+      a.wout = s->P.W[bo];
       a.stage = stage;
-      a.advance = stage == 2;
+      a.rk = r;
+      a.advance = last;
       if (timer) timer(s, 0, true);
       HIP_TRY(s, launch_ns_stage(M, s->ns_cfg, a, st));
       if (timer) timer(s, 0, false);
     }
   }
+  if (rk_stage(rk, 0).two_n) s->cur = (s->cur + S) % 2;
   return ADG_OK;
 }
 
@@ -111,7 +125,11 @@ adg_status build_graph(adg_solver *s) {
   if (!s->cap_stream) HIP_TRY(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
   HIP_TRY(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
   adg_status rc = ADG_OK;
+  const int cur0 = s->cur;
   for (int i = 0; i < s->graph_steps && rc == ADG_OK; ++i) rc = enqueue_step(s, s->cap_stream, nullptr);
+  s->graph_cur = cur0;
+  s->graph_cur_after = s->cur;
+  s->cur = cur0;   // nothing ran: capture only records
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
   if (rc != ADG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -161,6 +179,7 @@ adg_status adg_set_state(adg_solver *s, const double *w, int64_t count, int32_t 
   } else {
     return fail(s, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
   }
+  s->cur = 0;
   HIP_TRY(s, reset_problem(s->P, s->stream));
   if (where == ADG_HOST) HIP_TRY(s, hipStreamSynchronize(s->stream));
   return ADG_OK;
@@ -173,11 +192,19 @@ adg_status adg_step(adg_solver *s, int32_t n_steps) {
       adg_status rc = build_graph(s);
       if (rc != ADG_OK) return rc;
     }
-    int full = n_steps / s->graph_steps, rest = n_steps % s->graph_steps;
-    for (int i = 0; i < full; ++i) HIP_TRY(s, hipGraphLaunch(s->gexec, s->stream));
-    for (int i = 0; i < rest; ++i) {
-      adg_status rc = enqueue_step(s, s->stream, nullptr);
-      if (rc != ADG_OK) return rc;
+    // the graph starts from the buffer it was captured with; a plain step realigns
+    // the alternating state buffer of the 2N schemes when needed
+    int left = n_steps;
+    while (left > 0) {
+      if (left >= s->graph_steps && s->cur == s->graph_cur) {
+        HIP_TRY(s, hipGraphLaunch(s->gexec, s->stream));
+        s->cur = s->graph_cur_after;
+        left -= s->graph_steps;
+      } else {
+        adg_status rc = enqueue_step(s, s->stream, nullptr);
+        if (rc != ADG_OK) return rc;
+        left -= 1;
+      }
     }
     return ADG_OK;
   }
@@ -203,9 +230,9 @@ adg_status adg_get_state(adg_solver *s, double *w, int64_t count, int32_t where)
   const int VM = L.V * L.M;
   if (count != (int64_t)L.E * VM) return fail(s, ADG_ERR_ARG, "state size mismatch");
   if (where == ADG_HOST) {
-    HIP_TRY(s, download_state_host(s->P, w, s->stream));
+    HIP_TRY(s, download_state_host(s->P, s->P.W[s->cur], w, s->stream));
   } else if (where == ADG_DEVICE) {
-    HIP_TRY(s, launch_from_planes(s->P.W[0], w, L.E, VM, s->stream));
+    HIP_TRY(s, launch_from_planes(s->P.W[s->cur], w, L.E, VM, s->stream));
   } else {
     return fail(s, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
   }
@@ -252,7 +279,7 @@ adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *
   }
   // the launch classes of one step, in order
   std::vector<int> order;
-  for (int stage = 0; stage < 3; ++stage) {
+  for (int stage = 0; stage < s->P.lay.S; ++stage) {
     order.push_back(0);
     if (s->P.phys.model == ADG_ONESTEP && s->P.disc.limiter) {
       order.push_back(1);
@@ -286,12 +313,15 @@ adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
   if (choice) *choice = 0;
   if (s->P.phys.model != ADG_DETAILED) return ADG_OK;   // one decomposition only
   const int M = s->P.lay.M;
-  // stage-0 launches only: they read w^n and write the first stage buffer and the level's
-  // stage-0 history, which the next step recomputes; the state is untouched
+  // first-stage launches only: they read the state and write the first stage's output
+  // buffer (and the 2N register, whose old value the first stage does not read) and the
+  // level's first-stage history, all of which the next step recomputes; the state is untouched
   NsArgs a = s->P.na;
+  a.rk = rk_stage(s->P.disc.rk, 0);
+  const int bi = a.rk.two_n ? s->cur : 0, bo = a.rk.two_n ? (s->cur + 1) % 2 : 1;
   a.w0 = s->P.W[0];
-  a.ws = s->P.W[0];
-  a.wout = s->P.W[1];
+  a.ws = s->P.W[bi];
+  a.wout = s->P.W[bo];
   a.stage = 0;
   a.advance = 0;
   double best_ms = 0.0;

@@ -315,6 +315,7 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   if (!make_layout(phys, disc, as, L, &why)) return bfail(b, ADG_ERR_ARG, why);
   if (count != (int64_t)L.E * L.V * L.M) return bfail(b, ADG_ERR_ARG, "state size mismatch");
   if (where != ADG_HOST && where != ADG_DEVICE) return bfail(b, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
+  if (disc->rk != ADG_SSPRK3) return bfail(b, ADG_ERR_UNSUPPORTED, "batches run SSP-RK3 only");
   int slot = -1;
   for (int i = 0; i < b->max_inst; ++i)
     if (!b->slots[i].used) { slot = i; break; }
@@ -383,6 +384,7 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
       a.ws = P.W[in_buf[st]];
       a.wout = P.W[out_buf[st]];
       a.stage = st;
+      a.rk = rk_stage(ADG_SSPRK3, st);
       a.advance = st == 2 && !P.disc.limiter;
       a.step = P.step;
       a.err = P.err;
@@ -477,7 +479,7 @@ adg_status adg_batch_get_state(adg_batch *b, int32_t slot, double *w, int64_t co
   const int VM = L.V * L.M;
   if (count != (int64_t)L.E * VM) return bfail(b, ADG_ERR_ARG, "state size mismatch");
   if (where == ADG_HOST) {
-    BHIP(b, download_state_host(P, w, b->stream));
+    BHIP(b, download_state_host(P, P.W[0], w, b->stream));
   } else if (where == ADG_DEVICE) {
     BHIP(b, launch_from_planes(P.W[0], w, L.E, VM, b->stream));
   } else {

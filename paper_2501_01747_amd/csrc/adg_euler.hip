@@ -90,9 +90,11 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, int blk, in
   bool ok = true;
 
   double u[V][M], wn[V][M];
-  // w^n of an owned element is loaded together with the stage input, so both loads are in
-  // flight at once (the last stage overwrites w^n in place; only this lane reads it)
-  if (own && a.stage != 0) load_elem<M>(a.w0, E, x, wn);
+  // the second operand of the RK combination of an owned element (w^n, or the 2N
+  // register) is loaded together with the stage input, so both loads are in flight at
+  // once (the last Shu-Osher stage overwrites w^n in place; only this lane reads it)
+  const bool use_prev = own && (a.rk.two_n ? a.rk.ca != 0.0 : a.rk.ca != 0.0 || a.rk.cb != 1.0);
+  if (use_prev) load_elem<M>(a.rk.two_n ? a.kbuf : a.w0, E, x, wn);
   if (loads) {
     load_elem<M>(a.ws, E, x, u);
   } else {
@@ -158,7 +160,6 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, int blk, in
         srcR[j] += a.tb.WB[q][j] * (-rate);
       }
     }
-    const bool st_last = a.stage == 2;
     double *recR = (a.store_U && if_left >= 0)   // this element is right of interface if_left
                        ? ring_rec(a.ring, n, a.stage, a.dl.nif, if_left) + a.ring.off_U + V * M : nullptr;
     double *recL = (a.store_U && iface >= 0)     // left of interface iface
@@ -172,14 +173,19 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, int blk, in
         if (v == 3) s = srcR[j];
         if (v == 4) s = -srcR[j];
         const double L = a.two_over_dx * (half2j1 * vol[v][j]) + half2j1 * s;
-        const double y = u[v][j] + a.dt * L;
+        const size_t gi = sidx(x, v * M + j, V * M);
         double o;
-        if (a.stage == 0) {
-          o = y;
+        // explicit fused multiply-adds: every kernel that runs this combination (single
+        // problem or batch) rounds it the same way
+        if (a.rk.two_n) {
+          const double kn = use_prev ? fma(a.rk.ca, wn[v][j], a.dt * L) : a.dt * L;
+          a.kbuf[gi] = kn;
+          o = fma(a.rk.cb, kn, u[v][j]);
         } else {
-          o = st_last ? (1.0 / 3.0) * wn[v][j] + (2.0 / 3.0) * y : 0.75 * wn[v][j] + 0.25 * y;
+          const double y = fma(a.dt, L, u[v][j]);
+          o = use_prev ? fma(a.rk.ca, wn[v][j], a.rk.cb * y) : y;
         }
-        a.wout[sidx(x, v * M + j, V * M)] = o;
+        a.wout[gi] = o;
         if (recR) recR[v * M + j] = o;
         if (recL) recL[v * M + j] = o;
       }
@@ -517,7 +523,7 @@ __device__ __forceinline__ void scatter_body(const LimiterArgs &a, int blk, int 
         a.w[gi] = a.wlim[gi];
       }
   }
-  if (blk == 0 && threadIdx.x == 0) a.tcount[a.stage == 2 ? 0 : a.stage + 1] = 0u;
+  if (blk == 0 && threadIdx.x == 0) a.tcount[(a.stage + 1) % a.nstages] = 0u;
   if (a.advance) finish_step(a.step, a.done, nblk);
 }
 

@@ -32,6 +32,7 @@ struct DelayParams {
 struct RingParams {
   double *base;
   int D;
+  int stages;           // RK stages per time step (records per level)
   int rec;
   int off_F, off_Wc, off_U;
 };
@@ -51,7 +52,7 @@ __host__ __device__ inline size_t state_doubles(int E, int VM) {
 
 __host__ __device__ inline double *ring_rec(const RingParams &r, long long level, int stage, int nif, int i) {
   long long slot = level % r.D;
-  return r.base + ((slot * 3 + stage) * (long long)nif + i) * r.rec;
+  return r.base + ((slot * r.stages + stage) * (long long)nif + i) * r.rec;
 }
 
 // Per-element constant tables (host-computed).
@@ -66,6 +67,42 @@ struct OneStep {
   double gamma, q_heat, e_act, k_pre;
 };
 
+// Time-integration coefficients of one RK stage.
+struct RkStage {
+  int two_n;            // 0: Shu-Osher form  out = ca w^n + cb (w^(s) + dt L(w^(s)))  (ca = 0: out = w^(s) + dt L)
+                        // 1: 2N form         k = ca k + dt L(u), out = u + cb k
+  double ca, cb;
+};
+
+// Stages per step of an integrator (0 = SSP-RK3, 1 = RK2, 2 = LSERK4).
+__host__ __device__ inline int rk_stages(int rk) { return rk == 0 ? 3 : rk == 1 ? 2 : 5; }
+
+// The coefficients of stage s.  SSP-RK3 in Shu-Osher form; RK2 (Heun) and the
+// five-stage fourth-order scheme of Carpenter and Kennedy (NASA TM-109112, 1994)
+// in 2N-storage form.
+__host__ __device__ inline RkStage rk_stage(int rk, int s) {
+  RkStage r{};
+  if (rk == 0) {
+    r.two_n = 0;
+    r.ca = s == 0 ? 0.0 : s == 1 ? 0.75 : 1.0 / 3.0;
+    r.cb = s == 0 ? 1.0 : s == 1 ? 0.25 : 2.0 / 3.0;
+  } else if (rk == 1) {
+    r.two_n = 1;
+    r.ca = s == 0 ? 0.0 : -1.0;
+    r.cb = s == 0 ? 1.0 : 0.5;
+  } else {
+    const double A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                         -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+    const double B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                         2277821191437.0 / 14882151754819.0};
+    r.two_n = 1;
+    r.ca = A[s];
+    r.cb = B[s];
+  }
+  return r;
+}
+
 struct EulerArgs {
   const double *w0;     // w^n (may alias wout at the last stage)
   const double *ws;     // stage input w^(s)
@@ -79,6 +116,8 @@ struct EulerArgs {
   int E;
   int periodic;
   int stage;
+  RkStage rk;
+  double *kbuf;         // 2N register (2N schemes)
   int store_U;          // publish boundary-element outputs for the limiter
   double dt;
   double two_over_dx;
@@ -93,7 +132,7 @@ struct LimiterArgs {
   double *wlim;         // limited values of troubled cells
   int8_t *flags;        // [E]
   int *tlist;           // [E] troubled elements of the current stage, in any order
-  unsigned *tcount;     // [3] list lengths, one per RK stage
+  unsigned *tcount;     // [nstages] list lengths, one per RK stage
   unsigned long long *flag_count;
   const int *face_if;
   long long *step;
@@ -104,6 +143,7 @@ struct LimiterArgs {
   int E;
   int periodic;
   int stage;
+  int nstages;          // RK stages per step (list lengths, one per stage)
   double kx_h;          // dx^((N_p+1)/2)
   int indicator;        // ADG_KXRCF | ADG_MINMOD
   double tvb_mh2;       // M dx^2 of the TVB minmod test

@@ -108,7 +108,8 @@ struct NsLds {
 // traces are likewise mode 0 plus the FP32 sum of the higher modes.
 template <int M, int NS, typename OpT, int NTH, int TE>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
-                                        double *wout, int stage, int advance, int e0, int ntiles,
+                                        double *wout, int stage, int advance, const RkStage rk, double *kbuf,
+                                        int e0, int ntiles,
                                         NsLds<M, NS, TE> &Ls, NsMech &smech) {
   constexpr int V = 3 + NS, Q = M;
   using Lds = NsLds<M, NS, TE>;
@@ -154,7 +155,11 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   //    Every global load is issued before the first LDS store, so the phase costs about one
   //    memory latency.
   constexpr int kOut = (V * M * TE + NTH - 1) / NTH;
-  double w0pre[kOut];   // w^n of the outputs this thread writes in the last phase
+  // the second operand of the RK combination (w^n, or the 2N register) of the outputs
+  // this thread writes in the last phase
+  const bool use_prev = rk.two_n ? rk.ca != 0.0 : rk.ca != 0.0 || rk.cb != 1.0;
+  const double *prev = rk.two_n ? kbuf : w0;
+  double w0pre[kOut];
   {
     constexpr int nwords = (int)(sizeof(NsMech) / 8);
     constexpr int kMw = (nwords + NTH - 1) / NTH;
@@ -189,7 +194,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     for (int m = 0; m < kOut; ++m) {
       const int idx = t + m * NTH;
       w0pre[m] = 0.0;
-      if (stage != 0 && idx < V * M * nloc) w0pre[m] = w0[sidx(e0 + idx % nloc, idx / nloc, V * M)];
+      if (use_prev && idx < V * M * nloc) w0pre[m] = prev[sidx(e0 + idx % nloc, idx / nloc, V * M)];
     }
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
@@ -552,12 +557,17 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       b = (double)vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
     }
     const double L = 2.0 * a.inv_dx * (half2j1 * b) + half2j1 * src;
-    const double y = sW[c][el + 2] + a.dt * L;
     const size_t gi = sidx(e0 + el, c, V * M);
     double o;
-    if (stage == 0) o = y;
-    else if (stage == 1) o = 0.75 * w0pre[m] + 0.25 * y;
-    else o = (1.0 / 3.0) * w0pre[m] + (2.0 / 3.0) * y;
+    // explicit fused multiply-adds: the single-problem and batched kernels round alike
+    if (rk.two_n) {
+      const double kn = use_prev ? fma(rk.ca, w0pre[m], a.dt * L) : a.dt * L;
+      kbuf[gi] = kn;
+      o = fma(rk.cb, kn, sW[c][el + 2]);
+    } else {
+      const double y = fma(a.dt, L, sW[c][el + 2]);
+      o = use_prev ? fma(rk.ca, w0pre[m], rk.cb * y) : y;
+    }
     wout[gi] = o;
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
@@ -568,8 +578,8 @@ template <int M, int NS, int TE, int NTH>
 __global__ __launch_bounds__(NTH) void ns_stage_kernel(NsArgs a) {
   __shared__ NsLds<M, NS, TE> L;
   __shared__ NsMech smech;
-  ns_tile<M, NS, double, NTH, TE>(a, a.ws, a.w0, a.wout, a.stage, a.advance, xcd_item(blockIdx.x, gridDim.x) * TE,
-                                  gridDim.x, L, smech);
+  ns_tile<M, NS, double, NTH, TE>(a, a.ws, a.w0, a.wout, a.stage, a.advance, a.rk, a.kbuf,
+                                  xcd_item(blockIdx.x, gridDim.x) * TE, gridDim.x, L, smech);
 }
 
 // LDS of the batched kernel: room for the largest order it serves.
@@ -616,16 +626,17 @@ __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *_
   double *wout = a.W[out_buf];
   const int ntiles = (a.E + TE - 1) / TE;
   const int M = a.M;
+  const RkStage rk = rk_stage(ADG_SSPRK3, stage);   // batches run SSP-RK3
   if (M == 2) {
-    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m2, smech);
+    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m2, smech);
   } else if constexpr (MMAX >= 3) {
     if (M == 3) {
-      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m3, smech);
+      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m3, smech);
     } else if constexpr (MMAX >= 4) {
       if (M == 4) {
-        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m4, smech);
+        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m4, smech);
       } else if constexpr (MMAX >= 5) {
-        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, tl.y, ntiles, L.m5, smech);
+        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m5, smech);
       }
     }
   }

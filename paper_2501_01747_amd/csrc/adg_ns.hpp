@@ -54,6 +54,8 @@ struct NsArgs {
   const NsMech *mech;
   int E;
   int stage;
+  RkStage rk;
+  double *kbuf;         // 2N register (2N schemes)
   int viscous;
   double dt;
   double inv_dx;       // 1/dx

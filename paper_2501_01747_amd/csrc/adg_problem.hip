@@ -139,6 +139,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   } else {
     return bad("unknown model");
   }
+  if (d->rk != ADG_SSPRK3 && d->rk != ADG_RK2 && d->rk != ADG_LSERK4) return bad("unknown integrator");
   if (d->limiter && d->indicator != ADG_KXRCF && d->indicator != ADG_MINMOD) return bad("unknown indicator");
   if (d->limiter && !(d->tvb_m >= 0.0)) return bad("tvb_m must be >= 0");
   if (as->mode == ADG_SAA) {
@@ -158,6 +159,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   L.nif = periodic ? as->n_pe : as->n_pe - 1;
   L.nfaces = periodic ? L.E : L.E + 1;
   L.q = as->at_order > 0 ? as->at_order : d->order_p + 1;
+  L.S = rk_stages(d->rk);
   const int kmax = as->mode == ADG_SYNC ? 0 : as->L - 1;
   L.D = kmax + L.q;
   const bool visc = ph->model == ADG_DETAILED && ph->viscous;
@@ -174,7 +176,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   L.tlist = off;  off += d->limiter ? align256(sizeof(int) * (size_t)L.E) : 0;
   L.face_if = off; off += align256(sizeof(int) * (L.E + 1));
   L.counters = off; off += 256;
-  L.ring = off;   off += align256(sizeof(double) * (size_t)L.D * 3 * (L.nif > 0 ? L.nif : 1) * L.rec);
+  L.ring = off;   off += align256(sizeof(double) * (size_t)L.D * L.S * (L.nif > 0 ? L.nif : 1) * L.rec);
   L.sched = off;  off += as->mode == ADG_SCHEDULE ? align256((size_t)as->schedule_steps * (L.nif > 0 ? L.nif : 1)) : 0;
   L.mech = off;   off += ph->model == ADG_DETAILED ? align256(sizeof(NsMech)) : 0;
   L.total = off;
@@ -239,6 +241,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
   RingParams rp{};
   rp.base = P.ring;
   rp.D = L.D;
+  rp.stages = L.S;
   rp.rec = L.rec;
   rp.off_F = L.off_F;
   rp.off_Wc = L.off_Wc;
@@ -257,6 +260,8 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
     a.E = L.E;
     a.periodic = periodic;
     a.store_U = disc->limiter && L.nif > 0;
+    a.kbuf = P.W[2];
+    a.rk = rk_stage(disc->rk, 0);
     a.dt = disc->dt;
     a.two_over_dx = 2.0 / dx;
     a.ph = {phys->gamma, phys->q_heat, phys->e_act, phys->k_pre};
@@ -278,6 +283,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
       l.E = L.E;
       l.periodic = periodic;
       l.kx_h = std::pow(dx, 0.5 * (disc->order_p + 1));
+      l.nstages = L.S;
       l.indicator = disc->indicator;
       l.tvb_mh2 = disc->tvb_m * dx * dx;
       for (int k = 0; k < 3; ++k) l.gam[k] = disc->weno_gamma[k];
@@ -293,6 +299,8 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
                              (NsMech *)(base + L.mech));
     if (rc != ADG_OK) return rc;
     for (int b = 0; b < 3; ++b) P.na.W[b] = P.W[b];
+    P.na.kbuf = P.W[2];
+    P.na.rk = rk_stage(disc->rk, 0);
     P.na.target = kNoTarget;
   }
   return ADG_OK;
@@ -309,11 +317,11 @@ hipError_t upload_state_host(const Problem &P, const double *w, hipStream_t st) 
   return hipStreamSynchronize(st);
 }
 
-hipError_t download_state_host(const Problem &P, double *w, hipStream_t st) {
+hipError_t download_state_host(const Problem &P, const double *buf, double *w, hipStream_t st) {
   const Layout &L = P.lay;
   const int VM = L.V * L.M;
   std::vector<double> planes(state_doubles(L.E, VM));
-  hipError_t e = hipMemcpyAsync(planes.data(), P.W[0], planes.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(planes.data(), buf, planes.size() * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
@@ -326,7 +334,7 @@ hipError_t reset_problem(const Problem &P, hipStream_t st) {
   const Layout &L = P.lay;
   hipError_t e = hipMemsetAsync(P.base + L.counters, 0, 256, st);
   if (e == hipSuccess)
-    e = hipMemsetAsync(P.ring, 0, sizeof(double) * (size_t)L.D * 3 * (L.nif > 0 ? L.nif : 1) * L.rec, st);
+    e = hipMemsetAsync(P.ring, 0, sizeof(double) * (size_t)L.D * L.S * (L.nif > 0 ? L.nif : 1) * L.rec, st);
   if (e == hipSuccess) e = hipMemsetAsync(P.flags, 0, (size_t)L.E, st);
   return e;
 }

@@ -19,6 +19,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   size_t state, wlim, flags, tlist, face_if, counters, ring, sched, mech, total;
   int nif, nfaces, D, rec, q, V, M, E;
+  int S;                // RK stages per step
   int off_F, off_Wc, off_U;
 };
 
@@ -50,7 +51,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
 adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc, const adg_async *as, char *base,
                          const Layout &L, Problem &P);
 hipError_t upload_state_host(const Problem &P, const double *w, hipStream_t st);
-hipError_t download_state_host(const Problem &P, double *w, hipStream_t st);
+hipError_t download_state_host(const Problem &P, const double *buf, double *w, hipStream_t st);
 // Step counter, error flag, history ring and flags back to zero.
 hipError_t reset_problem(const Problem &P, hipStream_t st);
 

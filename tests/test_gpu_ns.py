@@ -158,3 +158,10 @@ def test_autotune_keeps_the_state_and_parity(adg, orc, mech):
     o.step(9)
     assert rel_per_var(s.state(), o.state()) < 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("rk", ["rk2", "lserk4"])
+def test_low_storage_integrators_detailed(adg, orc, mech, rk):
+    case, w0 = gen.case_c1(E=40, order_p=2, n_pe=5, mech=mech, cfl=0.08, Lx=0.01 * 40 / 2048)
+    case["disc"]["rk"] = rk
+    compare(adg, orc, case, w0, 9, every=3)
