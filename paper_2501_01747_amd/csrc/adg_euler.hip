@@ -229,36 +229,38 @@ __global__ __launch_bounds__(kEulerBlock) void euler_batch_kernel(const EulerSet
 // Y_R only, so the product entry of the columns with drho = 1 is 1 - Y_R (not the
 // mean state's Y_P): R is then the exact inverse for any state, and the limiter
 // keeps rho Y_R + rho Y_P - rho at round-off instead of feeding its round-off back.
-__device__ bool char_matrices(const OneStep &ph, const double *wb, double (&Lm)[5][5], double (&Rm)[5][5]) {
+// Field c only: row c of L into lr, column c of R into rc.
+__device__ __forceinline__ bool char_row_col(const OneStep &ph, const double *wb, int c, double (&lr)[5],
+                                             double (&rc)[5]) {
   Prim1 pr;
   const bool ok = prim1(ph, wb, pr);
   const double rho = pr.rho, u = pr.u, a = pr.a, g1 = ph.gamma - 1.0, q = ph.q_heat;
   const double dp[5] = {g1 * 0.5 * u * u, -g1 * u, g1, -g1 * q, 0.0};
   const double du[5] = {-u / rho, 1.0 / rho, 0.0, 0.0, 0.0};
   const double a2 = a * a;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    const double drho = c == 0 ? 1.0 : 0.0;
-    Lm[0][c] = (dp[c] - rho * a * du[c]) / (2.0 * a2);
-    Lm[1][c] = drho - dp[c] / a2;
-    Lm[4][c] = (dp[c] + rho * a * du[c]) / (2.0 * a2);
-  }
   const double YR = wb[3] / rho, YP = 1.0 - YR;
-  Lm[2][0] = -YR; Lm[2][1] = 0.0; Lm[2][2] = 0.0; Lm[2][3] = 1.0; Lm[2][4] = 0.0;
-  Lm[3][0] = -1.0; Lm[3][1] = 0.0; Lm[3][2] = 0.0; Lm[3][3] = 1.0; Lm[3][4] = 1.0;
+  const double l2[5] = {-YR, 0.0, 0.0, 1.0, 0.0};
+  const double l3[5] = {-1.0, 0.0, 0.0, 1.0, 1.0};
+  // the acoustic rows carry the sign of their wave speed u -+ a
+  const double sa = c == 0 ? -1.0 : 1.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double drho = k == 0 ? 1.0 : 0.0;
+    const double ac = (dp[k] + sa * rho * a * du[k]) / (2.0 * a2);
+    lr[k] = (c == 0 || c == 4) ? ac : c == 1 ? drho - dp[k] / a2 : c == 2 ? l2[k] : l3[k];
+  }
   // columns: acoustic -, entropy, reactant, species sum, acoustic +
   const double hk = 0.5 * u * u + q * YR;   // d(rho E)/d rho at fixed u, p, Y
   const double ha = a2 / g1;
-  const double col[5][5] = {
-      {1.0, u - a, ha + hk - u * a, YR, YP},
-      {1.0, u, hk, YR, YP},
-      {0.0, 0.0, q, 1.0, -1.0},
-      {0.0, 0.0, 0.0, 0.0, 1.0},
-      {1.0, u + a, ha + hk + u * a, YR, YP}};
-#pragma unroll
-  for (int k = 0; k < 5; ++k)
-#pragma unroll
-    for (int r = 0; r < 5; ++r) Rm[r][k] = col[k][r];
+  if (c == 0 || c == 4) {
+    rc[0] = 1.0; rc[1] = u + sa * a; rc[2] = ha + hk + sa * u * a; rc[3] = YR; rc[4] = YP;
+  } else if (c == 1) {
+    rc[0] = 1.0; rc[1] = u; rc[2] = hk; rc[3] = YR; rc[4] = YP;
+  } else if (c == 2) {
+    rc[0] = 0.0; rc[1] = 0.0; rc[2] = q; rc[3] = 1.0; rc[4] = -1.0;
+  } else {
+    rc[0] = 0.0; rc[1] = 0.0; rc[2] = 0.0; rc[3] = 0.0; rc[4] = 1.0;
+  }
   return ok && a > 0.0;
 }
 
@@ -392,90 +394,91 @@ __device__ __forceinline__ void indicator_body(const LimiterArgs &a, int blk) {
   }
 }
 
-// Characteristic WENO of Eq. (9)-(10) for a troubled element, into the side buffer.
+// The simple WENO reconstruction of Eq. (9)-(10) of one characteristic field (L row
+// lr): the limited modes vl of that field in the cell.
 template <int M>
-__device__ __forceinline__ void weno_cell(const LimiterArgs &a, int e, const double (&u)[5][M],
-                                          const double (&nbL)[5][M], const double (&nbR)[5][M]) {
-  double wb[5];
+__device__ __forceinline__ void weno_field(const LimiterArgs &a, const double (&lr)[5], const double (&u)[5][M],
+                                           const double (&nbL)[5][M], const double (&nbR)[5][M], double (&vl)[M]) {
+  double vc[M], vL[M], vR[M];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) wb[v] = u[v][0];
-  double Lm[5][5], Rm[5][5];
-  if (!char_matrices(a.ph, wb, Lm, Rm)) atomicOr(a.err, (int)kErrState);
-  double wl[5][M];
+  for (int j = 0; j < M; ++j) {
+    double x0 = 0.0, xl = 0.0, xr = 0.0;
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
-#pragma unroll
-    for (int j = 0; j < M; ++j) wl[v][j] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    double vc[M], vL[M], vR[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      double x0 = 0.0, xl = 0.0, xr = 0.0;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        x0 += Lm[c][v] * u[v][j];
-        xl += Lm[c][v] * nbL[v][j];
-        xr += Lm[c][v] * nbR[v][j];
-      }
-      vc[j] = x0; vL[j] = xl; vR[j] = xr;
+    for (int v = 0; v < 5; ++v) {
+      x0 += lr[v] * u[v][j];
+      xl += lr[v] * nbL[v][j];
+      xr += lr[v] * nbR[v][j];
     }
-    // re-expand the neighbours in the cell's coordinate and reset their mean
-    double tL[M], tR[M];
-#pragma unroll
-    for (int k2 = 0; k2 < M; ++k2) {
-      double sl = 0.0, sr = 0.0;
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        sl += a.Tl[k2][j] * vL[j];
-        sr += a.Tr[k2][j] * vR[j];
-      }
-      tL[k2] = sl; tR[k2] = sr;
-    }
-    tL[0] = vc[0];
-    tR[0] = vc[0];
-    double beta[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int p = 0; p < M; ++p)
-#pragma unroll
-      for (int r = 0; r < M; ++r) {
-        beta[0] += tL[p] * a.Bm[p][r] * tL[r];
-        beta[1] += vc[p] * a.Bm[p][r] * vc[r];
-        beta[2] += tR[p] * a.Bm[p][r] * tR[r];
-      }
-    double wbar[3], sum = 0.0;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const double d = a.eps + beta[s];
-      wbar[s] = a.gam[s] / (d * d);
-      sum += wbar[s];
-    }
-    const double om0 = wbar[0] / sum, om1 = wbar[1] / sum, om2 = wbar[2] / sum;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const double vl = om0 * tL[j] + om1 * vc[j] + om2 * tR[j];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) wl[v][j] += Rm[v][c] * vl;
-    }
+    vc[j] = x0; vL[j] = xl; vR[j] = xr;
   }
+  // re-expand the neighbours in the cell's coordinate and reset their mean
+  double tL[M], tR[M];
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
+  for (int k2 = 0; k2 < M; ++k2) {
+    double sl = 0.0, sr = 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) a.wlim[sidx(e, v * M + j, 5 * M)] = wl[v][j];
+    for (int j = 0; j < M; ++j) {
+      sl += a.Tl[k2][j] * vL[j];
+      sr += a.Tr[k2][j] * vR[j];
+    }
+    tL[k2] = sl; tR[k2] = sr;
+  }
+  tL[0] = vc[0];
+  tR[0] = vc[0];
+  double beta[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < M; ++p)
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      beta[0] += tL[p] * a.Bm[p][r] * tL[r];
+      beta[1] += vc[p] * a.Bm[p][r] * vc[r];
+      beta[2] += tR[p] * a.Bm[p][r] * tR[r];
+    }
+  double wbar[3], sum = 0.0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const double d = a.eps + beta[s];
+    wbar[s] = a.gam[s] / (d * d);
+    sum += wbar[s];
+  }
+  const double om0 = wbar[0] / sum, om1 = wbar[1] / sum, om2 = wbar[2] / sum;
+#pragma unroll
+  for (int j = 0; j < M; ++j) vl[j] = om0 * tL[j] + om1 * vc[j] + om2 * tR[j];
 }
 
-
-// Pass 2, the listed elements only (grid-stride over the list).
+// Pass 2, the listed elements only (grid-stride over the list), characteristic WENO
+// into the side buffer.  A group of kWenoGroup lanes per troubled element: lane c < 5
+// limits characteristic field c, and w_lim = sum_c R[:, c] v_c^lim is summed across
+// the group in a fixed butterfly order (lanes 5..7 add zeros).
 template <int M>
 __device__ __forceinline__ void weno_body(const LimiterArgs &a, int blk, int nblk) {
+  constexpr int G = kWenoGroup, per = kWenoBlock / G;
   const unsigned cnt = a.tcount[a.stage];
-  if ((unsigned)(blk * kWenoBlock) >= cnt) return;
+  if ((unsigned)(blk * per) >= cnt) return;
   const long long n = *a.step;
-  for (unsigned idx = blk * kWenoBlock + threadIdx.x; idx < cnt; idx += nblk * kWenoBlock) {
+  const int c = threadIdx.x % G;
+  const int cf = c < 5 ? c : 4;
+  // idx is uniform within a group, so the shuffles below see all G lanes
+  for (unsigned idx = blk * per + threadIdx.x / G; idx < cnt; idx += nblk * per) {
     const int e = a.tlist[idx];
     double u[5][M], nbL[5][M], nbR[5][M];
     limiter_stencil<M>(a, n, e, u, nbL, nbR);
-    weno_cell<M>(a, e, u, nbL, nbR);
+    double wb[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) wb[v] = u[v][0];
+    double lr[5], rc[5];
+    if (!char_row_col(a.ph, wb, cf, lr, rc) && c == 0) atomicOr(a.err, (int)kErrState);
+    double vl[M];
+    weno_field<M>(a, lr, u, nbL, nbR, vl);
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        double part = c < 5 ? rc[v] * vl[j] : 0.0;
+#pragma unroll
+        for (int m = 1; m < G; m <<= 1) part += __shfl_xor(part, m, G);
+        if (c == v) a.wlim[sidx(e, v * M + j, 5 * M)] = part;
+      }
   }
 }
 

@@ -174,12 +174,14 @@ enum ErrBits { kErrState = 1, kErrNewton = 2 };
 
 constexpr int kLimBlock = 128;
 constexpr int kWenoBlock = 64;
+constexpr int kWenoGroup = 8;     // lanes per troubled element in the WENO pass
 constexpr int kScatterBlock = 256;
 // Workgroups of the WENO and scatter passes, which walk the list of troubled
 // elements with a grid stride.
 __host__ __device__ inline int weno_blocks(int E) {
-  const int b = (E + kWenoBlock - 1) / kWenoBlock;
-  return b < 256 ? b : 256;
+  constexpr int per = kWenoBlock / kWenoGroup;
+  const int b = (E + per - 1) / per;
+  return b < 1024 ? b : 1024;
 }
 __host__ __device__ inline int scatter_blocks(int E) {
   const int b = (E + kScatterBlock - 1) / kScatterBlock;
