@@ -3,8 +3,8 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c2]
 
 A "step" is one full SSP-RK3 time step: three fused stage launches (DG right-hand
-side, chemistry, AT fluxes at PE interfaces, RK update, history publish) plus,
-for the limited workload, the KXRCF/AT-WENO limiter after every stage.  The
+side, chemistry, AT fluxes at PE interfaces, RK update, history publish; for the
+limited workload also the KXRCF/AT-WENO limiter of the stage's output).  The
 metric counts scalar DOF updates (E (N_p+1) (3+N_s) per stage) per second, with
 the inputs resident in HBM before the timed region starts.
 
@@ -80,10 +80,12 @@ def pmc_probe(args):
 def euler_stage_bytes(case) -> float:
     """Algorithmic HBM bytes of one stage launch, averaged over the three stages:
     stage 1 reads w^n and writes w^(1) (16 B/DOF); stages 2 and 3 read w^n and
-    w^(s) and write w^(s+1) (24 B/DOF)."""
+    w^(s) and write w^(s+1) (24 B/DOF); with the limiter (inside the same kernel)
+    one troubled-cell flag byte per element."""
     from workloads import gen
 
-    return gen.dof(case) * 8.0 * (2 + 3 + 3) / 3.0
+    flags = case["disc"]["n_elem"] if case["disc"].get("limiter") else 0
+    return gen.dof(case) * 8.0 * (2 + 3 + 3) / 3.0 + flags
 
 
 def detailed_stage_flops(case) -> float:

@@ -171,8 +171,8 @@ int32_t adg_n_interfaces(const adg_solver *s);
 /* Enqueue n_steps steps like adg_step and time every kernel launch with HIP
    events on the solver's stream.  ms_out[i] receives the mean duration in ms
    of kernel class i and launches_out[i] the launch count; n_classes is the
-   array length (classes: 0 stage kernel, 1 troubled-cell indicator, 2 limiter
-   scatter, 3 WENO of the troubled cells).
+   array length (class 0: the stage kernel, which includes the limiter of a
+   limited problem; there is one launch per RK stage).
    Synchronises. */
 adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *launches_out, int32_t n_classes);
 
@@ -201,8 +201,8 @@ const char *adg_last_error(const adg_solver *s);
  *
  * Many ADG problems of different sizes, orders, PE layouts and delay models
  * advance together: every RK stage of a time step is one batched launch for
- * all detailed-chemistry instances (plus one per order and flux for the
- * one-step model, and the limiter launches of limited instances), so small
+ * all detailed-chemistry instances (plus one per order, flux and limiter
+ * choice for the one-step model), so small
  * instances fill the device together.  Each workgroup works on one instance
  * with that instance's own arguments: an instance's result does not depend on
  * what else is in the batch (alone and in the mix are bitwise identical for
@@ -270,9 +270,9 @@ adg_status adg_batch_get_state(adg_batch *b, int32_t slot, double *w, int64_t co
 adg_status adg_batch_set_graph(adg_batch *b, int32_t steps_per_graph);
 
 /* Enqueue n_steps steps with HIP events around every launch; ms_out[c] is the
-   mean duration of launch class c (0 detailed stage, 1 one-step stage,
-   2 troubled-cell indicator, 3 WENO of the troubled cells, 4 limiter scatter)
-   and launches_out[c] its count.  Synchronises. */
+   mean duration of launch class c (0 detailed-chemistry stage, 1 one-step
+   stage, including the limiter of limited instances) and launches_out[c] its
+   count.  Synchronises. */
 adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int64_t *launches_out,
                              int32_t n_classes);
 

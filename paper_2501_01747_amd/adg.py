@@ -24,8 +24,8 @@ HOST, DEVICE = 0, 1
 FP64, MIXED_FP32 = 0, 1
 KXRCF, MINMOD = 0, 1
 SSPRK3, RK2, LSERK4 = 0, 1, 2
-PROFILE_CLASSES = ("stage", "limiter", "limiter_scatter", "weno")
-BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage", "limiter", "weno", "limiter_scatter")
+PROFILE_CLASSES = ("stage",)
+BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")

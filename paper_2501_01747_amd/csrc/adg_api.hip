@@ -62,39 +62,35 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
   const int in_buf[3] = {0, 1, 2}, out_buf[3] = {1, 2, 0};
   for (int stage = 0; stage < S; ++stage) {
     const RkStage r = rk_stage(rk, stage);
-    // Shu-Osher SSP-RK3: w^n in buffer 0, stages in 1 and 2, the last stage back into 0.
-    // 2N schemes: the state alternates between buffers 0 and 1 (s->cur holds it at the
-    // start of the step), the register is buffer 2.
-    const int bi = r.two_n ? (s->cur + stage) % 2 : in_buf[stage];
-    const int bo = r.two_n ? (s->cur + stage + 1) % 2 : out_buf[stage];
+    // Shu-Osher SSP-RK3: w^n in buffer 0, stages in 1 and 2, the last stage back into 0;
+    // with the limiter no stage may write a buffer it reads, so w^n alternates between
+    // buffers 0 and 1 (s->cur), stage 1 goes to the other one, stage 2 to buffer 2 and
+    // stage 3 to the other one again.  2N schemes: the state alternates between buffers
+    // 0 and 1 (s->cur holds it at the start of the step), the register is buffer 2
+    // (with the limiter, buffers 2 and 3 alternate the same way).
+    const bool alt = !r.two_n && s->P.disc.limiter && s->P.phys.model == ADG_ONESTEP;
+    const int lim_in[3] = {s->cur, 1 - s->cur, 2}, lim_out[3] = {1 - s->cur, 2, 1 - s->cur};
+    const int bi = r.two_n ? (s->cur + stage) % 2 : alt ? lim_in[stage] : in_buf[stage];
+    const int bo = r.two_n ? (s->cur + stage + 1) % 2 : alt ? lim_out[stage] : out_buf[stage];
     const bool last = stage == S - 1;
     if (s->P.phys.model == ADG_ONESTEP) {
+      const bool lim = s->P.disc.limiter != 0;
       EulerArgs a = s->P.ea;
-      a.w0 = s->P.W[0];
+      a.alt = 0;   // buffers chosen here (the batched kernels choose them by step parity)
+      a.w0 = s->P.W[alt ? s->cur : 0];
       a.ws = s->P.W[bi];
       a.wout = s->P.W[bo];
+      if (lim && r.two_n) {
+        // the two registers alternate like the state: read W[2 + bi], write W[2 + bo]
+        a.kbuf = s->P.W[2 + bi];
+        a.kout = s->P.W[2 + bo];
+      }
       a.stage = stage;
       a.rk = r;
-      a.advance = last && !s->P.disc.limiter;
+      a.advance = last;
       if (timer) timer(s, 0, true);
-      HIP_TRY(s, launch_euler_stage(M, s->P.disc.flux, a, st));
+      HIP_TRY(s, launch_euler_stage(M, s->P.disc.flux, a, lim ? &s->P.la : nullptr, st));
       if (timer) timer(s, 0, false);
-      if (s->P.disc.limiter) {
-        LimiterArgs l = s->P.la;
-        l.w = s->P.W[bo];
-        l.stage = stage;
-        l.advance = 0;
-        if (timer) timer(s, 1, true);
-        HIP_TRY(s, launch_limiter(M, l, st));
-        if (timer) timer(s, 1, false);
-        if (timer) timer(s, 3, true);
-        HIP_TRY(s, launch_weno(M, l, st));
-        if (timer) timer(s, 3, false);
-        l.advance = last;
-        if (timer) timer(s, 2, true);
-        HIP_TRY(s, launch_limiter_scatter(M, l, st));
-        if (timer) timer(s, 2, false);
-      }
     } else {
       NsArgs a = s->P.na;
       a.w0 = s->P.W[0];
@@ -109,6 +105,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
     }
   }
   if (rk_stage(rk, 0).two_n) s->cur = (s->cur + S) % 2;
+  else if (s->P.disc.limiter && s->P.phys.model == ADG_ONESTEP) s->cur = 1 - s->cur;
   return ADG_OK;
 }
 
@@ -193,7 +190,7 @@ adg_status adg_step(adg_solver *s, int32_t n_steps) {
       if (rc != ADG_OK) return rc;
     }
     // the graph starts from the buffer it was captured with; a plain step realigns
-    // the alternating state buffer of the 2N schemes when needed
+    // the alternating state buffer (2N schemes, limited Shu-Osher) when needed
     int left = n_steps;
     while (left > 0) {
       if (left >= s->graph_steps && s->cur == s->graph_cur) {
@@ -279,14 +276,7 @@ adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *
   }
   // the launch classes of one step, in order
   std::vector<int> order;
-  for (int stage = 0; stage < s->P.lay.S; ++stage) {
-    order.push_back(0);
-    if (s->P.phys.model == ADG_ONESTEP && s->P.disc.limiter) {
-      order.push_back(1);
-      order.push_back(3);
-      order.push_back(2);
-    }
-  }
+  for (int stage = 0; stage < s->P.lay.S; ++stage) order.push_back(0);
   HIP_TRY(s, hipStreamSynchronize(s->stream));
   std::vector<double> sum(n_classes, 0.0);
   std::vector<int64_t> cnt(n_classes, 0);

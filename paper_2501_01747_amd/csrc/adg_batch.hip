@@ -43,8 +43,9 @@ struct Slot {
 constexpr int kBatchMechs = 16;
 
 struct Group {
-  int kind;  // 0 detailed stage, 1 one-step stage, 2 indicator, 3 WENO, 4 scatter
+  int kind;  // 0 detailed stage, 1 one-step stage
   int M, flux;
+  bool lim;  // one-step instances with the limiter (in the stage kernel)
   int off, n;  // range of the work list
 };
 
@@ -152,12 +153,12 @@ void heap_give(adg_batch *b, size_t off, size_t bytes) {
 }
 
 // Work list: detailed instances first (one group), then one-step instances by
-// (kind, order, flux).  Entries of one instance are consecutive.
+// (order, flux, limiter).  Entries of one instance are consecutive.
 void rebuild_tiles(adg_batch *b) {
   b->groups.clear();
   b->h_tiles.clear();
-  auto add_group = [&](int kind, int M, int flux, auto pick, auto nblocks) {
-    Group g{kind, M, flux, (int)b->h_tiles.size(), 0};
+  auto add_group = [&](int kind, int M, int flux, bool lim, auto pick, auto nblocks) {
+    Group g{kind, M, flux, lim, (int)b->h_tiles.size(), 0};
     for (int i = 0; i < (int)b->slots.size(); ++i) {
       const Slot &s = b->slots[i];
       if (!s.used || !pick(s)) continue;
@@ -171,7 +172,7 @@ void rebuild_tiles(adg_batch *b) {
     for (int p = 0; p < g.n; ++p) b->h_tiles[g.off + p] = run[xcd_item(p, g.n)];
     if (g.n > 0) b->groups.push_back(g);
   };
-  add_group(0, 0, 0, [](const Slot &s) { return s.P.phys.model == ADG_DETAILED; },
+  add_group(0, 0, 0, false, [](const Slot &s) { return s.P.phys.model == ADG_DETAILED; },
             [&](const Slot &s) { return (s.P.lay.E + b->tile_elems - 1) / b->tile_elems; });
   if (!b->groups.empty() && b->groups[0].kind == 0) {
     int mm = 2;
@@ -179,15 +180,15 @@ void rebuild_tiles(adg_batch *b) {
       if (s.used && s.P.phys.model == ADG_DETAILED) mm = std::max(mm, s.P.lay.M);
     b->groups[0].M = mm;
   }
-  for (int kind = 1; kind <= 4; ++kind)
-    for (int M = 2; M <= kMaxM; ++M)
-      for (int flux = 0; flux <= (kind == 1 ? 1 : 0); ++flux)
-        add_group(kind, M, flux,
+  for (int M = 2; M <= kMaxM; ++M)
+    for (int flux = 0; flux <= 1; ++flux)
+      for (int lim = 0; lim <= 1; ++lim)
+        add_group(1, M, flux, lim != 0,
                   [&](const Slot &s) {
-                    return s.P.phys.model == ADG_ONESTEP && s.P.lay.M == M && (kind != 1 || s.P.disc.flux == flux) &&
-                           (kind == 1 || s.P.disc.limiter);
+                    return s.P.phys.model == ADG_ONESTEP && s.P.lay.M == M && s.P.disc.flux == flux &&
+                           (s.P.disc.limiter != 0) == (lim != 0);
                   },
-                  [&](const Slot &s) { return euler_batch_blocks(kind - 1, s.P.lay.E); });
+                  [&](const Slot &s) { return euler_blocks(s.P.lay.E, lim != 0); });
 }
 
 adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
@@ -202,7 +203,7 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
         BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->precision == ADG_MIXED_FP32, g.M,
                                 b->tile_elems, st));
       } else {
-        BHIP(b, launch_euler_batch(g.kind - 1, g.M, g.flux, b->d_eu, b->d_tiles + g.off, g.n, stage, st));
+        BHIP(b, launch_euler_batch(g.M, g.flux, g.lim, b->d_eu, b->d_tiles + g.off, g.n, stage, st));
       }
       if (timed) {
         BHIP(b, hipEventCreate(&e1));
@@ -379,30 +380,20 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
     std::memset(&es, 0, sizeof es);
     const int in_buf[3] = {0, 1, 2}, out_buf[3] = {1, 2, 0};
     for (int st = 0; st < 3; ++st) {
-      EulerArgs a = P.ea;
+      EulerArgs a = P.ea;   // with the limiter a.alt is set: the kernel picks the buffers
       a.w0 = P.W[0];
       a.ws = P.W[in_buf[st]];
       a.wout = P.W[out_buf[st]];
       a.stage = st;
       a.rk = rk_stage(ADG_SSPRK3, st);
-      a.advance = st == 2 && !P.disc.limiter;
+      a.advance = st == 2;
       a.step = P.step;
       a.err = P.err;
       a.done = P.done;
       a.target = s.target;
       es.st[st] = a;
-      if (P.disc.limiter) {
-        LimiterArgs l = P.la;
-        l.w = P.W[out_buf[st]];
-        l.stage = st;
-        l.advance = st == 2;
-        l.step = P.step;
-        l.err = P.err;
-        l.done = P.done;
-        l.target = s.target;
-        es.lim[st] = l;
-      }
     }
+    if (P.disc.limiter) es.lim = P.la;
     he = hipMemcpy(b->d_eu + slot, &es, sizeof es, hipMemcpyHostToDevice);
     if (he != hipSuccess) return fail_release(he, "descriptor upload");
   }
@@ -478,10 +469,18 @@ adg_status adg_batch_get_state(adg_batch *b, int32_t slot, double *w, int64_t co
   const Layout &L = P.lay;
   const int VM = L.V * L.M;
   if (count != (int64_t)L.E * VM) return bfail(b, ADG_ERR_ARG, "state size mismatch");
+  // with the limiter the state lives in buffer (step count) mod 2
+  const double *src = P.W[0];
+  if (P.ea.alt) {
+    long long n = 0;
+    BHIP(b, hipStreamSynchronize(b->stream));
+    BHIP(b, hipMemcpy(&n, P.step, sizeof n, hipMemcpyDeviceToHost));
+    src = P.W[n & 1];
+  }
   if (where == ADG_HOST) {
-    BHIP(b, download_state_host(P, P.W[0], w, b->stream));
+    BHIP(b, download_state_host(P, src, w, b->stream));
   } else if (where == ADG_DEVICE) {
-    BHIP(b, launch_from_planes(P.W[0], w, L.E, VM, b->stream));
+    BHIP(b, launch_from_planes(src, w, L.E, VM, b->stream));
   } else {
     return bfail(b, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
   }

@@ -12,7 +12,6 @@ constexpr int kMaxQ = 5;      // Gauss points = N_p + 1
 constexpr int kMaxL = 8;      // admissible delays
 constexpr int kMaxAT = 6;     // AT order q
 constexpr int kEulerBlock = 256;
-constexpr int kWaveElems = 62;   // elements owned by one wavefront of the Euler stage kernel
 
 // Delay model of Sec. 4 (CAA / SAA) and the start-up clamp k <= n - q + 1.
 struct DelayParams {
@@ -117,7 +116,14 @@ struct EulerArgs {
   int periodic;
   int stage;
   RkStage rk;
-  double *kbuf;         // 2N register (2N schemes)
+  double *kbuf;         // 2N register read by this stage (2N schemes)
+  double *kout;         // 2N register written by this stage (kbuf itself without the limiter)
+  // batched Shu-Osher stages with the limiter: w^n lives in W[n mod 2] (n = the step
+  // counter), stage 1 writes W[1 - n mod 2], stage 2 W[2], stage 3 W[1 - n mod 2], so
+  // no stage writes a buffer it reads (the kernel then ignores w0, ws and wout; the
+  // single-problem solver passes the same buffers explicitly)
+  int alt;
+  double *W[3];
   int store_U;          // publish boundary-element outputs for the limiter
   double dt;
   double two_over_dx;
@@ -127,32 +133,16 @@ struct EulerArgs {
   Tables tb;
 };
 
+// Constants of the troubled-cell indicator and the characteristic WENO limiter
+// (Sec. 3.3), which run inside the stage kernel of a limited problem.
 struct LimiterArgs {
-  double *w;            // unlimited stage output, limited in place by the scatter pass
-  double *wlim;         // limited values of troubled cells
-  int8_t *flags;        // [E]
-  int *tlist;           // [E] troubled elements of the current stage, in any order
-  unsigned *tcount;     // [nstages] list lengths, one per RK stage
-  unsigned long long *flag_count;
-  const int *face_if;
-  long long *step;
-  unsigned *done;
-  int advance;
-  int *err;
-  long long target;
-  int E;
-  int periodic;
-  int stage;
-  int nstages;          // RK stages per step (list lengths, one per stage)
+  int8_t *flags;        // [E] troubled flags of the latest stage
+  unsigned long long *flag_count;   // troubled (element, stage) pairs since set_state
   double kx_h;          // dx^((N_p+1)/2)
   int indicator;        // ADG_KXRCF | ADG_MINMOD
   double tvb_mh2;       // M dx^2 of the TVB minmod test
   double gam[3];
   double eps;
-  OneStep ph;
-  DelayParams dl;
-  RingParams ring;
-  Tables tb;
   double Bm[kMaxM][kMaxM];    // smoothness-indicator quadratic form
   double Tl[kMaxM][kMaxM];    // re-expansion of the left neighbour in the cell
   double Tr[kMaxM][kMaxM];    // re-expansion of the right neighbour
@@ -172,40 +162,28 @@ __host__ __device__ inline int xcd_item(int b, int n) {
 
 enum ErrBits { kErrState = 1, kErrNewton = 2 };
 
-constexpr int kLimBlock = 128;
-constexpr int kWenoBlock = 64;
-constexpr int kWenoGroup = 8;     // lanes per troubled element in the WENO pass
-constexpr int kScatterBlock = 256;
-// Workgroups of the WENO and scatter passes, which walk the list of troubled
-// elements with a grid stride.
-__host__ __device__ inline int weno_blocks(int E) {
-  constexpr int per = kWenoBlock / kWenoGroup;
-  const int b = (E + per - 1) / per;
-  return b < 1024 ? b : 1024;
-}
-__host__ __device__ inline int scatter_blocks(int E) {
-  const int b = (E + kScatterBlock - 1) / kScatterBlock;
-  return b < 128 ? b : 128;
-}
-
-// Argument blocks of one instance of the one-step model in a batch, per stage.
+// Argument blocks of one instance of the one-step model in a batch: one per stage,
+// and the limiter constants.
 struct EulerSet {
   EulerArgs st[3];
-  LimiterArgs lim[3];
+  LimiterArgs lim;
 };
 
 // Kernel launchers (defined in the .hip files).
-hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, hipStream_t s);
-hipError_t launch_limiter(int M, const LimiterArgs &a, hipStream_t s);
-hipError_t launch_weno(int M, const LimiterArgs &a, hipStream_t s);
-hipError_t launch_limiter_scatter(int M, const LimiterArgs &a, hipStream_t s);
-// Batched one-step launches over a work list of (instance, block) entries, all of
-// order M: kind 0 stage kernel (flux selects Rusanov/HLLC), 1 indicator, 2 WENO of
-// the troubled elements, 3 scatter.
-hipError_t launch_euler_batch(int kind, int M, int flux, const EulerSet *sets, const int2 *tiles, int ntiles,
+// One stage of the one-step model; `lim` (null = no limiter) adds the limiter to
+// the same kernel.
+hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, const LimiterArgs *lim, hipStream_t s);
+// Batched one-step stage over a work list of (instance, block) entries, all of
+// order M, flux `flux` (Rusanov/HLLC) and limiter choice `lim`.
+hipError_t launch_euler_batch(int M, int flux, bool lim, const EulerSet *sets, const int2 *tiles, int ntiles,
                               int stage, hipStream_t s);
-// Workgroups per instance of E elements for each kind.
-int euler_batch_blocks(int kind, int E);
+// Workgroups of the one-step stage kernel for E elements: a wavefront owns 62
+// elements, 60 with the limiter (two halo lanes on each side).
+__host__ __device__ inline int euler_blocks(int E, bool lim) {
+  const int we = lim ? 60 : 62;
+  const int waves = (E + we - 1) / we;
+  return (waves + kEulerBlock / 64 - 1) / (kEulerBlock / 64);
+}
 hipError_t launch_to_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
 hipError_t launch_from_planes(const double *src, double *dst, int E, int VM, hipStream_t s);
 

@@ -170,10 +170,11 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   (void)visc;
   size_t nstate = state_doubles(L.E, L.V * L.M) * sizeof(double);
   size_t off = 0;
-  L.state = off;  off += 3 * align256(nstate);
-  L.wlim = off;   off += d->limiter ? align256(nstate) : 0;
+  // a 2N scheme with the limiter keeps two registers (each stage writes the one it
+  // does not read)
+  L.nbuf = (d->limiter && ph->model == ADG_ONESTEP && rk_stage(d->rk, 0).two_n) ? 4 : 3;
+  L.state = off;  off += L.nbuf * align256(nstate);
   L.flags = off;  off += align256((size_t)L.E);
-  L.tlist = off;  off += d->limiter ? align256(sizeof(int) * (size_t)L.E) : 0;
   L.face_if = off; off += align256(sizeof(int) * (L.E + 1));
   L.counters = off; off += 256;
   L.ring = off;   off += align256(sizeof(double) * (size_t)L.D * L.S * (L.nif > 0 ? L.nif : 1) * L.rec);
@@ -201,8 +202,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
   P.lay = L;
   P.base = base;
   size_t nstate = state_doubles(L.E, L.V * L.M) * sizeof(double);
-  for (int b = 0; b < 3; ++b) P.W[b] = (double *)(base + L.state + b * align256(nstate));
-  P.Wlim = disc->limiter ? (double *)(base + L.wlim) : nullptr;
+  for (int b = 0; b < L.nbuf; ++b) P.W[b] = (double *)(base + L.state + b * align256(nstate));
   P.flags = (int8_t *)(base + L.flags);
   P.face_if = (int *)(base + L.face_if);
   P.step = (long long *)(base + L.counters);
@@ -261,6 +261,9 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
     a.periodic = periodic;
     a.store_U = disc->limiter && L.nif > 0;
     a.kbuf = P.W[2];
+    a.kout = P.W[2];
+    a.alt = disc->limiter && !rk_stage(disc->rk, 0).two_n;
+    for (int b = 0; b < 3; ++b) a.W[b] = P.W[b];
     a.rk = rk_stage(disc->rk, 0);
     a.dt = disc->dt;
     a.two_over_dx = 2.0 / dx;
@@ -270,28 +273,13 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
     a.tb = tb;
     if (disc->limiter) {
       LimiterArgs &l = P.la;
-      l.wlim = P.Wlim;
       l.flags = P.flags;
       l.flag_count = P.flag_count;
-      l.tlist = (int *)(base + L.tlist);
-      l.tcount = (unsigned *)(base + L.counters + 224);
-      l.face_if = P.face_if;
-      l.step = P.step;
-      l.done = P.done;
-      l.err = P.err;
-      l.target = kNoTarget;
-      l.E = L.E;
-      l.periodic = periodic;
       l.kx_h = std::pow(dx, 0.5 * (disc->order_p + 1));
-      l.nstages = L.S;
       l.indicator = disc->indicator;
       l.tvb_mh2 = disc->tvb_m * dx * dx;
       for (int k = 0; k < 3; ++k) l.gam[k] = disc->weno_gamma[k];
       l.eps = disc->weno_eps;
-      l.ph = a.ph;
-      l.dl = dl;
-      l.ring = rp;
-      l.tb = tb;
       build_limiter_tables(L.M, l);
     }
   } else {

@@ -17,7 +17,8 @@ constexpr long long kNoTarget = 0x7fffffffffffffffLL;
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t state, wlim, flags, tlist, face_if, counters, ring, sched, mech, total;
+  size_t state, flags, face_if, counters, ring, sched, mech, total;
+  int nbuf;             // state-sized buffers (3; 4 for a 2N scheme with the limiter)
   int nif, nfaces, D, rec, q, V, M, E;
   int S;                // RK stages per step
   int off_F, off_Wc, off_U;
@@ -29,8 +30,7 @@ struct Problem {
   adg_async as{};
   Layout lay{};
   char *base = nullptr;
-  double *W[3] = {nullptr, nullptr, nullptr};
-  double *Wlim = nullptr;
+  double *W[4] = {nullptr, nullptr, nullptr, nullptr};
   int8_t *flags = nullptr;
   int *face_if = nullptr;
   long long *step = nullptr;

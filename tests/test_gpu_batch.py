@@ -215,6 +215,22 @@ def test_step_targets(adg, mech):
     b.close()
 
 
+def test_limited_instance_stops_at_odd_step_count(adg):
+    """With the limiter an instance's state alternates between two buffers by step parity;
+    instances stopped at odd and even step counts both return their own state."""
+    c, w = gen.case_c2(E=256, n_pe=8, length=8.0, shock_x=2.0)
+    b = make_batch(adg, [(c, w), (c, w)])
+    sa = b.add(c, w, n_steps=5)
+    sb = b.add(c, w)
+    b.step(8)
+    st, er = b.poll()
+    assert st[sa] == 5 and st[sb] == 8 and not er[sa] and not er[sb]
+    for sl, n in ((sa, 5), (sb, 8)):
+        ref = single(adg, c, w, n)
+        assert np.max(np.abs(b.state(sl) - ref)) <= 1e-13 * np.abs(ref).max(), n
+    b.close()
+
+
 def test_graph_replay_matches_plain_launches(adg, mech):
     cases = mixed_cases(mech)[:3] + onestep_cases()[2:3]
     res = []
