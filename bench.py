@@ -301,6 +301,7 @@ def main():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--graph", type=int, default=10, help="time steps per captured HIP graph (0 = plain launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured copy / FP64 ceilings")
     ap.add_argument("--sweep-euler", action="store_true",
                     help="print the Euler stage-kernel size sweep instead of the benchmark line")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -403,6 +404,15 @@ def main():
         "kernel_ms": {k: v[0] for k, v in prof.items()},
     }
     s.close()
+    if not args.no_peaks:
+        # the device's measured ceilings (project-written copy and FP64 FMA kernels), beside
+        # the published peaks the roofline fraction uses
+        from paper_2501_01747_amd import peaks
+
+        mp = peaks.measure()
+        out["measured_peaks"] = mp
+        ceiling = mp["fp64_vector_TFLOPs"] if detailed else mp["copy_GBps"]
+        out["roofline"]["frac_of_measured"] = out["roofline"]["achieved"] / ceiling
     if not args.no_batched and detailed:
         bb = bench_batched(args.batch_steps, 5, args.graph, args.precision)
         out["batched_mixed"] = bb

@@ -60,3 +60,15 @@ def test_batch_sizing():
     assert nb % 256 == 0 and nb >= adg.Problem(case).workspace_bytes()
     bad = dict(case, disc=dict(case["disc"], order_p=0))
     assert adg.Batch.instance_bytes(bad) == 0
+
+
+def test_peaks_library_exports_its_header():
+    src = open(os.path.join(ROOT, "include", "adg_peaks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    syms = sorted(set(re.findall(r"\b(adg_[a-z0-9_]+)\s*\(", src)))
+    assert syms == ["adg_peak_copy", "adg_peak_fp64", "adg_peak_fp64_out_bytes"]
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2501_01747_amd", "libadg_peaks.so"))
+    assert all(hasattr(lib, s) for s in syms)
+    from paper_2501_01747_amd import peaks
+
+    assert sorted(peaks.EXPORTED) == syms
