@@ -389,7 +389,8 @@ def main():
         achieved = nbytes / (stage_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(traffic_key, kernel_src),
-                "kernel": "euler_stage_kernel", "launch_ms": stage_ms, "bytes_per_launch": nbytes}
+                "kernel": "euler_lim_kernel" if case["disc"].get("limiter") else "euler_stage_kernel",
+                "launch_ms": stage_ms, "bytes_per_launch": nbytes}
     d = case["disc"]
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,

@@ -182,14 +182,20 @@ adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph);
 
 /* Choose the stage kernel's work decomposition by measurement: for the
    detailed-chemistry model, the tile size (4 or 8 elements) and workgroup size
-   (256 or 512 threads) of the stage kernel, each candidate timed over n_reps
+   (256, 512 or 1024 threads) of the stage kernel, each candidate timed over n_reps
    launches of the first RK stage on the current state; later steps use the
    fastest.  The timed launches only rewrite the first stage buffer and the
    current level's first-stage history, which the next step recomputes, so the
    solution is unchanged.  *choice (optional) receives the chosen candidate
-   (0: 8/512, 1: 8/256, 2: 4/256, 3: 4/512; always 0 for the one-step model,
+   (0: 8/512, 1: 8/256, 2: 4/256, 3: 4/512, 4: 8/1024; always 0 for the one-step model,
    whose kernel has one decomposition).  Synchronises. */
 adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice);
+
+/* Use work decomposition `config` (the numbering of adg_autotune; only 0 for
+   the one-step model) for the following steps.  ADG_ERR_ARG for any other
+   value.  The result of a step does not depend on the decomposition beyond
+   the order of floating-point sums across lanes. */
+adg_status adg_set_kernel_config(adg_solver *s, int32_t config);
 
 /* Release the solver (the caller's workspace is not freed). */
 void adg_destroy(adg_solver *s);

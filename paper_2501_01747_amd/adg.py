@@ -87,6 +87,7 @@ _sig = {
     "adg_n_interfaces": (C.c_int32, [C.c_void_p]),
     "adg_profile": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_int64), C.c_int32]),
     "adg_set_graph": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "adg_set_kernel_config": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_autotune": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_int32)]),
     "adg_destroy": (None, [C.c_void_p]),
     "adg_last_error": (C.c_char_p, [C.c_void_p]),
@@ -274,6 +275,10 @@ class Solver:
         c = C.c_int32(0)
         self._check(adg_autotune(self.h, int(n_reps), C.byref(c)))
         return c.value
+
+    def set_kernel_config(self, config: int):
+        """Use stage-kernel work decomposition `config` (adg_autotune's numbering)."""
+        self._check(adg_set_kernel_config(self.h, int(config)))
 
     def profile(self, n_steps: int) -> dict:
         k = len(PROFILE_CLASSES)

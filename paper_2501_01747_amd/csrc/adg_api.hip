@@ -339,6 +339,17 @@ adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
   return adg_sync(s);
 }
 
+adg_status adg_set_kernel_config(adg_solver *s, int32_t config) {
+  if (!s) return ADG_ERR_ARG;
+  const int n = s->P.phys.model == ADG_DETAILED ? kNsConfigs : 1;
+  if (config < 0 || config >= n) return fail(s, ADG_ERR_ARG, "no such work decomposition");
+  if (s->P.phys.model == ADG_DETAILED && config != s->ns_cfg) {
+    s->ns_cfg = config;
+    destroy_graph(s);
+  }
+  return ADG_OK;
+}
+
 adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph) {
   if (!s || steps_per_graph < 0) return ADG_ERR_ARG;
   s->graph_steps = steps_per_graph;

@@ -49,11 +49,11 @@ __device__ __forceinline__ void load_elem(const double *__restrict__ w, int E, i
 
 // Numerical flux at a face from its two traces; at PE interface i the AT flux.
 template <int FLUX>
-__device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int i, const double *wm,
+__device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int nmod, int i, const double *wm,
                                           const double *wp, double *F) {
   bool ok = numflux1<FLUX>(a.ph, wm, wp, F);
   if (i >= 0) {
-    double *rec = ring_rec(a.ring, n, a.stage, a.dl.nif, i) + a.ring.off_F;
+    double *rec = ring_at(a.ring, nmod, a.stage, a.dl.nif, i) + a.ring.off_F;
 #pragma unroll
     for (int v = 0; v < 5; ++v) rec[v] = F[v];
     const int k = eff_delay(a.dl, n, i);
@@ -66,7 +66,8 @@ __device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int i
           const int j = j0 + d;
           const bool in = j < a.dl.q;
           const double c = in ? at_weight(a.dl.q, k, j) : 0.0;
-          const double *h = ring_rec(a.ring, n - k - (in ? j : 0), a.stage, a.dl.nif, i) + a.ring.off_F;
+          const double *h = ring_at(a.ring, ring_slot(nmod, k + (in ? j : 0), a.ring.D), a.stage, a.dl.nif, i) +
+                            a.ring.off_F;
 #pragma unroll
           for (int v = 0; v < 5; ++v) acc[v] += c * h[v];
         }
@@ -141,26 +142,27 @@ __device__ __forceinline__ double trace_at(const double (&c)[M], int side) {
 }
 
 // Where the limiter of an owned element takes the neighbour across one face from:
-// the neighbouring lane's unlimited output (kind 0), the constant ghost equal to
-// the element's own mean at a transmissive end (kind 1), or at a PE interface i
-// with effective delay k > 0 the Eq. (11) AT combination of the unlimited outputs
-// that past levels published to the history ring: formed once into one of the
-// wavefront's LDS slots (kind 3), or, when the wavefront's slots are taken, read
-// from the ring at every use (kind 2).
+// LDS at base + v sv + j sj.  Either the neighbouring lane's unlimited output, or one
+// of the wavefront's slots holding, at a transmissive end (ghost), the constant equal
+// to the element's own mean, or at a PE interface i with effective delay k > 0 the
+// Eq. (11) AT combination of the unlimited outputs that past levels published to the
+// history ring, formed once per stage.
 struct NbSide {
-  int kind, i, k, slot;
+  int base, sv, sj, i, k, ghost;
 };
 
-// LDS per wavefront: the unlimited outputs [5M][64], then kAtSlots AT neighbours [5M].
-constexpr int kAtSlots = 4;
+// LDS per wavefront: the unlimited outputs [5M][64], then kNbSlots neighbours [5M]:
+// two per lane for kSlotLanes lanes at a time.
+constexpr int kSlotLanes = 4;
+constexpr int kNbSlots = 2 * kSlotLanes;
 template <int M>
-constexpr int lds_wave_doubles() { return 5 * M * 64 + kAtSlots * 5 * M; }
+constexpr int lds_wave_doubles() { return 5 * M * 64 + kNbSlots * 5 * M; }
 
-// The Eq. (11) combination of the modal data of the neighbour across PE interface
-// sd.i (side 0: the element left of it, the first U block of the record), variable
-// by variable in c[5M].
+// The Eq. (11) combination of the modal data of the neighbour across PE interface i
+// with delay k (side 0: the element left of it, the first U block of the record),
+// variable by variable in c[5M].
 template <int M>
-__device__ __forceinline__ void at_neighbour(const EulerArgs &a, long long n, const NbSide &sd, int side,
+__device__ __forceinline__ void at_neighbour(const EulerArgs &a, long long n, int nmod, int i, int k, int side,
                                              double (&c)[5 * M]) {
 #pragma unroll
   for (int t = 0; t < 5 * M; ++t) c[t] = 0.0;
@@ -171,51 +173,28 @@ __device__ __forceinline__ void at_neighbour(const EulerArgs &a, long long n, co
     for (int d = 0; d < 2; ++d) {
       const int jj = j0 + d;
       const bool in = jj < a.dl.q;
-      const double w = in ? at_weight(a.dl.q, sd.k, jj) : 0.0;
-      const double *h = ring_rec(a.ring, n - sd.k - (in ? jj : 0), a.stage, a.dl.nif, sd.i) + off;
+      const double w = in ? at_weight(a.dl.q, k, jj) : 0.0;
+      const double *h = ring_at(a.ring, ring_slot(nmod, k + (in ? jj : 0), a.ring.D), a.stage, a.dl.nif, i) + off;
 #pragma unroll
       for (int t = 0; t < 5 * M; ++t) c[t] += w * h[t];
     }
   }
 }
 
-// Modes of variable v of the neighbour across face `side` (0 left, 1 right).  ls is
-// the wavefront's LDS area.
+// Modes of variable v of the neighbour across one face.  ls is the wavefront's LDS area.
 template <int M>
-__device__ __forceinline__ void nb_var(const EulerArgs &a, long long n, const NbSide &sd, int side, int v,
-                                       const double *ls, int lane, double (&c)[M]) {
-  if (sd.kind == 1) {
-    const double mean = ls[(v * M) * 64 + lane];
+__device__ __forceinline__ void nb_var(const NbSide &sd, int v, const double *ls, double (&c)[M]) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) c[j] = j == 0 ? mean : 0.0;
-  } else if (sd.kind == 3) {
-    const double *sl = ls + 5 * M * 64 + sd.slot * 5 * M + v * M;
-#pragma unroll
-    for (int j = 0; j < M; ++j) c[j] = sl[j];
-  } else if (sd.kind == 2) {
-#pragma unroll
-    for (int j = 0; j < M; ++j) c[j] = 0.0;
-    const int off = a.ring.off_U + (side == 0 ? 0 : 5 * M) + v * M;
-    for (int jj = 0; jj < a.dl.q; ++jj) {
-      const double w = at_weight(a.dl.q, sd.k, jj);
-      const double *h = ring_rec(a.ring, n - sd.k - jj, a.stage, a.dl.nif, sd.i) + off;
-#pragma unroll
-      for (int j = 0; j < M; ++j) c[j] += w * h[j];
-    }
-  } else {
-    const int src = lane + (side == 0 ? -1 : 1);
-#pragma unroll
-    for (int j = 0; j < M; ++j) c[j] = ls[(v * M + j) * 64 + src];
-  }
+  for (int j = 0; j < M; ++j) c[j] = ls[sd.base + v * sd.sv + j * sd.sj];
 }
 
 // Troubled-cell indicator of an owned element with unlimited modes u (KXRCF or TVB
 // minmod).
 template <int M>
-__device__ __forceinline__ bool troubled(const EulerArgs &a, const LimiterArgs &l, long long n,
+__device__ __forceinline__ bool troubled(const EulerArgs &a, const LimiterArgs &l, int nmod,
                                          const NbSide (&sd)[2], const double (&u)[5][M], const double *ls,
                                          int lane) {
-  const bool ghostL = sd[0].kind == 1, ghostR = sd[1].kind == 1;
+  const bool ghostL = sd[0].ghost, ghostR = sd[1].ghost;
   bool flag = false;
   if (l.indicator == 1) {
     // TVB minmod: the face deviations from the mean against the mean differences, every
@@ -226,9 +205,9 @@ __device__ __forceinline__ bool troubled(const EulerArgs &a, const LimiterArgs &
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       double c[M];
-      nb_var<M>(a, n, sd[0], 0, v, ls, lane, c);
+      nb_var<M>(sd[0], v, ls, c);
       mL[v] = c[0];
-      nb_var<M>(a, n, sd[1], 1, v, ls, lane, c);
+      nb_var<M>(sd[1], v, ls, c);
       mR[v] = c[0];
       scale = fmax(scale, fmax(fabs(u[v][0]), fmax(fabs(mL[v]), fabs(mR[v]))));
     }
@@ -249,9 +228,9 @@ __device__ __forceinline__ bool troubled(const EulerArgs &a, const LimiterArgs &
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
       double c[M];
-      nb_var<M>(a, n, sd[0], 0, v, ls, lane, c);
+      nb_var<M>(sd[0], v, ls, c);
       tL[v] = trace_at<M>(c, 1);
-      nb_var<M>(a, n, sd[1], 1, v, ls, lane, c);
+      nb_var<M>(sd[1], v, ls, c);
       tR[v] = trace_at<M>(c, 0);
     }
     const double uL_e = trace_at<M>(u[1], 0) / trace_at<M>(u[0], 0);
@@ -318,74 +297,49 @@ __device__ __forceinline__ void weno_field(const LimiterArgs &l, const double (&
   for (int j = 0; j < M; ++j) vl[j] = om0 * tL[j] + om1 * vc[j] + om2 * tR[j];
 }
 
-// Characteristic WENO of troubled element x (its unlimited modes in the LDS area ls,
-// lane `lane`), written to wout: w_lim = sum_c R[:, c] v_c^lim.  One characteristic
-// field at a time; each field's limited modes are parked in the element's own output
-// slots (components c M .. c M + M - 1), which the back-projection then reads and
-// overwrites.  Returns false if the mean state has no valid characteristic
-// decomposition.
+// Characteristic WENO of the troubled element x_c whose unlimited modes sit in lane cl
+// of the wavefront's LDS area, by a group of 8 lanes: lane c < 5 limits characteristic
+// field c (lanes 5..7 repeat field 4 and contribute nothing); w_lim[v] = sum_c R[v][c]
+// v_c^lim is summed across the group in a fixed butterfly order and lane v writes
+// variable v.  Returns false if the mean state has no valid characteristic decomposition.
 template <int M>
-__device__ __forceinline__ bool weno_cell(const EulerArgs &a, const LimiterArgs &l, long long n,
-                                          const NbSide (&sd)[2], const double *ls, int lane, double *wout,
-                                          int x) {
-  bool ok = true;
-#pragma unroll 1
-  for (int c = 0; c < 5; ++c) {
-    // an offset the compiler cannot see through: the LDS reads below stay inside the
-    // loop instead of being hoisted out of it into 3 x 5M live registers
-    int z = 0;
-    asm volatile("" : "+v"(z));
-    const double *lz = ls + z;
-    double wb[5];
+__device__ __forceinline__ bool weno_group(const EulerArgs &a, const LimiterArgs &l, int nmod,
+                                           const NbSide (&sd)[2], const double *ls, int cl, int c, double *wout,
+                                           int xc) {
+  double wb[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) wb[v] = lz[(v * M) * 64 + lane];
-    double lr[5], rc[5];
-    ok = char_row_col(a.ph, wb, c, lr, rc) && ok;
-    double vc[M], vL[M], vR[M];
+  for (int v = 0; v < 5; ++v) wb[v] = ls[(v * M) * 64 + cl];
+  double lr[5], rc[5];
+  const bool ok = char_row_col(a.ph, wb, c < 5 ? c : 4, lr, rc);
+  double vc[M], vL[M], vR[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    vc[j] = 0.0; vL[j] = 0.0; vR[j] = 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double cl_[M], cr_[M];
+    nb_var<M>(sd[0], v, ls, cl_);
+    nb_var<M>(sd[1], v, ls, cr_);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      vc[j] = 0.0; vL[j] = 0.0; vR[j] = 0.0;
+      vc[j] += lr[v] * ls[(v * M + j) * 64 + cl];
+      vL[j] += lr[v] * cl_[j];
+      vR[j] += lr[v] * cr_[j];
     }
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      double cl[M], cr[M];
-      nb_var<M>(a, n, sd[0], 0, v, lz, lane, cl);
-      nb_var<M>(a, n, sd[1], 1, v, lz, lane, cr);
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        vc[j] += lr[v] * lz[(v * M + j) * 64 + lane];
-        vL[j] += lr[v] * cl[j];
-        vR[j] += lr[v] * cr[j];
-      }
-    }
-    double vl[M];
-    weno_field<M>(l, vc, vL, vR, vl);
-#pragma unroll
-    for (int j = 0; j < M; ++j) wout[sidx(x, c * M + j, 5 * M)] = vl[j];
+    // one variable's reads at a time: keeps the stage kernel's register budget
+    __builtin_amdgcn_sched_barrier(0);
   }
-  double va[5][M];
-#pragma unroll
-  for (int c = 0; c < 5; ++c)
-#pragma unroll
-    for (int j = 0; j < M; ++j) va[c][j] = wout[sidx(x, c * M + j, 5 * M)];
-  double wb[5], Rm[5][5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) wb[v] = ls[(v * M) * 64 + lane];
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    double lr[5], rc[5];
-    (void)char_row_col(a.ph, wb, c, lr, rc);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Rm[v][c] = rc[v];
-  }
+  double vl[M];
+  weno_field<M>(l, vc, vL, vR, vl);
 #pragma unroll
   for (int v = 0; v < 5; ++v)
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double o = 0.0;
+      double part = c < 5 ? rc[v] * vl[j] : 0.0;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) o += Rm[v][c] * va[c][j];
-      wout[sidx(x, v * M + j, 5 * M)] = o;
+      for (int m = 1; m < 8; m <<= 1) part += __shfl_xor(part, m, 8);
+      if (c == v) wout[sidx(xc, v * M + j, 5 * M)] = part;
     }
   return ok;
 }
@@ -402,8 +356,8 @@ __device__ __forceinline__ bool weno_cell(const EulerArgs &a, const LimiterArgs 
 // stages its outputs in LDS (ls, 5M x 64 doubles per wavefront), and each owned
 // element runs the indicator and, if troubled, the WENO reconstruction from them.
 template <int M, int FLUX, bool LIM>
-__device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const LimiterArgs &l, double *lds, int blk,
-                                                 int nblk) {
+__device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const LimiterArgs &l, double *lds, int *rounds,
+                                                 int blk, int nblk) {
   constexpr int V = 5, Q = M;
   constexpr int H = LIM ? 2 : 1;
   constexpr int WE = 64 - 2 * H;
@@ -426,6 +380,7 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   int fidx = xu + 1;
   if (a.periodic && (fidx < 0 || fidx > E)) fidx = fidx < 0 ? fidx + E : fidx - E;
   const long long n = *a.step;
+  const int nmod = (int)(n % a.ring.D);
   bool ok = true;
   const double *w0 = a.w0, *ws = a.ws;
   double *wout = a.wout;
@@ -469,7 +424,7 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
     double wp[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) wp[v] = __shfl_down(wl[v], 1);
-    const bool fok = face_flux<FLUX>(a, n, iface, wr, wp, F);
+    const bool fok = face_flux<FLUX>(a, n, nmod, iface, wr, wp, F);
     if (face_lane) ok = fok && ok;
   }
   double Fl[V];
@@ -512,9 +467,9 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
       }
     }
     double *recR = (own && a.store_U && if_left >= 0)   // this element is right of interface if_left
-                       ? ring_rec(a.ring, n, a.stage, a.dl.nif, if_left) + a.ring.off_U + V * M : nullptr;
+                       ? ring_at(a.ring, nmod, a.stage, a.dl.nif, if_left) + a.ring.off_U + V * M : nullptr;
     double *recL = (own && a.store_U && iface >= 0)     // left of interface iface
-                       ? ring_rec(a.ring, n, a.stage, a.dl.nif, iface) + a.ring.off_U : nullptr;
+                       ? ring_at(a.ring, nmod, a.stage, a.dl.nif, iface) + a.ring.off_U : nullptr;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
 #pragma unroll
@@ -536,8 +491,8 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
           const double y = fma(a.dt, L, u[v][j]);
           o = use_prev ? fma(a.rk.ca, wn[v][j], a.rk.cb * y) : y;
         }
-        if (LIM) ls[(v * M + j) * 64 + lane] = o;
-        if (own) wout[gi] = o;   // a troubled element's limited value replaces it below
+        if (LIM) ls[(v * M + j) * 64 + lane] = o;   // stored below, limited if troubled
+        else if (own) wout[gi] = o;
         if (recR) recR[v * M + j] = o;
         if (recL) recL[v * M + j] = o;
       }
@@ -545,47 +500,105 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   }
 
   if constexpr (LIM) {
-    __syncthreads();
+    // neighbour sources of the owned elements; faces at a transmissive end or a delayed
+    // PE interface need a slot: kSlotLanes such elements per round, two slots each
     NbSide sd[2];
+    bool needs = false;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const bool ghost = !a.periodic && (side == 0 ? x == 0 : x == E - 1);
+      const bool ghost = own && !a.periodic && (side == 0 ? x == 0 : x == E - 1);
       const int i = (own && !ghost) ? a.face_if[side == 0 ? x : x + 1] : -1;
       const int k = i >= 0 ? eff_delay(a.dl, n, i) : 0;
-      sd[side].kind = ghost ? 1 : k > 0 ? 2 : 0;
+      sd[side].base = lane + (side == 0 ? -1 : 1);
+      sd[side].sv = M * 64;
+      sd[side].sj = 64;
       sd[side].i = i;
       sd[side].k = k;
-      sd[side].slot = 0;
+      sd[side].ghost = ghost;
+      needs = needs || ghost || k > 0;
     }
-    // the first kAtSlots/2 owned elements of the wavefront next to a delayed PE face form
-    // their AT neighbours once, into LDS slots only they read
-    const bool need = own && (sd[0].kind == 2 || sd[1].kind == 2);
-    const unsigned long long needs = __ballot(need);
-    const int rank = __popcll(needs & ((1ull << lane) - 1ull));
-    if (need && rank < kAtSlots / 2) {
+    const unsigned long long nball = __ballot(needs);
+    const int rank = __popcll(nball & ((1ull << lane) - 1ull));
+    const int my_round = needs ? rank / kSlotLanes : 0;
+    if (lane == 0) rounds[threadIdx.x >> 6] = (__popcll(nball) + kSlotLanes - 1) / kSlotLanes;
+    __syncthreads();   // the wavefront's outputs are in LDS; every wavefront's round count too
+    int nrounds = 1;
 #pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        if (sd[side].kind != 2) continue;
-        double c[5 * M];
-        at_neighbour<M>(a, n, sd[side], side, c);
-        double *sl = ls + 5 * M * 64 + (2 * rank + side) * 5 * M;
+    for (int w = 0; w < kEulerBlock / 64; ++w) nrounds = max(nrounds, rounds[w]);
+#pragma unroll 1
+    for (int round = 0; round < nrounds; ++round) {
+      if (round > 0) __syncthreads();   // the previous round's slots have been read
+      // this round's slots: one pass over each element's first such face, a second over
+      // elements whose both faces need one
+      const bool mine = needs && my_round == round;
+      const bool two = mine && (sd[0].ghost || sd[0].k > 0) && (sd[1].ghost || sd[1].k > 0);
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool go = pass == 0 ? mine : two;
+        if (!__ballot(go)) break;
+        if (go) {
+          const int side = (pass == 0 && (sd[0].ghost || sd[0].k > 0)) ? 0 : 1;
+          const int slot = 2 * (rank % kSlotLanes) + side;
+          double *sl = ls + 5 * M * 64 + slot * 5 * M;
+          if (side == 0 ? sd[0].ghost : sd[1].ghost) {
 #pragma unroll
-        for (int t = 0; t < 5 * M; ++t) sl[t] = c[t];
-        sd[side].kind = 3;
-        sd[side].slot = 2 * rank + side;
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+              for (int j = 0; j < M; ++j) sl[v * M + j] = j == 0 ? ls[(v * M) * 64 + lane] : 0.0;
+          } else {
+            double c[5 * M];
+            at_neighbour<M>(a, n, nmod, side == 0 ? sd[0].i : sd[1].i, side == 0 ? sd[0].k : sd[1].k, side, c);
+#pragma unroll
+            for (int t = 0; t < 5 * M; ++t) sl[t] = c[t];
+          }
+          NbSide &t = side == 0 ? sd[0] : sd[1];
+          t.base = 5 * M * 64 + slot * 5 * M;
+          t.sv = M;
+          t.sj = 1;
+        }
       }
-    }
-    if (own) {
-      double u2[V][M];
+      __syncthreads();   // the slots are read by other lanes of the wavefront below
+      bool flag = false;
+      if (own && my_round == round) {
+        double u2[V][M];
 #pragma unroll
-      for (int v = 0; v < V; ++v)
+        for (int v = 0; v < V; ++v)
 #pragma unroll
-        for (int j = 0; j < M; ++j) u2[v][j] = ls[(v * M + j) * 64 + lane];
-      const bool flag = troubled<M>(a, l, n, sd, u2, ls, lane);
-      l.flags[x] = flag ? 1 : 0;
-      if (flag) {
-        atomicAdd(l.flag_count, 1ull);
-        ok = weno_cell<M>(a, l, n, sd, ls, lane, wout, x) && ok;
+          for (int j = 0; j < M; ++j) u2[v][j] = ls[(v * M + j) * 64 + lane];
+        flag = troubled<M>(a, l, nmod, sd, u2, ls, lane);
+        l.flags[x] = flag ? 1 : 0;
+        if (flag) {
+          atomicAdd(l.flag_count, 1ull);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int j = 0; j < M; ++j) wout[sidx(x, v * M + j, V * M)] = u2[v][j];
+        }
+      }
+      // troubled elements: eight at a time, one group of 8 lanes each (group g takes the
+      // g-th lowest remaining troubled lane)
+      unsigned long long rem = __ballot(flag);
+      const int grp = lane >> 3, cf = lane & 7;
+#pragma unroll 1
+      while (rem) {
+        unsigned long long r = rem;
+        for (int g = 0; g < grp && r; ++g) r &= r - 1;
+        const int cl = r ? __ffsll((long long)r) - 1 : -1;
+        for (int g = 0; g < 8 && rem; ++g) rem &= rem - 1;
+        const int src = cl < 0 ? 0 : cl;
+        const int xc = __shfl(x, src);
+        NbSide sc[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          sc[side].base = __shfl(sd[side].base, src);
+          sc[side].sv = __shfl(sd[side].sv, src);
+          sc[side].sj = __shfl(sd[side].sj, src);
+          sc[side].i = __shfl(sd[side].i, src);
+          sc[side].k = __shfl(sd[side].k, src);
+          sc[side].ghost = __shfl(sd[side].ghost, src);
+        }
+        if (cl >= 0) ok = weno_group<M>(a, l, nmod, sc, ls, cl, cf, wout, xc) && ok;
       }
     }
   }
@@ -595,13 +608,14 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
 
 template <int M, int FLUX>
 __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
-  euler_stage_body<M, FLUX, false>(a, LimiterArgs{}, nullptr, blockIdx.x, gridDim.x);
+  euler_stage_body<M, FLUX, false>(a, LimiterArgs{}, nullptr, nullptr, blockIdx.x, gridDim.x);
 }
 
 template <int M, int FLUX>
 __global__ __launch_bounds__(kEulerBlock, M <= 4 ? 3 : 2) void euler_lim_kernel(EulerArgs a, LimiterArgs l) {
   __shared__ double lds[(kEulerBlock / 64) * lds_wave_doubles<M>()];
-  euler_stage_body<M, FLUX, true>(a, l, lds, blockIdx.x, gridDim.x);
+  __shared__ int rounds[kEulerBlock / 64];
+  euler_stage_body<M, FLUX, true>(a, l, lds, rounds, blockIdx.x, gridDim.x);
 }
 
 // Batched stage kernel: one workgroup per (instance, block) entry of the work
@@ -615,9 +629,10 @@ __global__ __launch_bounds__(kEulerBlock, M <= 4 ? 3 : 2) void euler_batch_kerne
   if (*a.step >= a.target) return;
   if constexpr (LIM) {
     __shared__ double lds[(kEulerBlock / 64) * lds_wave_doubles<M>()];
-    euler_stage_body<M, FLUX, true>(a, sets[tl.x].lim, lds, tl.y, euler_blocks(a.E, true));
+    __shared__ int rounds[kEulerBlock / 64];
+    euler_stage_body<M, FLUX, true>(a, sets[tl.x].lim, lds, rounds, tl.y, euler_blocks(a.E, true));
   } else {
-    euler_stage_body<M, FLUX, false>(a, sets[tl.x].lim, nullptr, tl.y, euler_blocks(a.E, false));
+    euler_stage_body<M, FLUX, false>(a, sets[tl.x].lim, nullptr, nullptr, tl.y, euler_blocks(a.E, false));
   }
 }
 

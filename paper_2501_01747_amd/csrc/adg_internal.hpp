@@ -49,9 +49,14 @@ __host__ __device__ inline size_t state_doubles(int E, int VM) {
   return (size_t)((E + kLayoutBlock - 1) / kLayoutBlock) * kLayoutBlock * VM;
 }
 
-__host__ __device__ inline double *ring_rec(const RingParams &r, long long level, int stage, int nif, int i) {
-  long long slot = level % r.D;
-  return r.base + ((slot * r.stages + stage) * (long long)nif + i) * r.rec;
+// Record of (slot, stage, interface i).  Level n - b (0 <= b < D) lives in slot
+// ring_slot(n mod D, b): a kernel forms n mod D once and steps back from it.
+__host__ __device__ inline int ring_slot(int n_mod_d, int back, int D) {
+  const int s = n_mod_d - back;
+  return s < 0 ? s + D : s;
+}
+__host__ __device__ inline double *ring_at(const RingParams &r, int slot, int stage, int nif, int i) {
+  return r.base + ((size_t)(slot * r.stages + stage) * (size_t)nif + (size_t)i) * (size_t)r.rec;
 }
 
 // Per-element constant tables (host-computed).

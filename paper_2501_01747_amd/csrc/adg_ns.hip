@@ -147,6 +147,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const int E = a.E;
   const int nloc = min(TE, E - e0);
   const long long n = *a.step;
+  const int nmod = (int)(n % a.ring.D);   // the current level's ring slot
   const NsMech *__restrict__ mk = &smech;
   const int q_at = a.dl.q;
   bool ok = true;
@@ -247,7 +248,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     double acw = 0.0, acf = 0.0;
     for (int j = 0; j < q_at; ++j) {
       const double c = at_weight(q_at, k, j);
-      const double *rec = ring_rec(a.ring, n - k - j, stage, a.dl.nif, i);
+      const double *rec = ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), stage, a.dl.nif, i);
       acw += c * rec[a.ring.off_Wc + v];
       acf += c * rec[a.ring.off_F + v];
     }
@@ -264,7 +265,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
                              : (double)((OpT)0.5 * ((OpT)sTp[v][fl] + (OpT)sTm[v][fl + 1]));
     const int i = sI[fl];
     if (i >= 0 && fl >= 1 && fl <= nloc)   // faces e0 .. e0+nloc-1 are owned by this tile
-      ring_rec(a.ring, n, stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
+      ring_at(a.ring, nmod, stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
     sWc[v][fl] = wc;
     if (i < 0 || sK[fl] == 0) sWa[v][fl] = wc;
   }
@@ -521,7 +522,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     double F;
     if (i >= 0) {
       const double Fs = 0.5 * (sGs[0][v][ff] + sGs[1][v][ff] - diss);
-      if (ff < nloc) ring_rec(a.ring, n, stage, a.dl.nif, i)[a.ring.off_F + v] = Fs;
+      if (ff < nloc) ring_at(a.ring, nmod, stage, a.dl.nif, i)[a.ring.off_F + v] = Fs;
       F = sK[ff + 1] > 0 ? sFat[v][ff] : Fs;
     } else {
       F = 0.5 * (sGf[0][v][ff] + sGf[1][v][ff] - diss);
@@ -754,6 +755,7 @@ static hipError_t ns_M(int cfg, const NsArgs &a, hipStream_t s) {
     case 1: return ns_launch<M, 8, 256>(a, s);
     case 2: return ns_launch<M, 4, 256>(a, s);
     case 3: return ns_launch<M, 4, 512>(a, s);
+    case 4: return ns_launch<M, 8, 1024>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -71,8 +71,8 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
 // The device form of a mechanism (host side; validates it).
 adg_status ns_build_mech(const adg_physics *ph, NsMech &hm);
 // Work decompositions of the single-problem stage kernel: (tile elements, threads)
-// = (8, 512), (8, 256), (4, 256), (4, 512).
-constexpr int kNsConfigs = 4;
+// = (8, 512), (8, 256), (4, 256), (4, 512), (8, 1024).
+constexpr int kNsConfigs = 5;
 hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, hipStream_t s);
 // One stage for every (instance, tile) entry of `tiles` (device); mixed = FP32 modal operators;
 // max_m = the largest N_p + 1 among the listed instances; tiles of tile_elems (4 or 8) elements.

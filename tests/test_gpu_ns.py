@@ -150,13 +150,30 @@ def test_autotune_keeps_the_state_and_parity(adg, orc, mech):
     before = s.state()
     choice = s.autotune(3)
     print(f"[autotune] choice {choice}", flush=True)
-    assert 0 <= choice < 4
+    assert 0 <= choice < 5
     np.testing.assert_array_equal(s.state(), before)
     o = orc.OracleSolver(case, w0, 20)
     o.step(3)
     s.step(9)
     o.step(9)
     assert rel_per_var(s.state(), o.state()) < 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("config", [0, 1, 2, 3, 4])
+def test_every_work_decomposition_matches_the_oracle(adg, orc, mech, config):
+    """Each of the stage kernel's work decompositions (tile of 8 or 4 elements, 256 to 1024
+    threads) on a mesh with a ragged last tile, against the oracle."""
+    case, w0 = gen.case_c1(E=93, n_pe=6, mech=mech, Lx=0.01 * 93 / 2048)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.set_kernel_config(config)
+    o = orc.OracleSolver(case, w0, 10)
+    s.step(7)
+    o.step(7)
+    err = rel_per_var(s.state(), o.state())
+    print(f"[config {config}] rel err {err:.2e}", flush=True)
+    assert err < 1e-10
     s.close()
 
 
