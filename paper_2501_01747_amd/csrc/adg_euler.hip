@@ -47,33 +47,42 @@ __device__ __forceinline__ void load_elem(const double *__restrict__ w, int E, i
     for (int j = 0; j < M; ++j) u[v][j] = w[sidx(e, v * M + j, 5 * M)];
 }
 
-// Numerical flux at a face from its two traces; at PE interface i the AT flux.
+// The AT flux of Eq. (7) at PE interface i with delay k > 0: the past levels' synchronous
+// fluxes of this stage combined with the Eq. (8) weights.  Levels 0..3 are loaded together
+// (a level past q reads level n-k with weight 0), later ones (q > 4) one at a time.
+__device__ __forceinline__ void at_flux(const EulerArgs &a, int nmod, int i, int k, double (&acc)[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) acc[v] = 0.0;
+  const int q = a.dl.q;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bool in = j < q;
+    const double c = in ? at_weight(q, k, j) : 0.0;
+    const double *h = ring_at(a.ring, ring_slot(nmod, k + (in ? j : 0), a.ring.D), a.stage, a.dl.nif, i) + a.ring.off_F;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[v] += c * h[v];
+  }
+  for (int j = 4; j < q; ++j) {
+    const double c = at_weight(q, k, j);
+    const double *h = ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), a.stage, a.dl.nif, i) + a.ring.off_F;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[v] += c * h[v];
+  }
+}
+
+// Numerical flux at a face from its two traces; at PE interface i the synchronous flux
+// is published for this level and, with delay k > 0, replaced by the AT flux Fat.
 template <int FLUX>
-__device__ __forceinline__ bool face_flux(const EulerArgs &a, long long n, int nmod, int i, const double *wm,
-                                          const double *wp, double *F) {
+__device__ __forceinline__ bool face_flux(const EulerArgs &a, int nmod, int i, int k, const double (&Fat)[5],
+                                          const double *wm, const double *wp, double *F) {
   bool ok = numflux1<FLUX>(a.ph, wm, wp, F);
   if (i >= 0) {
     double *rec = ring_at(a.ring, nmod, a.stage, a.dl.nif, i) + a.ring.off_F;
 #pragma unroll
     for (int v = 0; v < 5; ++v) rec[v] = F[v];
-    const int k = eff_delay(a.dl, n, i);
     if (k > 0) {
-      double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      // two levels per round trip (a level past q reads level n-k with weight 0)
-      for (int j0 = 0; j0 < a.dl.q; j0 += 2) {
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          const int j = j0 + d;
-          const bool in = j < a.dl.q;
-          const double c = in ? at_weight(a.dl.q, k, j) : 0.0;
-          const double *h = ring_at(a.ring, ring_slot(nmod, k + (in ? j : 0), a.ring.D), a.stage, a.dl.nif, i) +
-                            a.ring.off_F;
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] += c * h[v];
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 5; ++v) F[v] = acc[v];
+      for (int v = 0; v < 5; ++v) F[v] = Fat[v];
     }
   }
   return ok;
@@ -97,10 +106,11 @@ __device__ __forceinline__ bool char_row_col(const OneStep &ph, const double *wb
   Prim1 pr;
   const bool ok = prim1(ph, wb, pr);
   const double rho = pr.rho, u = pr.u, a = pr.a, g1 = ph.gamma - 1.0, q = ph.q_heat;
+  const double irho = 1.0 / rho;
   const double dp[5] = {g1 * 0.5 * u * u, -g1 * u, g1, -g1 * q, 0.0};
-  const double du[5] = {-u / rho, 1.0 / rho, 0.0, 0.0, 0.0};
-  const double a2 = a * a;
-  const double YR = wb[3] / rho, YP = 1.0 - YR;
+  const double du[5] = {-u * irho, irho, 0.0, 0.0, 0.0};
+  const double a2 = a * a, ia2 = 1.0 / a2;
+  const double YR = wb[3] * irho, YP = 1.0 - YR;
   const double l2[5] = {-YR, 0.0, 0.0, 1.0, 0.0};
   const double l3[5] = {-1.0, 0.0, 0.0, 1.0, 1.0};
   // the acoustic rows carry the sign of their wave speed u -+ a
@@ -108,8 +118,8 @@ __device__ __forceinline__ bool char_row_col(const OneStep &ph, const double *wb
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const double drho = k == 0 ? 1.0 : 0.0;
-    const double ac = (dp[k] + sa * rho * a * du[k]) / (2.0 * a2);
-    lr[k] = (c == 0 || c == 4) ? ac : c == 1 ? drho - dp[k] / a2 : c == 2 ? l2[k] : l3[k];
+    const double ac = (dp[k] + sa * rho * a * du[k]) * (0.5 * ia2);
+    lr[k] = (c == 0 || c == 4) ? ac : c == 1 ? drho - dp[k] * ia2 : c == 2 ? l2[k] : l3[k];
   }
   // columns: acoustic -, entropy, reactant, species sum, acoustic +
   const double hk = 0.5 * u * u + q * YR;   // d(rho E)/d rho at fixed u, p, Y
@@ -292,7 +302,8 @@ __device__ __forceinline__ void weno_field(const LimiterArgs &l, const double (&
     wbar[s] = l.gam[s] / (d * d);
     sum += wbar[s];
   }
-  const double om0 = wbar[0] / sum, om1 = wbar[1] / sum, om2 = wbar[2] / sum;
+  const double isum = 1.0 / sum;
+  const double om0 = wbar[0] * isum, om1 = wbar[1] * isum, om2 = wbar[2] * isum;
 #pragma unroll
   for (int j = 0; j < M; ++j) vl[j] = om0 * tL[j] + om1 * vc[j] + om2 * tR[j];
 }
@@ -342,6 +353,42 @@ __device__ __forceinline__ bool weno_group(const EulerArgs &a, const LimiterArgs
       if (c == v) wout[sidx(xc, v * M + j, 5 * M)] = part;
     }
   return ok;
+}
+
+// Slots of a wavefront's round (kSlotLanes elements, two slots each): the ghost or AT
+// neighbour of every face of the element that needs one, then the face's source points
+// at its slot.  One pass over each element's first such face, a second over elements
+// whose both faces need one.
+template <int M>
+__device__ __forceinline__ void fill_slots(const EulerArgs &a, long long n, int nmod, NbSide (&sd)[2], bool mine,
+                                           int rank, double *ls, int lane) {
+  const bool need0 = sd[0].ghost || sd[0].k > 0, need1 = sd[1].ghost || sd[1].k > 0;
+  const bool two = mine && need0 && need1;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool go = pass == 0 ? mine : two;
+    if (!__ballot(go)) break;
+    if (go) {
+      const int side = (pass == 0 && need0) ? 0 : 1;
+      const int slot = 2 * (rank % kSlotLanes) + side;
+      double *sl = ls + 5 * M * 64 + slot * 5 * M;
+      if (side == 0 ? sd[0].ghost : sd[1].ghost) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int j = 0; j < M; ++j) sl[v * M + j] = j == 0 ? ls[(v * M) * 64 + lane] : 0.0;
+      } else {
+        double c[5 * M];
+        at_neighbour<M>(a, n, nmod, side == 0 ? sd[0].i : sd[1].i, side == 0 ? sd[0].k : sd[1].k, side, c);
+#pragma unroll
+        for (int t = 0; t < 5 * M; ++t) sl[t] = c[t];
+      }
+      NbSide &t = side == 0 ? sd[0] : sd[1];
+      t.base = 5 * M * 64 + slot * 5 * M;
+      t.sv = M;
+      t.sj = 1;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- stage kernel
@@ -408,6 +455,11 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
       for (int j = 0; j < M; ++j) u[v][j] = 0.0;
   }
   const int iface = face_lane ? a.face_if[fidx] : -1;
+  // a delayed PE-interface face gathers its past levels' fluxes now, while the state
+  // loads are in flight
+  const int kf = iface >= 0 ? eff_delay(a.dl, n, iface) : 0;
+  double Fat[V];
+  if (kf > 0) at_flux(a, nmod, iface, kf, Fat);
 
   double wl[V], wr[V];
   traces<M>(u, wl, wr);
@@ -424,7 +476,7 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
     double wp[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) wp[v] = __shfl_down(wl[v], 1);
-    const bool fok = face_flux<FLUX>(a, n, nmod, iface, wr, wp, F);
+    const bool fok = face_flux<FLUX>(a, nmod, iface, kf, Fat, wr, wp, F);
     if (face_lane) ok = fok && ok;
   }
   double Fl[V];
@@ -520,44 +572,20 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
     const unsigned long long nball = __ballot(needs);
     const int rank = __popcll(nball & ((1ull << lane) - 1ull));
     const int my_round = needs ? rank / kSlotLanes : 0;
+    // the first round's slots are formed before the barrier: they need only this lane's data
+    fill_slots<M>(a, n, nmod, sd, needs && my_round == 0, rank, ls, lane);
     if (lane == 0) rounds[threadIdx.x >> 6] = (__popcll(nball) + kSlotLanes - 1) / kSlotLanes;
-    __syncthreads();   // the wavefront's outputs are in LDS; every wavefront's round count too
+    __syncthreads();   // the wavefront's outputs and slots are in LDS; every wavefront's round count too
     int nrounds = 1;
 #pragma unroll
     for (int w = 0; w < kEulerBlock / 64; ++w) nrounds = max(nrounds, rounds[w]);
 #pragma unroll 1
     for (int round = 0; round < nrounds; ++round) {
-      if (round > 0) __syncthreads();   // the previous round's slots have been read
-      // this round's slots: one pass over each element's first such face, a second over
-      // elements whose both faces need one
-      const bool mine = needs && my_round == round;
-      const bool two = mine && (sd[0].ghost || sd[0].k > 0) && (sd[1].ghost || sd[1].k > 0);
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
-        const bool go = pass == 0 ? mine : two;
-        if (!__ballot(go)) break;
-        if (go) {
-          const int side = (pass == 0 && (sd[0].ghost || sd[0].k > 0)) ? 0 : 1;
-          const int slot = 2 * (rank % kSlotLanes) + side;
-          double *sl = ls + 5 * M * 64 + slot * 5 * M;
-          if (side == 0 ? sd[0].ghost : sd[1].ghost) {
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-#pragma unroll
-              for (int j = 0; j < M; ++j) sl[v * M + j] = j == 0 ? ls[(v * M) * 64 + lane] : 0.0;
-          } else {
-            double c[5 * M];
-            at_neighbour<M>(a, n, nmod, side == 0 ? sd[0].i : sd[1].i, side == 0 ? sd[0].k : sd[1].k, side, c);
-#pragma unroll
-            for (int t = 0; t < 5 * M; ++t) sl[t] = c[t];
-          }
-          NbSide &t = side == 0 ? sd[0] : sd[1];
-          t.base = 5 * M * 64 + slot * 5 * M;
-          t.sv = M;
-          t.sj = 1;
-        }
+      if (round > 0) {
+        __syncthreads();   // the previous round's slots have been read
+        fill_slots<M>(a, n, nmod, sd, needs && my_round == round, rank, ls, lane);
+        __syncthreads();   // the slots are read by other lanes of the wavefront below
       }
-      __syncthreads();   // the slots are read by other lanes of the wavefront below
       bool flag = false;
       if (own && my_round == round) {
         double u2[V][M];
