@@ -246,7 +246,17 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const int i = sI[fl], k = sK[fl];
     if (i < 0 || k == 0) continue;
     double acw = 0.0, acf = 0.0;
-    for (int j = 0; j < q_at; ++j) {
+    // levels 0..3 loaded together (a level past q reads level n-k with weight 0), later
+    // ones (q > 4) one at a time
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool in = j < q_at;
+      const double c = in ? at_weight(q_at, k, j) : 0.0;
+      const double *rec = ring_at(a.ring, ring_slot(nmod, k + (in ? j : 0), a.ring.D), stage, a.dl.nif, i);
+      acw += c * rec[a.ring.off_Wc + v];
+      acf += c * rec[a.ring.off_F + v];
+    }
+    for (int j = 4; j < q_at; ++j) {
       const double c = at_weight(q_at, k, j);
       const double *rec = ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), stage, a.dl.nif, i);
       acw += c * rec[a.ring.off_Wc + v];
