@@ -400,6 +400,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     Rmix = group_sum<LP>(Rmix);
     double T, cv;
     const bool conv = newton_T(c, mk->T_guess, estar, T, cv);
+    const double lnT = log(T);   // shared by the viscosity law and the Gibbs energies
     const double cp = cv + Rmix;
     const double pr = wr * Rmix * T;
     const double snd = sqrt(cp / cv * pr * rho_inv);
@@ -410,7 +411,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 #pragma unroll
     for (int m = 0; m < NO; ++m) gy[m] = gsy[m] = wy[m] * u;
     if (a.viscous) {
-      const double mu = mk->mu_ref * exp(mk->mu_exp * log(T * mk->inv_T_ref));
+      const double mu = mk->mu_ref * exp(mk->mu_exp * (lnT - mk->ln_T_ref));
       const double kappa = mu * cp * mk->inv_prandtl;
       const double rhoD = mu * mk->inv_prandtl;
       const double En = we * rho_inv;
@@ -453,7 +454,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
           sG[2][p] = g2;
           sT[p] = T;
         }
-        const double lnT = log(T), invT = 1.0 / T;
+        const double invT = 1.0 / T;
         if (k == 1) {
           sLnT[p] = lnT;
           sInvT[p] = invT;
@@ -693,7 +694,7 @@ adg_status ns_build_mech(const adg_physics *ph, NsMech &hm) {
   hm.p_ref = m->p_ref;
   hm.T_guess = m->T_guess;
   hm.mu_ref = m->mu_ref;
-  hm.inv_T_ref = 1.0 / m->T_ref;
+  hm.ln_T_ref = std::log(m->T_ref);
   hm.mu_exp = m->mu_exp;
   hm.inv_prandtl = 1.0 / m->prandtl;
   hm.ln_p_over_Ru = std::log(m->p_ref / m->Ru);

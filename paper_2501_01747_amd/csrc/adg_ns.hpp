@@ -13,7 +13,7 @@ constexpr int kNsMaxReactions = 32;
 struct NsMech {
   int ns, nr;
   double Ru, p_ref, T_guess;
-  double mu_ref, inv_T_ref, mu_exp, inv_prandtl;
+  double mu_ref, ln_T_ref, mu_exp, inv_prandtl;   // mu = mu_ref exp(mu_exp (ln T - ln T_ref))
   double ln_p_over_Ru;              // ln(p_ref / Ru)
   double W[kNsMaxSpecies], invW[kNsMaxSpecies], Ri[kNsMaxSpecies];
   // NASA-7 in Horner-ready form, per species:
