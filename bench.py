@@ -220,7 +220,7 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
 
 # Arrival rate of the served stream: 0.7 x the saturation throughput of the server
 # (all requests queued at t = 0), measured once with --calibrate and then fixed.
-C4_RATE = 13.7   # 0.7 x 19.57 requests/s measured with --calibrate --requests 300
+C4_RATE = 14.5   # 0.7 x 20.77 requests/s measured with --calibrate --requests 300
 
 
 def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, precision: str):

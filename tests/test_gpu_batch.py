@@ -231,6 +231,24 @@ def test_limited_instance_stops_at_odd_step_count(adg):
     b.close()
 
 
+def test_limited_instances_with_one_element_per_pe(adg):
+    """Batched limited instances whose every face is a delayed PE interface (the stage
+    kernel forms the limiter's ring neighbours in several rounds) equal the single solver."""
+    cases = []
+    for E, mode in ((150, "saa"), (97, "caa")):
+        c, w = gen.case_c2(E=E, order_p=2, length=E / 32.0, shock_x=(E // 4) / 32.0, n_pe=E, mode=mode)
+        if mode == "caa":
+            c["async"]["L"] = 3
+        cases.append((c, w))
+    b = make_batch(adg, cases)
+    slots = [b.add(c, w) for c, w in cases]
+    b.step(7)
+    for (c, w), sl in zip(cases, slots):
+        ref = single(adg, c, w, 7)
+        assert np.max(np.abs(b.state(sl) - ref)) <= 1e-13 * np.abs(ref).max()
+    b.close()
+
+
 def test_graph_replay_matches_plain_launches(adg, mech):
     cases = mixed_cases(mech)[:3] + onestep_cases()[2:3]
     res = []

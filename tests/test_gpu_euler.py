@@ -319,3 +319,25 @@ def test_limiter_periodic_small_meshes(adg, orc, E):
         r = rel_l2(s.state(), o.state())
         assert r < 1e-10, (k, r)
 
+
+
+@pytest.mark.parametrize("E,mode,bc", [(150, "saa", "transmissive"), (130, "caa", "periodic")])
+def test_limiter_every_face_a_pe_interface(adg, orc, E, mode, bc):
+    """One element per PE: every face is a delayed PE interface, so every element of a
+    wavefront needs both of its limiter neighbours formed from the history ring (more than
+    the wavefront's slots hold at once: the stage kernel takes them in several rounds);
+    states and flags against the oracle."""
+    case, w0 = gen.case_c2(E=E, order_p=2, length=E / 32.0, shock_x=(E // 4) / 32.0, n_pe=E, mode=mode)
+    case["disc"]["bc"] = bc
+    if mode == "caa":
+        case["async"]["L"] = 3
+    s = adg.Solver(case)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, 12)
+    for k in (5, 6):
+        s.step(k)
+        o.step(k)
+        fg, tot = s.flags()
+        assert np.array_equal(fg, o.flags()) and tot == o.total_flags() and tot > 0, k
+        r = rel_l2(s.state(), o.state())
+        assert r < 1e-10, (k, r)
