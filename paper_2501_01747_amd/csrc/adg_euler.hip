@@ -598,10 +598,11 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
         if (flag) {
           atomicAdd(l.flag_count, 1ull);
         } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-#pragma unroll
-            for (int j = 0; j < M; ++j) wout[sidx(x, v * M + j, V * M)] = u2[v][j];
+          // a rolled loop: the compiler would otherwise keep one 64-bit address per
+          // component live across the limiter (and spill them)
+          double *dst = wout + sidx(x, 0, V * M);
+#pragma unroll 1
+          for (int c = 0; c < V * M; ++c) dst[c * kLayoutBlock] = ls[c * 64 + lane];
         }
       }
       // troubled elements: eight at a time, one group of 8 lanes each (group g takes the
