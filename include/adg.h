@@ -182,9 +182,10 @@ adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph);
 
 /* Choose the stage kernel's work decomposition by measurement: for the
    detailed-chemistry model, the tile size (4 or 8 elements) and workgroup size
-   (256, 512 or 1024 threads) of the stage kernel, each candidate timed over n_reps
-   launches of the first RK stage on the current state; later steps use the
-   fastest.  The timed launches only rewrite the first stage buffer and the
+   (256, 512 or 1024 threads) of the stage kernel: every candidate is warmed up,
+   then timed over n_reps launches of the first RK stage on the current state in
+   three interleaved rounds, its fastest round counting; later steps use the
+   fastest candidate.  The timed launches only rewrite the first stage buffer and the
    current level's first-stage history, which the next step recomputes, so the
    solution is unchanged.  *choice (optional) receives the chosen candidate
    (0: 8/512, 1: 8/256, 2: 4/256, 3: 4/512, 4: 8/1024; always 0 for the one-step model,

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -314,21 +315,29 @@ adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
   a.wout = s->P.W[bo];
   a.stage = 0;
   a.advance = 0;
-  double best_ms = 0.0;
-  int best = 0;
+  // every candidate warmed up first, then timed in three interleaved rounds; each keeps
+  // its fastest round (clock ramp-up and other transients then bias no candidate)
+  double t[kNsConfigs];
   hipEvent_t e0, e1;
   HIP_TRY(s, hipEventCreate(&e0));
   HIP_TRY(s, hipEventCreate(&e1));
   for (int c = 0; c < kNsConfigs; ++c) {
-    HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));   // warm-up
-    HIP_TRY(s, hipEventRecord(e0, s->stream));
-    for (int r = 0; r < n_reps; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));
-    HIP_TRY(s, hipEventRecord(e1, s->stream));
-    HIP_TRY(s, hipEventSynchronize(e1));
-    float ms = 0.0f;
-    HIP_TRY(s, hipEventElapsedTime(&ms, e0, e1));
-    if (c == 0 || ms < best_ms) { best_ms = ms; best = c; }
+    for (int r = 0; r < 2; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));
+    t[c] = 1e30;
   }
+  for (int round = 0; round < 3; ++round)
+    for (int c = 0; c < kNsConfigs; ++c) {
+      HIP_TRY(s, hipEventRecord(e0, s->stream));
+      for (int r = 0; r < n_reps; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));
+      HIP_TRY(s, hipEventRecord(e1, s->stream));
+      HIP_TRY(s, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_TRY(s, hipEventElapsedTime(&ms, e0, e1));
+      t[c] = std::min(t[c], (double)ms);
+    }
+  int best = 0;
+  for (int c = 1; c < kNsConfigs; ++c)
+    if (t[c] < t[best]) best = c;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (best != s->ns_cfg) {
