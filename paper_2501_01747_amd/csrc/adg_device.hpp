@@ -14,6 +14,29 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
   return z ^ (z >> 31);
 }
 
+// Cross-lane moves by the data-parallel-primitive (DPP) modifier, without the LDS
+// crossbar.  dpp_move<CTRL>(x) returns the x of the lane that CTRL selects (a lane
+// with no source keeps its own x): quad permutations, row mirrors and the
+// wavefront shifts.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const unsigned long long v = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)v, (int)(unsigned)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(v >> 32), (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF,
+                                             false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppFromNext = 0x130;   // lane l takes lane l+1's value (wavefront shift)
+constexpr int kDppFromPrev = 0x138;   // lane l takes lane l-1's value
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane l takes lane 7-l of its group of 8
+constexpr int kDppMirror = 0x140;     // lane l takes lane 15-l of its group of 16
+
 // Delay at PE interface i for time step n (Sec. 4), clamped so that all q
 // levels n-k .. n-k-q+1 exist.
 __device__ __forceinline__ int eff_delay(const DelayParams &d, long long n, int i) {

@@ -348,8 +348,9 @@ __device__ __forceinline__ bool weno_group(const EulerArgs &a, const LimiterArgs
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       double part = c < 5 ? rc[v] * vl[j] : 0.0;
-#pragma unroll
-      for (int m = 1; m < 8; m <<= 1) part += __shfl_xor(part, m, 8);
+      part += dpp_move<kDppXor1>(part);
+      part += dpp_move<kDppXor2>(part);
+      part += dpp_move<kDppHalfMirror>(part);   // the same sum as from lane ^ 4
       if (c == v) wout[sidx(xc, v * M + j, 5 * M)] = part;
     }
   return ok;
@@ -465,8 +466,8 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   traces<M>(u, wl, wr);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const double next_l = __shfl_down(wl[v], 1);
-    const double prev_r = __shfl_up(wr[v], 1);
+    const double next_l = dpp_move<kDppFromNext>(wl[v]);
+    const double prev_r = dpp_move<kDppFromPrev>(wr[v]);
     if (ghost_l) wr[v] = next_l;
     if (ghost_r) wl[v] = prev_r;
   }
@@ -475,14 +476,14 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   {
     double wp[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) wp[v] = __shfl_down(wl[v], 1);
+    for (int v = 0; v < V; ++v) wp[v] = dpp_move<kDppFromNext>(wl[v]);
     const bool fok = face_flux<FLUX>(a, nmod, iface, kf, Fat, wr, wp, F);
     if (face_lane) ok = fok && ok;
   }
   double Fl[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) Fl[v] = __shfl_up(F[v], 1);
-  const int if_left = __shfl_up(iface, 1);
+  for (int v = 0; v < V; ++v) Fl[v] = dpp_move<kDppFromPrev>(F[v]);
+  const int if_left = dpp_move<kDppFromPrev>(iface);
 
   // with the limiter: this wavefront's outputs, [component][lane]
   double *ls = LIM ? lds + (threadIdx.x >> 6) * lds_wave_doubles<M>() : nullptr;

@@ -28,15 +28,6 @@ namespace adg {
 constexpr int kThreadsBatch = 256;   // batched kernel: more resident workgroups per CU
 constexpr int kThreadsSingle = 512;  // one problem: more lanes per tile, shorter phases
 
-// A double from lane-permuting data-parallel-primitive move CTRL (both dwords).
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double x) {
-  const unsigned long long v = (unsigned long long)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 // Sum over the LP lanes of a point group (every lane receives the same value:
 // the pairwise sums are formed in the same order on every lane).  Groups of up to
 // 16 lanes use lane moves inside the SIMD's rows (swap within pairs, then within
@@ -46,10 +37,10 @@ __device__ __forceinline__ double dpp_move(double x) {
 template <int LP>
 __device__ __forceinline__ double group_sum(double x) {
   if constexpr (LP <= 16) {
-    if constexpr (LP >= 2) x += dpp_move<0xB1>(x);    // quad_perm [1,0,3,2]
-    if constexpr (LP >= 4) x += dpp_move<0x4E>(x);    // quad_perm [2,3,0,1]
-    if constexpr (LP >= 8) x += dpp_move<0x141>(x);   // row_half_mirror
-    if constexpr (LP >= 16) x += dpp_move<0x140>(x);  // row_mirror
+    if constexpr (LP >= 2) x += dpp_move<kDppXor1>(x);
+    if constexpr (LP >= 4) x += dpp_move<kDppXor2>(x);
+    if constexpr (LP >= 8) x += dpp_move<kDppHalfMirror>(x);
+    if constexpr (LP >= 16) x += dpp_move<kDppMirror>(x);
   } else {
 #pragma unroll
     for (int m = 1; m < LP; m <<= 1) x += __shfl_xor(x, m, LP);
