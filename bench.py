@@ -293,6 +293,32 @@ def sweep_euler(sizes, steps=20):
     return out
 
 
+def sweep_limiter(sizes, steps=20):
+    """Size sweep of the one-step stage kernel with the limiter inside (the detonation
+    workload's physics at its resolution dx = 1/32, N_p = 3, HLLC, KXRCF + AT-WENO, 64 PEs):
+    per size, the kernel's mean launch time and its algorithmic bandwidth."""
+    import torch
+
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    out = []
+    for E in sizes:
+        case, w0 = gen.case_c2(E=E, length=E / 32.0, shock_x=E / 512.0)
+        s = adg.Solver(case)
+        s.set_state(w0)
+        s.step(3)
+        prof = s.profile(steps)
+        ms = prof["stage"][0]
+        nbytes = euler_stage_bytes(case)
+        out.append({"n_elem": E, "dof": gen.dof(case), "stage_ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9,
+                    "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,7 +329,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured copy / FP64 ceilings")
     ap.add_argument("--sweep-euler", action="store_true",
-                    help="print the Euler stage-kernel size sweep instead of the benchmark line")
+                    help="print the one-step stage-kernel size sweeps (without and with the limiter) instead of the benchmark line")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="calibration copy + plain-launch steps for rocprofv3 --pmc (no benchmark line)")
     ap.add_argument("--n-elem", type=int, default=None, help="override the workload's element count")
@@ -351,7 +377,9 @@ def main():
         pmc_probe(args)
         return
     if args.sweep_euler:
-        print(json.dumps({"sweep": "euler_stage_kernel", "results": sweep_euler([2**p for p in range(10, 23, 1)])}),
+        print(json.dumps({"sweep": "euler_stage_kernel", "results": sweep_euler([2**p for p in range(10, 24, 1)])}),
+              flush=True)
+        print(json.dumps({"sweep": "euler_lim_kernel", "results": sweep_limiter([2**p for p in range(13, 23, 1)])}),
               flush=True)
         return
     case, w0 = workload(args.workload, args.n_elem)
