@@ -8,8 +8,8 @@
 //
 // A time step launches, per stage, one batched kernel for all detailed-
 // chemistry instances (orders dispatched inside the kernel) and one batched
-// kernel per (order, flux) group of one-step instances, then the limiter and
-// scatter kernels of the limited ones.  Every workgroup works on one instance
+// kernel per (order, flux, limiter) group of one-step instances, the limiter of
+// limited instances inside that kernel.  Every workgroup works on one instance
 // only, with that instance's own arguments, so the arithmetic of an instance
 // does not depend on what else is in the batch.
 #include <hip/hip_runtime.h>
