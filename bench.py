@@ -166,6 +166,47 @@ def cpu_baseline(case, w0, budget_s: float = 12.0):
                       f"({el:.1f} s, single thread, gcc -O2)"}
 
 
+def cpu_baseline_batch(cases, budget_s: float = 10.0, steps: int = 8):
+    """The oracle as it stands on the batched workload's instances, one instance per host
+    thread at a time (the oracle is a C library called through ctypes, which releases the
+    interpreter lock): instances taken in order, `steps` time steps each, until about
+    `budget_s` has passed.  Threads = the host cores this process may use, at most 16."""
+    import threading
+
+    from oracle import oracle
+    from workloads import gen
+
+    oracle.build(force=not os.path.exists(oracle._LIB_PATH))
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    lock = threading.Lock()
+    state = {"next": 0, "work": 0.0, "done": 0}
+    t0 = time.perf_counter()
+
+    def worker():
+        while True:
+            with lock:
+                if time.perf_counter() - t0 >= budget_s or state["next"] >= len(cases):
+                    return
+                c, w = cases[state["next"]]
+                state["next"] += 1
+            s = oracle.OracleSolver(c, w, steps + 1)
+            s.step(steps)
+            s.close()
+            with lock:
+                state["work"] += gen.dof(c) * 3 * steps
+                state["done"] += 1
+
+    pool = [threading.Thread(target=worker) for _ in range(threads)]
+    for t in pool:
+        t.start()
+    for t in pool:
+        t.join()
+    el = time.perf_counter() - t0
+    return {"value": state["work"] / el, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{state['done']} of the batch's instances, {steps} time steps each, FP64, "
+                      f"{threads} host threads ({el:.1f} s)"}
+
+
 def build_c3_batch(precision: str, n_inst: int = 4096):
     from paper_2501_01747_amd import adg
     from workloads import gen
@@ -179,7 +220,8 @@ def build_c3_batch(precision: str, n_inst: int = 4096):
     return b, cases
 
 
-def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed", n_inst: int = 4096):
+def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed", n_inst: int = 4096,
+                  cpu: bool = False):
     """The batched ignition workload: n_inst instances (element counts log-uniform in
     [128, 4096], N_p in {2, 3}, 4-32 PEs, SAA delays k <= 2) in one batch; every stage of
     every instance is one batched launch.  Returns the measurement as a dict."""
@@ -205,7 +247,7 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
     flops = sum(detailed_stage_flops(c) for c, _ in cases)
     achieved = flops / (stage_ms * 1e-3) / 1e12
     b.close()
-    return {
+    out = {
         "value": dof * 3 * steps / el, "unit": "DOF-updates/s", "ms_per_step": el * 1e3 / steps,
         "steps": steps, "warmup": warmup, "precision": precision,
         "config": {"workload": "c3_batched_ignition", "instances": len(cases), "elements": elems, "dof": dof,
@@ -216,6 +258,9 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
                      "traffic": read_traffic("c3", ["adg_ns.hip", "adg_ns.hpp"]), "kernel": "ns_batch_kernel",
                      "launch_ms": stage_ms, "flops_per_launch": flops},
     }
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline_batch(cases)
+    return out
 
 
 # Arrival rate of the served stream: 0.7 x the saturation throughput of the server
@@ -355,7 +400,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "c3" and not args.pmc_probe:
-        out = bench_batched(args.steps, args.warmup, args.graph, args.precision)
+        out = bench_batched(args.steps, args.warmup, args.graph, args.precision, cpu=not args.no_cpu_baseline)
         out.update({"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
                     "vs_baseline": None, "dtype": "f64+f32" if args.precision == "mixed" else "f64",
                     "data": "synthetic"})
@@ -443,7 +488,7 @@ def main():
         ceiling = mp["fp64_vector_TFLOPs"] if detailed else mp["copy_GBps"]
         out["roofline"]["frac_of_measured"] = out["roofline"]["achieved"] / ceiling
     if not args.no_batched and detailed:
-        bb = bench_batched(args.batch_steps, 5, args.graph, args.precision)
+        bb = bench_batched(args.batch_steps, 5, args.graph, args.precision, cpu=not args.no_cpu_baseline)
         out["batched_mixed"] = bb
         out["batched_over_plain"] = bb["value"] / value
     if not args.no_cpu_baseline:
