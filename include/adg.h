@@ -123,7 +123,8 @@ typedef struct {
   int32_t L;              /* number of admissible delays, k in {0 .. L-1}; 1 <= L <= 8 */
   const double *pmf;      /* [L] SAA probabilities (host); must sum to 1 within 1e-12 */
   uint64_t seed;          /* SAA: counter-based SplitMix64 draw per (step, interface) */
-  const int8_t *schedule; /* ADG_SCHEDULE: [schedule_steps][n_if] delays (host), period schedule_steps */
+  const int8_t *schedule; /* ADG_SCHEDULE: [schedule_steps][n_if] delays in 0..L-1 (host), period
+                             schedule_steps; any other delay is ADG_ERR_ARG */
   int32_t schedule_steps;
   int32_t at_order;       /* q, number of levels in Eq. (7): 0 = N_p + 1; 1..6 */
 } adg_async;

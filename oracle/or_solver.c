@@ -165,6 +165,9 @@ int or_create(const or_config *cfg, const double *w0, int32_t max_steps, or_solv
     if (cfg->schedule_steps < 1) { or_destroy(s); return -1; }
     s->schedule = dup(cfg->schedule, (size_t)cfg->schedule_steps * (s->nif > 0 ? s->nif : 1));
     s->cfg.schedule = s->schedule;
+    /* a schedule holds delays from the L admissible ones, 0..L-1 (Sec. 4) */
+    for (size_t t = 0; t < (size_t)cfg->schedule_steps * (size_t)s->nif; ++t)
+      if (s->schedule[t] < 0 || s->schedule[t] >= cfg->L) { or_destroy(s); return -1; }
   }
   s->pe_off = malloc(sizeof(int32_t) * (cfg->n_pe + 1));
   for (int p = 0; p <= cfg->n_pe; ++p)

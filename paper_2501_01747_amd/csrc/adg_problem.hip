@@ -151,7 +151,20 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
     }
     if (std::fabs(s - 1.0) > 1e-12) return bad("pmf must sum to 1");
   }
-  if (as->mode == ADG_SCHEDULE && (!as->schedule || as->schedule_steps < 1)) return bad("schedule missing");
+  if (d->bc != ADG_PERIODIC && d->bc != ADG_TRANSMISSIVE) return bad("unknown boundary condition");
+  if (d->flux != ADG_RUSANOV && d->flux != ADG_HLLC) return bad("unknown numerical flux");
+  if (d->limiter) {
+    if (!(d->weno_eps > 0.0)) return bad("weno_eps must be > 0");
+    for (int k = 0; k < 3; ++k)
+      if (!(d->weno_gamma[k] > 0.0)) return bad("weno_gamma entries must be > 0");
+  }
+  if (as->mode == ADG_SCHEDULE) {
+    if (!as->schedule || as->schedule_steps < 1) return bad("schedule missing");
+    // every delay must be one of the L admissible ones: the history ring holds L - 1 + q levels
+    const long long nif = d->bc == ADG_PERIODIC ? as->n_pe : as->n_pe - 1;
+    for (long long t = 0; t < (long long)as->schedule_steps * nif; ++t)
+      if (as->schedule[t] < 0 || as->schedule[t] >= as->L) return bad("schedule delays must be in 0..L-1");
+  }
   const bool periodic = d->bc == ADG_PERIODIC;
   L.E = d->n_elem;
   L.M = d->order_p + 1;

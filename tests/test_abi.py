@@ -72,3 +72,30 @@ def test_peaks_library_exports_its_header():
     from paper_2501_01747_amd import peaks
 
     assert sorted(peaks.EXPORTED) == syms
+
+
+def test_argument_validation():
+    """Values outside the documented ranges are refused (workspace size 0, ADG_ERR_ARG at
+    create): boundary condition and flux codes, WENO constants, schedule delays >= L."""
+    import numpy as np
+
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    case, _ = gen.case_c2(E=64, length=2.0, shock_x=0.5, n_pe=4)
+    assert adg.Problem(case).workspace_bytes() > 0
+    for field, value in (("bc", 7), ("flux", 5), ("weno_eps", 0.0)):
+        pr = adg.Problem(case)
+        setattr(pr.disc, field, value)
+        assert pr.workspace_bytes() == 0, field
+    pr = adg.Problem(case)
+    pr.disc.weno_gamma[1] = -1.0
+    assert pr.workspace_bytes() == 0
+    sched = np.zeros((5, 3), dtype=np.int8)          # 4 PEs, transmissive: 3 interfaces
+    ok = dict(case, **{"async": dict(case["async"], mode="schedule", L=3, schedule=sched)})
+    assert adg.Problem(ok).workspace_bytes() > 0
+    for bad_value in (3, -1):
+        bad = sched.copy()
+        bad[2, 1] = bad_value
+        c = dict(case, **{"async": dict(case["async"], mode="schedule", L=3, schedule=bad)})
+        assert adg.Problem(c).workspace_bytes() == 0, bad_value
