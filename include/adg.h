@@ -96,7 +96,8 @@ typedef struct {
   int32_t n_quad;         /* Gauss-Legendre points per element: 0 = N_p + 1 (only value supported) */
   int32_t n_elem;         /* N_E >= 1 */
   double x_left, x_right;
-  int32_t bc;             /* ADG_PERIODIC | ADG_TRANSMISSIVE (ghost trace = interior trace) */
+  int32_t bc;             /* ADG_PERIODIC | ADG_TRANSMISSIVE (ghost trace = interior trace; one-step
+                             model only, the detailed model returns ADG_ERR_UNSUPPORTED) */
   int32_t flux;           /* ADG_RUSANOV | ADG_HLLC (HLLC with ADG_ONESTEP only) */
   int32_t limiter;        /* 1 = troubled-cell indicator + characteristic (AT-)WENO after every
                              stage (ADG_ONESTEP) */
