@@ -50,15 +50,20 @@ COPY_PROBE_BYTES = 256 * 1024 * 1024
 
 def pmc_probe(args):
     """Run under rocprofv3 --pmc: one plain device copy of COPY_PROBE_BYTES (the calibration
-    kernel for FETCH_SIZE / WRITE_SIZE), then args.steps time steps with plain launches."""
+    kernel for FETCH_SIZE / WRITE_SIZE), two launches of the FP64 FMA-chain kernel
+    (peaks.adg_peak_fp64_fmas() FMAs each: the calibration of the FP64 instruction
+    counters), then args.steps time steps with plain launches."""
     import torch
 
-    from paper_2501_01747_amd import adg
+    from paper_2501_01747_amd import adg, peaks
 
     src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    peaks.fp64_rate(n_reps=1)
     torch.cuda.synchronize()
     if args.workload == "c3":
         b, cases = build_c3_batch(args.precision)

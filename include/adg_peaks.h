@@ -25,11 +25,16 @@ int32_t adg_peak_copy(const void *src, void *dst, size_t bytes, int32_t n_reps, 
 /* Size of the output buffer adg_peak_fp64 needs (one double per thread). */
 size_t adg_peak_fp64_out_bytes(void);
 
-/* Eight independent FMA chains per thread over a grid of eight wavefronts per
-   SIMD, n_reps timed launches after one untimed one; *tflops receives
+/* Eight independent chains of 4096 FMAs per thread over a grid of eight wavefronts
+   per SIMD, n_reps timed launches after one untimed one; *tflops receives
    2 * (FMAs per launch) / (mean time per launch) in TFLOP/s.  out receives
    each thread's sum (adg_peak_fp64_out_bytes() bytes). */
 int32_t adg_peak_fp64(void *out, int32_t n_reps, void *hip_stream, double *tflops);
+
+/* FP64 fused multiply-adds one launch of adg_peak_fp64's kernel performs, counted per
+   lane: a kernel of known FP64 work, by which the per-kernel FP64 instruction counters
+   of a profiler can be read as operations. */
+double adg_peak_fp64_fmas(void);
 
 #ifdef __cplusplus
 }

@@ -87,6 +87,8 @@ extern "C" int32_t adg_peak_copy(const void *src, void *dst, size_t bytes, int32
 
 extern "C" size_t adg_peak_fp64_out_bytes(void) { return sizeof(double) * (size_t)kFmaBlocks * kFmaBlock; }
 
+extern "C" double adg_peak_fp64_fmas(void) { return (double)kFmaBlocks * kFmaBlock * kFmaIters * kFmaChains; }
+
 extern "C" int32_t adg_peak_fp64(void *out, int32_t n_reps, void *hip_stream, double *tflops) {
   if (!out || !tflops || n_reps < 1) return -(int32_t)hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)hip_stream;
@@ -95,7 +97,6 @@ extern "C" int32_t adg_peak_fp64(void *out, int32_t n_reps, void *hip_stream, do
     hipLaunchKernelGGL(fma_kernel, dim3(kFmaBlocks), dim3(kFmaBlock), 0, st, (double *)out, 0.999999, 1e-7);
   }, &ms);
   if (rc) return rc;
-  const double fmas = (double)kFmaBlocks * kFmaBlock * kFmaIters * kFmaChains;
-  *tflops = 2.0 * fmas / (ms * 1e-3) / 1e12;
+  *tflops = 2.0 * adg_peak_fp64_fmas() / (ms * 1e-3) / 1e12;
   return 0;
 }

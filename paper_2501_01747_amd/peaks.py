@@ -15,6 +15,7 @@ _sig = {
                                   C.POINTER(C.c_double)]),
     "adg_peak_fp64_out_bytes": (C.c_size_t, []),
     "adg_peak_fp64": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
+    "adg_peak_fp64_fmas": (C.c_double, []),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -25,6 +26,18 @@ for _name, (_res, _args) in _sig.items():
 EXPORTED = tuple(_sig)
 
 
+def fp64_rate(n_reps: int = 20) -> float:
+    """FP64 FMA rate (TFLOP/s) of the FMA-chain kernel on torch's current stream."""
+    import torch
+
+    out = torch.empty(adg_peak_fp64_out_bytes() // 8, dtype=torch.float64, device="cuda")
+    tf = C.c_double()
+    rc = adg_peak_fp64(out.data_ptr(), n_reps, torch.cuda.current_stream().cuda_stream, C.byref(tf))
+    if rc:
+        raise RuntimeError(f"adg_peak_fp64 failed ({rc})")
+    return tf.value
+
+
 def measure(copy_bytes: int = 1 << 30, n_reps: int = 20) -> dict:
     """Copy bandwidth (GB/s, read + write) over copy_bytes and the FP64 FMA rate (TFLOP/s),
     on torch's current stream of the current device."""
@@ -32,17 +45,14 @@ def measure(copy_bytes: int = 1 << 30, n_reps: int = 20) -> dict:
 
     src = torch.ones(copy_bytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    out = torch.empty(adg_peak_fp64_out_bytes() // 8, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    gbs, tf = C.c_double(), C.c_double()
+    gbs = C.c_double()
     rc = adg_peak_copy(src.data_ptr(), dst.data_ptr(), copy_bytes, n_reps, stream, C.byref(gbs))
     if rc:
         raise RuntimeError(f"adg_peak_copy failed ({rc})")
-    rc = adg_peak_fp64(out.data_ptr(), n_reps, stream, C.byref(tf))
-    if rc:
-        raise RuntimeError(f"adg_peak_fp64 failed ({rc})")
     if not torch.equal(dst[:1024], src[:1024]):
         raise RuntimeError("copy probe produced wrong data")
-    del src, dst, out
+    del src, dst
+    tf = fp64_rate(n_reps)
     torch.cuda.empty_cache()
-    return {"copy_GBps": gbs.value, "fp64_vector_TFLOPs": tf.value, "copy_bytes": copy_bytes}
+    return {"copy_GBps": gbs.value, "fp64_vector_TFLOPs": tf, "copy_bytes": copy_bytes}

@@ -66,12 +66,14 @@ def test_peaks_library_exports_its_header():
     src = open(os.path.join(ROOT, "include", "adg_peaks.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     syms = sorted(set(re.findall(r"\b(adg_[a-z0-9_]+)\s*\(", src)))
-    assert syms == ["adg_peak_copy", "adg_peak_fp64", "adg_peak_fp64_out_bytes"]
+    assert syms == ["adg_peak_copy", "adg_peak_fp64", "adg_peak_fp64_fmas", "adg_peak_fp64_out_bytes"]
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2501_01747_amd", "libadg_peaks.so"))
     assert all(hasattr(lib, s) for s in syms)
     from paper_2501_01747_amd import peaks
 
     assert sorted(peaks.EXPORTED) == syms
+    # eight chains of 4096 FMAs per thread, one thread per output double
+    assert peaks.adg_peak_fp64_fmas() == peaks.adg_peak_fp64_out_bytes() // 8 * 8 * 4096
 
 
 def test_argument_validation():
