@@ -37,12 +37,18 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane l takes lane 7-l of its group of 8
 constexpr int kDppMirror = 0x140;     // lane l takes lane 15-l of its group of 16
 
+// n mod d for a step count n >= 0 and 0 < d: in 32-bit arithmetic while n fits
+// (a 64-bit remainder by a run-time divisor is a long instruction sequence).
+__device__ __forceinline__ int step_mod(long long n, int d) {
+  return n >= 0 && n <= 0x7fffffffll ? (int)((unsigned)n % (unsigned)d) : (int)(n % d);
+}
+
 // Delay at PE interface i for time step n (Sec. 4), clamped so that all q
 // levels n-k .. n-k-q+1 exist.
 __device__ __forceinline__ int eff_delay(const DelayParams &d, long long n, int i) {
   int k = 0;
   if (d.mode == 1) {
-    k = (int)(n % d.L);
+    k = step_mod(n, d.L);
   } else if (d.mode == 2) {
     unsigned long long ctr = (unsigned long long)n * (unsigned long long)d.nif + (unsigned long long)i;
     unsigned long long z = splitmix64(d.seed ^ (ctr * 0x9E3779B97F4A7C15ull));
@@ -51,7 +57,7 @@ __device__ __forceinline__ int eff_delay(const DelayParams &d, long long n, int 
     for (int j = 0; j < d.L; ++j)
       if (u < d.cum[j]) { k = j; break; }
   } else if (d.mode == 3) {
-    k = d.sched[(n % d.sched_steps) * d.nif + i];
+    k = d.sched[(long long)step_mod(n, d.sched_steps) * d.nif + i];
   }
   if (k <= 0) return 0;
   long long lim = n - d.q + 1;

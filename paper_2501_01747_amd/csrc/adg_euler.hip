@@ -423,12 +423,13 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   const bool calc = LIM ? live && lane >= 1 && lane <= 62 && (a.periodic ? xu <= E : (xu >= 0 && xu < E)) : own;
   // computes the flux at face xu + 1 (faces 0..E; periodic faces wrap)
   const bool face_lane = live && lane <= 62 && (a.periodic ? xu + 1 <= E - 1 + H : (xu >= -1 && xu < E));
-  int x = xu % E;
-  if (x < 0) x += E;
+  int x = xu;   // within a few periods of [0, E)
+  while (x < 0) x += E;
+  while (x >= E) x -= E;
   int fidx = xu + 1;
   if (a.periodic && (fidx < 0 || fidx > E)) fidx = fidx < 0 ? fidx + E : fidx - E;
   const long long n = *a.step;
-  const int nmod = (int)(n % a.ring.D);
+  const int nmod = step_mod(n, a.ring.D);
   bool ok = true;
   const double *w0 = a.w0, *ws = a.ws;
   double *wout = a.wout;

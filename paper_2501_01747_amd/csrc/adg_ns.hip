@@ -26,6 +26,7 @@
 namespace adg {
 
 constexpr int kThreadsBatch = 256;   // batched kernel: more resident workgroups per CU
+constexpr int kBatchLanesPerPoint = 4;   // batched kernel: lanes per point of the point phase
 constexpr int kThreadsSingle = 512;  // one problem: more lanes per tile, shorter phases
 
 // Sum over the LP lanes of a point group (every lane receives the same value:
@@ -117,7 +118,9 @@ struct NsLds {
 // the magnitude of the state (pressure-sized fluxes would otherwise lose about
 // 4 digits of their element-to-element differences).  Gradients at nodes and
 // traces are likewise mode 0 plus the FP32 sum of the higher modes.
-template <int M, int NS, typename OpT, int NTH, int TE>
+// LPP: lanes per point of the point phase (0: the workgroup's lanes spread over
+// 32 or 64 point slots).
+template <int M, int NS, typename OpT, int NTH, int TE, int LPP = 0>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
                                         double *wout, int stage, int advance, const RkStage rk, double *kbuf,
                                         int e0, int ntiles,
@@ -158,7 +161,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const int E = a.E;
   const int nloc = min(TE, E - e0);
   const long long n = *a.step;
-  const int nmod = (int)(n % a.ring.D);   // the current level's ring slot
+  const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
   const NsMech *__restrict__ mk = &smech;
   const int q_at = a.dl.q;
   bool ok = true;
@@ -191,22 +194,25 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       sw[m] = 0.0;
       if (idx < V * M * NH) {
         const int c = idx / NH, l = idx % NH;
-        int e = (e0 - 2 + l) % E;
-        if (e < 0) e += E;
+        int e = e0 - 2 + l;   // periodic: within a few periods of [0, E)
+        while (e < 0) e += E;
+        while (e >= E) e -= E;
         sw[m] = ws[sidx(e, c, V * M)];
       }
     }
     int fi = -1;
     if (t < NF) {
-      int f = (e0 - 1 + t) % E;
-      if (f < 0) f += E;
+      int f = e0 - 1 + t;
+      while (f < 0) f += E;
+      while (f >= E) f -= E;
       fi = a.face_if[f];
     }
 #pragma unroll
     for (int m = 0; m < kOut; ++m) {
       const int idx = t + m * NTH;
+      const int c = idx / TE, el = idx % TE;
       w0pre[m] = 0.0;
-      if (use_prev && idx < V * M * nloc) w0pre[m] = prev[sidx(e0 + idx % nloc, idx / nloc, V * M)];
+      if (use_prev && idx < V * M * TE && el < nloc) w0pre[m] = prev[sidx(e0 + el, c, V * M)];
     }
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
@@ -322,185 +328,188 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   //    At the nodes the lanes also form the Gibbs energies and concentrations of their species.
   {
     constexpr int kSlots = NP <= 32 ? 32 : 64;   // point slots per workgroup
-    constexpr int LP = NTH / kSlots;             // lanes per point
+    constexpr int LP = LPP > 0 ? LPP : NTH / kSlots;   // lanes per point
     static_assert(LP >= 1 && LP <= 64 && (LP & (LP - 1)) == 0 && NP <= NTH / LP, "every point has a lane group");
     constexpr int NO = (NS + LP - 1) / LP;
-    const int k = t % LP;
-    const int p = min(t / LP, NP - 1);          // spare groups redo the last point and write nothing
-    const bool writer = t / LP < NP;
-    const bool node = p < NN;
-    int qn = 0, ff = 0, side = 0, l, lq;
-    if (node) {
-      qn = p % Q;
-      l = p / Q + 2;
-      lq = p / Q + 1;
-    } else {
-      const int pp = p - NN;
-      ff = pp >> 1;                             // face e0 + ff
-      side = pp & 1;                            // 0: the element left of the face (its xi = +1)
-      l = ff + 1 + side;
-      lq = ff + side;                           // gradient slot; its faces are lq and lq + 1
-    }
-    const bool pe = !node && sI[ff + 1] >= 0;
-    // value, gradient and synchronous gradient (PE-interface traces) of variable v
-    auto eval = [&](int v, double &x, double &d, double &ds) {
+    // a wavefront whose lanes all lie past the last point's group has no point to form
+    if ((t & ~63) / LP < NP) {
+      const int k = t % LP;
+      const int p = min(t / LP, NP - 1);          // spare groups redo the last point and write nothing
+      const bool writer = t / LP < NP;
+      const bool node = p < NN;
+      int qn = 0, ff = 0, side = 0, l, lq;
       if (node) {
-        OpT xo = 0, dO = 0;
-#pragma unroll
-        for (int j = kMixed ? 1 : 0; j < M; ++j) {
-          xo += (OpT)sB[qn][j] * (OpT)sW[v * M + j][l];
-          dO += (OpT)sB[qn][j] * (OpT)sQ[v * M + j][lq];
-        }
-        x = kMixed ? sW[v * M][l] + (double)xo : (double)xo;
-        d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
-        ds = d;
+        qn = p % Q;
+        l = p / Q + 2;
+        lq = p / Q + 1;
       } else {
-        const OpT sgn = side ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
-        OpT dO = 0, pj = kMixed ? sgn : (OpT)1;
-#pragma unroll
-        for (int j = kMixed ? 1 : 0; j < M; ++j) {
-          dO += pj * (OpT)sQ[v * M + j][lq];
-          pj *= sgn;
-        }
-        x = side ? sTm[v][l] : sTp[v][l];
-        d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
-        ds = d;
-        if (pe) {
-          // synchronous gradient trace at a PE interface: undo the AT central traces of the element's faces
-          const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
-          double corr = 0.0, pk = 1.0;
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
-            pk *= side ? -1.0 : 1.0;
-          }
-          ds = d + corr;
-        }
+        const int pp = p - NN;
+        ff = pp >> 1;                             // face e0 + ff
+        side = pp & 1;                            // 0: the element left of the face (its xi = +1)
+        l = ff + 1 + side;
+        lq = ff + side;                           // gradient slot; its faces are lq and lq + 1
       }
-    };
-    double wr, dr0, sr0, wm, dm, sm, we, de, se;
-    eval(0, wr, dr0, sr0);
-    eval(1, wm, dm, sm);
-    eval(2, we, de, se);
-    double wy[NO], dy[NO], sy[NO];
+      const bool pe = !node && sI[ff + 1] >= 0;
+      // value, gradient and synchronous gradient (PE-interface traces) of variable v
+      auto eval = [&](int v, double &x, double &d, double &ds) {
+        if (node) {
+          OpT xo = 0, dO = 0;
 #pragma unroll
-    for (int m = 0; m < NO; ++m) {
-      const int i = k + LP * m;
-      if (i < NS) eval(3 + i, wy[m], dy[m], sy[m]);
-      else wy[m] = dy[m] = sy[m] = 0.0;
-    }
-    const double rho_inv = 1.0 / wr;
-    const double u = wm * rho_inv;
-    const double estar = we * rho_inv - 0.5 * u * u;
-    double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Rmix = 0.0;
+          for (int j = kMixed ? 1 : 0; j < M; ++j) {
+            xo += (OpT)sB[qn][j] * (OpT)sW[v * M + j][l];
+            dO += (OpT)sB[qn][j] * (OpT)sQ[v * M + j][lq];
+          }
+          x = kMixed ? sW[v * M][l] + (double)xo : (double)xo;
+          d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
+          ds = d;
+        } else {
+          const OpT sgn = side ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
+          OpT dO = 0, pj = kMixed ? sgn : (OpT)1;
 #pragma unroll
-    for (int m = 0; m < NO; ++m) {
-      const int i = k + LP * m;
-      if (i >= NS) continue;
-      const double yr = (wy[m] * rho_inv) * mk->Ri[i];
-      c[0] += yr * (mk->a[i][0] - 1.0);
-      c[1] += yr * mk->h2[i][0];
-      c[2] += yr * mk->h2[i][1];
-      c[3] += yr * mk->h2[i][2];
-      c[4] += yr * mk->h2[i][3];
-      c[5] += yr * mk->a[i][5];
-      Rmix += yr;
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) c[q] = group_sum<LP>(c[q]);
-    Rmix = group_sum<LP>(Rmix);
-    double T, cv;
-    const bool conv = newton_T(c, mk->T_guess, estar, T, cv);
-    const double lnT = log(T);   // shared by the viscosity law and the Gibbs energies
-    const double cp = cv + Rmix;
-    const double pr = wr * Rmix * T;
-    const double snd = sqrt(cp / cv * pr * rho_inv);
-    if (writer) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
-    double g0 = wm, g1 = wm * u + pr, g2 = u * (we + pr);
-    double gs1 = g1, gs2 = g2;
-    double gy[NO], gsy[NO];
-#pragma unroll
-    for (int m = 0; m < NO; ++m) gy[m] = gsy[m] = wy[m] * u;
-    if (a.viscous) {
-      const double mu = mk->mu_ref * exp(mk->mu_exp * (lnT - mk->ln_T_ref));
-      const double kappa = mu * cp * mk->inv_prandtl;
-      const double rhoD = mu * mk->inv_prandtl;
-      const double En = we * rho_inv;
-      // f^d of Eq. (2)-(3) for one gradient: tau = 4/3 mu u_x, heat flux -k T_x + sum_i h_i J_i,
-      // unit Lewis number J_i = -rho D dY_i/dx with rho D = mu/Pr
-      auto diffusive = [&](double d0, double d1, double d2, const double (&dyy)[NO], double (&gyy)[NO],
-                           double &h1, double &h2) {
-        const double u_x = (d1 - u * d0) * rho_inv;
-        const double e_x = (d2 - En * d0) * rho_inv - u * u_x;
-        double sum_eY = 0.0, sum_hJ = 0.0;
-#pragma unroll
-        for (int m = 0; m < NO; ++m) {
-          const int i = k + LP * m;
-          if (i >= NS) continue;
-          const double *ai = mk->a[i];
-          const double *h2i = mk->h2[i];
-          const double hT = T * (ai[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3])))) + ai[5];  // h_i/R_i
-          const double Yx = (dyy[m] - (wy[m] * rho_inv) * d0) * rho_inv;
-          sum_eY += mk->Ri[i] * (hT - T) * Yx;
-          const double J = -rhoD * Yx;
-          sum_hJ += mk->Ri[i] * hT * J;
-          gyy[m] += J;                  // f^d_i = -J_i
-        }
-        sum_eY = group_sum<LP>(sum_eY);
-        sum_hJ = group_sum<LP>(sum_hJ);
-        const double T_x = (e_x - sum_eY) / cv;
-        const double tau = (4.0 / 3.0) * mu * u_x;
-        const double qh = -kappa * T_x + sum_hJ;
-        h1 -= tau;
-        h2 -= tau * u - qh;
-      };
-      diffusive(dr0, dm, de, dy, gy, g1, g2);
-      if (pe) diffusive(sr0, sm, se, sy, gsy, gs1, gs2);
-    }
-    if (writer) {
-      if (node) {
-        if (k == 0) {
-          sG[0][p] = g0;
-          sG[1][p] = g1;
-          sG[2][p] = g2;
-          sT[p] = T;
-        }
-        const double invT = 1.0 / T;
-        if (k == 1) {
-          sLnT[p] = lnT;
-          sInvT[p] = invT;
-        }
-#pragma unroll
-        for (int m = 0; m < NO; ++m) {
-          const int i = k + LP * m;
-          if (i >= NS) continue;
-          sG[3 + i][p] = gy[m];
-          const double *ci = mk->a[i];
-          const double *h2i = mk->h2[i];
-          const double *s2i = mk->s2[i];
-          const double hRT = ci[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3]))) + ci[5] * invT;
-          const double sR = ci[0] * lnT + T * (ci[1] + T * (s2i[0] + T * (s2i[1] + T * s2i[2]))) + ci[6];
-          sGRT[i][p] = hRT - sR;
-          sConc[i][p] = wy[m] * mk->invW[i];
-        }
-      } else {
-        if (k == 0) {
-          sGf[side][0][ff] = g0;
-          sGf[side][1][ff] = g1;
-          sGf[side][2][ff] = g2;
-          sLam[side][ff] = fabs(u) + snd;
+          for (int j = kMixed ? 1 : 0; j < M; ++j) {
+            dO += pj * (OpT)sQ[v * M + j][lq];
+            pj *= sgn;
+          }
+          x = side ? sTm[v][l] : sTp[v][l];
+          d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
+          ds = d;
           if (pe) {
-            sGs[side][0][ff] = g0;
-            sGs[side][1][ff] = gs1;
-            sGs[side][2][ff] = gs2;
+            // synchronous gradient trace at a PE interface: undo the AT central traces of the element's faces
+            const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
+            double corr = 0.0, pk = 1.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
+              pk *= side ? -1.0 : 1.0;
+            }
+            ds = d + corr;
           }
         }
+      };
+      double wr, dr0, sr0, wm, dm, sm, we, de, se;
+      eval(0, wr, dr0, sr0);
+      eval(1, wm, dm, sm);
+      eval(2, we, de, se);
+      double wy[NO], dy[NO], sy[NO];
 #pragma unroll
-        for (int m = 0; m < NO; ++m) {
-          const int i = k + LP * m;
-          if (i >= NS) continue;
-          sGf[side][3 + i][ff] = gy[m];
-          if (pe) sGs[side][3 + i][ff] = gsy[m];
+      for (int m = 0; m < NO; ++m) {
+        const int i = k + LP * m;
+        if (i < NS) eval(3 + i, wy[m], dy[m], sy[m]);
+        else wy[m] = dy[m] = sy[m] = 0.0;
+      }
+      const double rho_inv = 1.0 / wr;
+      const double u = wm * rho_inv;
+      const double estar = we * rho_inv - 0.5 * u * u;
+      double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Rmix = 0.0;
+#pragma unroll
+      for (int m = 0; m < NO; ++m) {
+        const int i = k + LP * m;
+        if (i >= NS) continue;
+        const double yr = (wy[m] * rho_inv) * mk->Ri[i];
+        c[0] += yr * (mk->a[i][0] - 1.0);
+        c[1] += yr * mk->h2[i][0];
+        c[2] += yr * mk->h2[i][1];
+        c[3] += yr * mk->h2[i][2];
+        c[4] += yr * mk->h2[i][3];
+        c[5] += yr * mk->a[i][5];
+        Rmix += yr;
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) c[q] = group_sum<LP>(c[q]);
+      Rmix = group_sum<LP>(Rmix);
+      double T, cv;
+      const bool conv = newton_T(c, mk->T_guess, estar, T, cv);
+      const double lnT = log(T);   // shared by the viscosity law and the Gibbs energies
+      const double cp = cv + Rmix;
+      const double pr = wr * Rmix * T;
+      const double snd = sqrt(cp / cv * pr * rho_inv);
+      if (writer) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
+      double g0 = wm, g1 = wm * u + pr, g2 = u * (we + pr);
+      double gs1 = g1, gs2 = g2;
+      double gy[NO], gsy[NO];
+#pragma unroll
+      for (int m = 0; m < NO; ++m) gy[m] = gsy[m] = wy[m] * u;
+      if (a.viscous) {
+        const double mu = mk->mu_ref * exp(mk->mu_exp * (lnT - mk->ln_T_ref));
+        const double kappa = mu * cp * mk->inv_prandtl;
+        const double rhoD = mu * mk->inv_prandtl;
+        const double En = we * rho_inv;
+        // f^d of Eq. (2)-(3) for one gradient: tau = 4/3 mu u_x, heat flux -k T_x + sum_i h_i J_i,
+        // unit Lewis number J_i = -rho D dY_i/dx with rho D = mu/Pr
+        auto diffusive = [&](double d0, double d1, double d2, const double (&dyy)[NO], double (&gyy)[NO],
+                             double &h1, double &h2) {
+          const double u_x = (d1 - u * d0) * rho_inv;
+          const double e_x = (d2 - En * d0) * rho_inv - u * u_x;
+          double sum_eY = 0.0, sum_hJ = 0.0;
+#pragma unroll
+          for (int m = 0; m < NO; ++m) {
+            const int i = k + LP * m;
+            if (i >= NS) continue;
+            const double *ai = mk->a[i];
+            const double *h2i = mk->h2[i];
+            const double hT = T * (ai[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3])))) + ai[5];  // h_i/R_i
+            const double Yx = (dyy[m] - (wy[m] * rho_inv) * d0) * rho_inv;
+            sum_eY += mk->Ri[i] * (hT - T) * Yx;
+            const double J = -rhoD * Yx;
+            sum_hJ += mk->Ri[i] * hT * J;
+            gyy[m] += J;                  // f^d_i = -J_i
+          }
+          sum_eY = group_sum<LP>(sum_eY);
+          sum_hJ = group_sum<LP>(sum_hJ);
+          const double T_x = (e_x - sum_eY) / cv;
+          const double tau = (4.0 / 3.0) * mu * u_x;
+          const double qh = -kappa * T_x + sum_hJ;
+          h1 -= tau;
+          h2 -= tau * u - qh;
+        };
+        diffusive(dr0, dm, de, dy, gy, g1, g2);
+        if (pe) diffusive(sr0, sm, se, sy, gsy, gs1, gs2);
+      }
+      if (writer) {
+        if (node) {
+          if (k == 0) {
+            sG[0][p] = g0;
+            sG[1][p] = g1;
+            sG[2][p] = g2;
+            sT[p] = T;
+          }
+          const double invT = 1.0 / T;
+          if (k == 1) {
+            sLnT[p] = lnT;
+            sInvT[p] = invT;
+          }
+#pragma unroll
+          for (int m = 0; m < NO; ++m) {
+            const int i = k + LP * m;
+            if (i >= NS) continue;
+            sG[3 + i][p] = gy[m];
+            const double *ci = mk->a[i];
+            const double *h2i = mk->h2[i];
+            const double *s2i = mk->s2[i];
+            const double hRT = ci[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3]))) + ci[5] * invT;
+            const double sR = ci[0] * lnT + T * (ci[1] + T * (s2i[0] + T * (s2i[1] + T * s2i[2]))) + ci[6];
+            sGRT[i][p] = hRT - sR;
+            sConc[i][p] = wy[m] * mk->invW[i];
+          }
+        } else {
+          if (k == 0) {
+            sGf[side][0][ff] = g0;
+            sGf[side][1][ff] = g1;
+            sGf[side][2][ff] = g2;
+            sLam[side][ff] = fabs(u) + snd;
+            if (pe) {
+              sGs[side][0][ff] = g0;
+              sGs[side][1][ff] = gs1;
+              sGs[side][2][ff] = gs2;
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < NO; ++m) {
+            const int i = k + LP * m;
+            if (i >= NS) continue;
+            sGf[side][3 + i][ff] = gy[m];
+            if (pe) sGs[side][3 + i][ff] = gsy[m];
+          }
         }
       }
     }
@@ -557,8 +566,9 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 #pragma unroll
   for (int m = 0; m < kOut; ++m) {
     const int idx = t + m * NTH;
-    if (idx >= V * M * nloc) break;
-    const int c = idx / nloc, el = idx % nloc;
+    if (idx >= V * M * TE) break;
+    const int c = idx / TE, el = idx % TE;   // output component c of local element el
+    if (el >= nloc) continue;
     const int v = c / M, j = c % M;
     OpT vol = 0;
     double srcs = 0.0;
@@ -651,15 +661,15 @@ __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *_
   const int M = a.M;
   const RkStage rk = rk_stage(ADG_SSPRK3, stage);   // batches run SSP-RK3
   if (M == 2) {
-    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m2, smech);
+    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m2, smech);
   } else if constexpr (MMAX >= 3) {
     if (M == 3) {
-      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m3, smech);
+      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m3, smech);
     } else if constexpr (MMAX >= 4) {
       if (M == 4) {
-        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m4, smech);
+        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m4, smech);
       } else if constexpr (MMAX >= 5) {
-        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m5, smech);
+        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m5, smech);
       }
     }
   }
