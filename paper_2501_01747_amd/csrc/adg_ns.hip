@@ -516,35 +516,43 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   }
   __syncthreads();
 
-  // chemistry (Sec. 2: W_i omega_i): one lane per (node, reaction), then one lane per (node, species)
-  for (int idx = t; idx < nr * NN; idx += NTH) {
-    const int r = idx / NN, p = idx % NN;
-    const double lnT = sLnT[p];
-    const double lnkf = mk->lnA[r] + mk->b[r] * lnT - mk->EaR[r] * sInvT[p];
-    double dG = 0.0;
-    for (int g = 0; g < mk->ng[r]; ++g) dG += mk->gnu[r][g] * sGRT[mk->gidx[r][g]][p];
-    const double lnKc = -dG + (double)mk->dnu[r] * (mk->ln_p_over_Ru - lnT);
-    double fwd = exp(lnkf), rev = exp(lnkf - lnKc);
+  // chemistry (Sec. 2: W_i omega_i): one lane per (node, reaction), then one lane per (node, species).
+  // The rate of one (node, reaction) is branch-free (the unused entries of a reaction's Gibbs
+  // list hold coefficient 0, a missing reactant or product multiplies by 1), so a lane forms
+  // two of them side by side and their dependent chains overlap.
+  {
+    auto rate = [&](int idx) -> double {
+      const int r = idx / NN, p = idx % NN;
+      const double lnT = sLnT[p];
+      const double lnkf = mk->lnA[r] + mk->b[r] * lnT - mk->EaR[r] * sInvT[p];
+      double dG = 0.0;
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int sf = mk->rf[r][m], sb = mk->rr[r][m];
-      if (sf >= 0) fwd *= sConc[sf][p];
-      if (sb >= 0) rev *= sConc[sb][p];
+      for (int g = 0; g < 4; ++g) dG += mk->gnu[r][g] * sGRT[mk->gidx[r][g]][p];
+      const double lnKc = -dG + (double)mk->dnu[r] * (mk->ln_p_over_Ru - lnT);
+      double fwd = exp(lnkf), rev = exp(lnkf - lnKc);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int sf = mk->rf[r][m], sb = mk->rr[r][m];
+        fwd *= sf >= 0 ? sConc[max(sf, 0)][p] : 1.0;
+        rev *= sb >= 0 ? sConc[max(sb, 0)][p] : 1.0;
+      }
+      return fwd - rev;
+    };
+    const int nitems = nr * NN;
+    for (int idx = t; idx < nitems; idx += 2 * NTH) {
+      const bool two = idx + NTH < nitems;
+      const int idx2 = two ? idx + NTH : idx;
+      const double ra = rate(idx), rb = rate(idx2);
+      sRate[idx / NN][idx % NN] = ra;
+      if (two) sRate[idx2 / NN][idx2 % NN] = rb;
     }
-    sRate[r][p] = fwd - rev;
-  }
-  __syncthreads();
-  for (int idx = t; idx < NS * NN; idx += NTH) {
-    const int i = idx / NN, p = idx % NN;
-    double wdot = 0.0;
-    const int cnt = mk->spn[i];
-    for (int m = 0; m < cnt; ++m) wdot += (double)mk->spnu[i][m] * sRate[mk->spr[i][m]][p];
-    sS[i][p] = mk->W[i] * wdot;
   }
 
   // 5. Rusanov total flux f = (g- + g+)/2 - lambda (w+ - w-)/2 at faces e0 + ff; at PE
   //    interfaces the synchronous flux is published and the AT combination is used
-  for (int idx = t; idx < V * (TE + 1); idx += NTH) {
+  //    (needs only the point phase: it runs beside the rates, from the last lane down, where
+  //    lanes hold one rate item, not two)
+  for (int idx = NTH - 1 - t; idx < V * (TE + 1); idx += NTH) {
     const int v = idx / (TE + 1), ff = idx % (TE + 1);
     const double wm = sTp[v][ff + 1], wp = sTm[v][ff + 2];
     const double lam = fmax(sLam[0][ff], sLam[1][ff]);
@@ -559,6 +567,15 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       F = 0.5 * (sGf[0][v][ff] + sGf[1][v][ff] - diss);
     }
     sF[v][ff] = F;
+  }
+  __syncthreads();
+  // species production W_i omega_i = W_i sum_r nu_ir (rate r), one lane per (node, species)
+  for (int idx = t; idx < NS * NN; idx += NTH) {
+    const int i = idx / NN, p = idx % NN;
+    double wdot = 0.0;
+    const int cnt = mk->spn[i];
+    for (int m = 0; m < cnt; ++m) wdot += (double)mk->spnu[i][m] * sRate[mk->spr[i][m]][p];
+    sS[i][p] = mk->W[i] * wdot;
   }
   __syncthreads();
 
@@ -768,7 +785,6 @@ adg_status ns_build_mech(const adg_physics *ph, NsMech &hm) {
         ++g;
       }
     }
-    hm.ng[r] = g;
   }
   return ADG_OK;
 }

@@ -28,9 +28,10 @@ struct NsMech {
   int dnu[kNsMaxReactions];
   // compact per-reaction form for one lane per (point, reaction): the species
   // multiplied into the forward and reverse rates (-1 = none) and the nonzero
-  // net coefficients nu_i = nu''_i - nu'_i
+  // net coefficients nu_i = nu''_i - nu'_i with their species, padded to four
+  // entries with coefficient 0 (species 0)
   int rf[kNsMaxReactions][2], rr[kNsMaxReactions][2];
-  int ng[kNsMaxReactions], gidx[kNsMaxReactions][4];
+  int gidx[kNsMaxReactions][4];
   double gnu[kNsMaxReactions][4];
   // per species, the reactions with a nonzero net coefficient (increasing r) and that coefficient
   int spn[kNsMaxSpecies];
