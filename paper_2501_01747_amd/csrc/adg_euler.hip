@@ -357,12 +357,13 @@ __device__ __forceinline__ bool weno_group(const EulerArgs &a, const LimiterArgs
 }
 
 // Slots of a wavefront's round (kSlotLanes elements, two slots each): the ghost or AT
-// neighbour of every face of the element that needs one, then the face's source points
-// at its slot.  One pass over each element's first such face, a second over elements
-// whose both faces need one.
+// neighbour of every face of the element that needs one (AT slots only unless at_ready:
+// the first round's are gathered at the start of the kernel), then the face's source
+// points at its slot.  One pass over each element's first such face, a second over
+// elements whose both faces need one.
 template <int M>
 __device__ __forceinline__ void fill_slots(const EulerArgs &a, long long n, int nmod, NbSide (&sd)[2], bool mine,
-                                           int rank, double *ls, int lane) {
+                                           int rank, double *ls, int lane, bool at_ready) {
   const bool need0 = sd[0].ghost || sd[0].k > 0, need1 = sd[1].ghost || sd[1].k > 0;
   const bool two = mine && need0 && need1;
 #pragma unroll 1
@@ -378,7 +379,7 @@ __device__ __forceinline__ void fill_slots(const EulerArgs &a, long long n, int 
         for (int v = 0; v < 5; ++v)
 #pragma unroll
           for (int j = 0; j < M; ++j) sl[v * M + j] = j == 0 ? ls[(v * M) * 64 + lane] : 0.0;
-      } else {
+      } else if (!at_ready) {
         double c[5 * M];
         at_neighbour<M>(a, n, nmod, side == 0 ? sd[0].i : sd[1].i, side == 0 ? sd[0].k : sd[1].k, side, c);
 #pragma unroll
@@ -388,6 +389,43 @@ __device__ __forceinline__ void fill_slots(const EulerArgs &a, long long n, int 
       t.base = 5 * M * 64 + slot * 5 * M;
       t.sv = M;
       t.sj = 1;
+    }
+  }
+}
+
+// The AT neighbours of a wavefront's first round (slot 2r + side belongs to the r-th lane
+// of the wavefront that needs a slot), gathered by all lanes of the wavefront at once:
+// lane l forms components l, l + 64, l + 128 of the slots' 8 x 5M, each the same Eq. (11)
+// combination at_neighbour forms (levels in the same order, so the same rounding).
+// Ghost slots are left to their owners.
+template <int M>
+__device__ __forceinline__ void gather_first_slots(const EulerArgs &a, int nmod, const NbSide (&sd)[2],
+                                                   unsigned long long nball, double *ls, int lane) {
+  constexpr int C = 5 * M;
+  const int q = a.dl.q;
+#pragma unroll
+  for (int q0 = 0; q0 < kNbSlots * C; q0 += 64) {
+    const int pair = q0 + lane;
+    const int s = min(pair / C, kNbSlots - 1), comp = pair % C;
+    const int r = s >> 1, side = s & 1;
+    unsigned long long m = nball;
+    for (int j = 0; j < r; ++j) m &= m - 1;   // drop the r lowest lanes that need a slot
+    const int src = m ? __ffsll((long long)m) - 1 : 0;
+    const int i0 = __shfl(sd[0].i, src), i1 = __shfl(sd[1].i, src);
+    const int k0 = __shfl(sd[0].k, src), k1 = __shfl(sd[1].k, src);
+    const int i = side ? i1 : i0, k = side ? k1 : k0;   // a ghost side has i = -1, k = 0
+    if (pair < kNbSlots * C && m != 0 && i >= 0 && k > 0) {
+      const int off = a.ring.off_U + (side == 0 ? 0 : C) + comp;
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool in = j < q;
+        const double w = in ? at_weight(q, k, j) : 0.0;
+        acc += w * ring_at(a.ring, ring_slot(nmod, k + (in ? j : 0), a.ring.D), a.stage, a.dl.nif, i)[off];
+      }
+      for (int j = 4; j < q; ++j)
+        acc += at_weight(q, k, j) * ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), a.stage, a.dl.nif, i)[off];
+      ls[5 * M * 64 + s * C + comp] = acc;
     }
   }
 }
@@ -463,6 +501,32 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   double Fat[V];
   if (kf > 0) at_flux(a, nmod, iface, kf, Fat);
 
+  // with the limiter: this wavefront's outputs, [component][lane], and the neighbour
+  // sources of the owned elements.  Faces at a transmissive end or a delayed PE interface
+  // need a slot: kSlotLanes such elements per round, two slots each; the first round's AT
+  // neighbours are gathered now, while the state loads are in flight.
+  double *ls = LIM ? lds + (threadIdx.x >> 6) * lds_wave_doubles<M>() : nullptr;
+  NbSide sd[2];
+  bool needs = false;
+  unsigned long long nball = 0;
+  if constexpr (LIM) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const bool ghost = own && !a.periodic && (side == 0 ? x == 0 : x == E - 1);
+      const int i = (own && !ghost) ? a.face_if[side == 0 ? x : x + 1] : -1;
+      const int k = i >= 0 ? eff_delay(a.dl, n, i) : 0;
+      sd[side].base = lane + (side == 0 ? -1 : 1);
+      sd[side].sv = M * 64;
+      sd[side].sj = 64;
+      sd[side].i = i;
+      sd[side].k = k;
+      sd[side].ghost = ghost;
+      needs = needs || ghost || k > 0;
+    }
+    nball = __ballot(needs);
+    gather_first_slots<M>(a, nmod, sd, nball, ls, lane);
+  }
+
   double wl[V], wr[V];
   traces<M>(u, wl, wr);
 #pragma unroll
@@ -486,8 +550,6 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   for (int v = 0; v < V; ++v) Fl[v] = dpp_move<kDppFromPrev>(F[v]);
   const int if_left = dpp_move<kDppFromPrev>(iface);
 
-  // with the limiter: this wavefront's outputs, [component][lane]
-  double *ls = LIM ? lds + (threadIdx.x >> 6) * lds_wave_doubles<M>() : nullptr;
   if (calc) {
     // b_j = sum_q w_q P_j'(xi_q) f_q - F_{e+1} P_j(1) + F_e P_j(-1); the face terms go in first
     double vol[V][M], srcR[M];
@@ -554,28 +616,11 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   }
 
   if constexpr (LIM) {
-    // neighbour sources of the owned elements; faces at a transmissive end or a delayed
-    // PE interface need a slot: kSlotLanes such elements per round, two slots each
-    NbSide sd[2];
-    bool needs = false;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const bool ghost = own && !a.periodic && (side == 0 ? x == 0 : x == E - 1);
-      const int i = (own && !ghost) ? a.face_if[side == 0 ? x : x + 1] : -1;
-      const int k = i >= 0 ? eff_delay(a.dl, n, i) : 0;
-      sd[side].base = lane + (side == 0 ? -1 : 1);
-      sd[side].sv = M * 64;
-      sd[side].sj = 64;
-      sd[side].i = i;
-      sd[side].k = k;
-      sd[side].ghost = ghost;
-      needs = needs || ghost || k > 0;
-    }
-    const unsigned long long nball = __ballot(needs);
     const int rank = __popcll(nball & ((1ull << lane) - 1ull));
     const int my_round = needs ? rank / kSlotLanes : 0;
-    // the first round's slots are formed before the barrier: they need only this lane's data
-    fill_slots<M>(a, n, nmod, sd, needs && my_round == 0, rank, ls, lane);
+    // the first round's ghost slots and slot pointers are set before the barrier: they need
+    // only this lane's data (its AT slots were gathered at the start)
+    fill_slots<M>(a, n, nmod, sd, needs && my_round == 0, rank, ls, lane, true);
     if (lane == 0) rounds[threadIdx.x >> 6] = (__popcll(nball) + kSlotLanes - 1) / kSlotLanes;
     __syncthreads();   // the wavefront's outputs and slots are in LDS; every wavefront's round count too
     int nrounds = 1;
@@ -585,7 +630,7 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
     for (int round = 0; round < nrounds; ++round) {
       if (round > 0) {
         __syncthreads();   // the previous round's slots have been read
-        fill_slots<M>(a, n, nmod, sd, needs && my_round == round, rank, ls, lane);
+        fill_slots<M>(a, n, nmod, sd, needs && my_round == round, rank, ls, lane, false);
         __syncthreads();   // the slots are read by other lanes of the wavefront below
       }
       bool flag = false;
