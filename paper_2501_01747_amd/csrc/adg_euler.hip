@@ -466,6 +466,9 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   while (x >= E) x -= E;
   int fidx = xu + 1;
   if (a.periodic && (fidx < 0 || fidx > E)) fidx = fidx < 0 ? fidx + E : fidx - E;
+  // the PE interface at this lane's face: loaded first, beside the step counter (the
+  // state's buffers and the delays depend on the step, the interface map does not)
+  const int iface = face_lane ? a.face_if[fidx] : -1;
   const long long n = *a.step;
   const int nmod = step_mod(n, a.ring.D);
   bool ok = true;
@@ -494,7 +497,6 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
 #pragma unroll
       for (int j = 0; j < M; ++j) u[v][j] = 0.0;
   }
-  const int iface = face_lane ? a.face_if[fidx] : -1;
   // a delayed PE-interface face gathers its past levels' fluxes now, while the state
   // loads are in flight
   const int kf = iface >= 0 ? eff_delay(a.dl, n, iface) : 0;
@@ -510,10 +512,12 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   bool needs = false;
   unsigned long long nball = 0;
   if constexpr (LIM) {
+    // an owned element's faces x and x + 1 are the faces of the previous lane and of this one
+    const int iface_prev = dpp_move<kDppFromPrev>(iface);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const bool ghost = own && !a.periodic && (side == 0 ? x == 0 : x == E - 1);
-      const int i = (own && !ghost) ? a.face_if[side == 0 ? x : x + 1] : -1;
+      const int i = (own && !ghost) ? (side == 0 ? iface_prev : iface) : -1;
       const int k = i >= 0 ? eff_delay(a.dl, n, i) : 0;
       sd[side].base = lane + (side == 0 ? -1 : 1);
       sd[side].sv = M * 64;
