@@ -569,12 +569,24 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     sF[v][ff] = F;
   }
   __syncthreads();
-  // species production W_i omega_i = W_i sum_r nu_ir (rate r), one lane per (node, species)
+  // species production W_i omega_i = W_i sum_r nu_ir (rate r), one lane per (node, species);
+  // four terms per round trip (the entries past a species' count hold coefficient 0,
+  // reaction 0, and add nothing)
+  static_assert(kNsMaxReactions % 4 == 0, "species lists are read in fours");
   for (int idx = t; idx < NS * NN; idx += NTH) {
     const int i = idx / NN, p = idx % NN;
     double wdot = 0.0;
     const int cnt = mk->spn[i];
-    for (int m = 0; m < cnt; ++m) wdot += (double)mk->spnu[i][m] * sRate[mk->spr[i][m]][p];
+    for (int m0 = 0; m0 < cnt; m0 += 4) {
+      double nu[4], rt[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        nu[d] = (double)mk->spnu[i][m0 + d];
+        rt[d] = sRate[mk->spr[i][m0 + d]][p];
+      }
+#pragma unroll
+      for (int d = 0; d < 4; ++d) wdot += nu[d] * rt[d];
+    }
     sS[i][p] = mk->W[i] * wdot;
   }
   __syncthreads();

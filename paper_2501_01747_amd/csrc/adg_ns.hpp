@@ -33,7 +33,8 @@ struct NsMech {
   int rf[kNsMaxReactions][2], rr[kNsMaxReactions][2];
   int gidx[kNsMaxReactions][4];
   double gnu[kNsMaxReactions][4];
-  // per species, the reactions with a nonzero net coefficient (increasing r) and that coefficient
+  // per species, the reactions with a nonzero net coefficient (increasing r) and that
+  // coefficient; the entries past the count hold reaction 0 with coefficient 0
   int spn[kNsMaxSpecies];
   unsigned char spr[kNsMaxSpecies][kNsMaxReactions];
   signed char spnu[kNsMaxSpecies][kNsMaxReactions];
