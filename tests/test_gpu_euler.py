@@ -341,3 +341,29 @@ def test_limiter_every_face_a_pe_interface(adg, orc, E, mode, bc):
         assert np.array_equal(fg, o.flags()) and tot == o.total_flags() and tot > 0, k
         r = rel_l2(s.state(), o.state())
         assert r < 1e-10, (k, r)
+
+
+@pytest.mark.parametrize("order_p,at_order,n_pe", [(4, 0, 8), (3, 6, 130), (4, 6, 130)])
+def test_limiter_at_combinations_of_more_than_four_levels(adg, orc, order_p, at_order, n_pe):
+    """AT combinations of five and six past levels (q = N_p + 1 = 5, and q = 6 set explicitly)
+    in the limited stage kernel: the delayed fluxes, the neighbour slots the wavefront gathers
+    at the start of the kernel and, with one element per PE, the slots of later rounds; states
+    and flags against the oracle.  Periodic mesh, a density jump (2 | 1) advected at u = 1,
+    p = 1 (at a shock, extrapolating five or six levels across delayed PE faces leaves the
+    physical states)."""
+    E = 130
+    case, _ = gen.case_c2(E=E, order_p=order_p, length=E / 32.0, n_pe=n_pe, mode="saa", at_order=at_order)
+    case["disc"]["bc"] = "periodic"
+    length, phys = E / 32.0, case["physics"]
+    w0 = gen.project(lambda x: gen.onestep_conserved(np.where(x < length / 2, 2.0, 1.0), 1.0 + 0 * x,
+                                                     1.0 + 0 * x, 1.0, phys), E, order_p, 0.0, length)
+    s = adg.Solver(case)
+    s.set_state(w0)
+    o = orc.OracleSolver(case, w0, 12)
+    for k in (5, 6):
+        s.step(k)
+        o.step(k)
+        fg, tot = s.flags()
+        assert np.array_equal(fg, o.flags()) and tot == o.total_flags() and tot > 0, k
+        r = rel_l2(s.state(), o.state())
+        assert r < 1e-10, (k, r)
