@@ -187,7 +187,8 @@ adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph);
    (256, 512 or 1024 threads) of the stage kernel: every candidate is warmed up,
    then timed over n_reps launches of the first RK stage on the current state in
    three interleaved rounds, its fastest round counting; later steps use the
-   fastest candidate.  The timed launches only rewrite the first stage buffer and the
+   fastest candidate, or the first one (8/512) unless the fastest beats it by
+   more than 3 %.  The timed launches only rewrite the first stage buffer and the
    current level's first-stage history, which the next step recomputes, so the
    solution is unchanged.  *choice (optional) receives the chosen candidate
    (0: 8/512, 1: 8/256, 2: 4/256, 3: 4/512, 4: 8/1024; always 0 for the one-step model,
