@@ -78,18 +78,22 @@ struct NsLds {
   static constexpr int NQ = TE + 2;   // gradients of elements e0-1 .. e0+TE; local lq <-> element e0 - 1 + lq
   static constexpr int NN = TE * Q;   // quadrature nodes of the tile; node p <-> element p / Q, node p % Q
   static constexpr int NR = kNsMaxReactions;
-  double sW[V * M][NH];
-  double sTm[V][NH], sTp[V][NH];
-  double sG[V][NN];
-  double sS[NS][NN];
+  // rows padded to an odd number of doubles: the lanes of a point group read or write one
+  // row each (their species) at the same column, and rows an even number of doubles apart
+  // would put several of them on the same LDS banks
+  static constexpr int NHP = NH | 1, NQP = NQ | 1, NNP = NN | 1;
+  double sW[V * M][NHP];
+  double sTm[V][NHP], sTp[V][NHP];
+  double sG[V][NNP];
+  double sS[NS][NNP];
   double sT[NN];
-  double sConc[NS][NN], sGRT[NS][NN];
+  double sConc[NS][NNP], sGRT[NS][NNP];
   // the reaction rates of the chemistry phase reuse the storage of the central traces and
   // LDG gradients, which are dead once the point phase has ended
   union {
     struct {
       double sWc[V][NF], sWa[V][NF];
-      double sQ[V * M][NQ];
+      double sQ[V * M][NQP];
     } early;
     double sRate[NR][NN];
   } u;
