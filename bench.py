@@ -415,7 +415,7 @@ def main():
     ap.add_argument("--serve-chunk", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
 

@@ -84,7 +84,7 @@ typedef struct {
                                 source W omega = -+ k_pre rho Y_R exp(-e_act/T), T = p/rho.
                              ADG_DETAILED: mixture of Ns thermally perfect species with the
                                 mechanism `mech`; viscous = 1 adds the Navier-Stokes terms. */
-  int32_t n_species;      /* Ns (2 for ADG_ONESTEP, 9 for ADG_DETAILED in this build) */
+  int32_t n_species;      /* Ns (2 for ADG_ONESTEP; the detailed-chemistry kernels take 9) */
   int32_t viscous;
   double gamma, q_heat, e_act, k_pre;
   const adg_mechanism *mech;
