@@ -394,9 +394,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="c1")
-    ap.add_argument("--graph", type=int, default=10, help="time steps per captured HIP graph (0 = plain launches)")
+    ap.add_argument("--graph", type=int, default=50, help="time steps per captured HIP graph (0 = plain launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured copy / FP64 ceilings")
     ap.add_argument("--sweep-euler", action="store_true",

@@ -107,7 +107,7 @@ def test_worst_case_schedule(adg, orc, mech):
 
 def test_c1_full_size(adg, orc, mech):
     """The C1 workload at full size (E = 2048, N_p = 3, 16 PEs, SAA set-1) in the launch
-    configuration the benchmark times (HIP graph of 10 steps)."""
+    configuration the benchmark times (steps replayed from a captured HIP graph)."""
     case, w0 = gen.case_c1()
     s = adg.Solver(case)
     s.set_graph(10)
