@@ -9,11 +9,14 @@
 //      this level goes to the history ring and the element-side w* becomes the
 //      AT combination of past levels (Eq. (7) applied to w*);
 //   3. LDG gradients q (modal) of the tile and one halo element per side;
-//   4. one lane per point (quadrature nodes of the tile, both traces of every
-//      tile face): temperature Newton, primitives, convective and diffusive
-//      fluxes, and at the nodes the mass-action chemistry (FP64 throughout);
-//   5. Rusanov total flux per face; at PE interfaces the synchronous flux goes
-//      to the ring and the AT combination replaces it;
+//   4. a group of lanes per point (quadrature nodes of the tile, both traces of
+//      every tile face): temperature Newton, primitives, convective and diffusive
+//      fluxes, and at the nodes the Gibbs energies and concentrations (FP64
+//      throughout);
+//   5. mass-action rates per (node, reaction) and, beside them, the Rusanov total
+//      flux per face (at PE interfaces the synchronous flux goes to the ring and
+//      the AT combination replaces it); then the species production per (node,
+//      species);
 //   6. volume and source projection, lift and SSP-RK3 combination; the output
 //      is stored once.
 #include "adg_device.hpp"
