@@ -26,6 +26,9 @@ struct adg_solver {
   int cur = 0;            // state buffer at the start of the next step (2N schemes alternate 0 and 1)
   int graph_cur = 0;      // state buffer the captured graph starts from
   int graph_cur_after = 0;
+  int par = 0;            // step counter parity of the next step (P.step[par] holds its count)
+  int graph_par = 0;      // parity the captured graph starts from
+  int graph_par_after = 0;
   int ns_cfg = 0;   // work decomposition of the detailed-chemistry stage kernel
   int graph_steps = 0;
   int graph_built_for = 0;
@@ -89,6 +92,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       a.stage = stage;
       a.rk = r;
       a.advance = last;
+      a.par = s->par;
       if (timer) timer(s, 0, true);
       HIP_TRY(s, launch_euler_stage(M, s->P.disc.flux, a, lim ? &s->P.la : nullptr, st));
       if (timer) timer(s, 0, false);
@@ -100,6 +104,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       a.stage = stage;
       a.rk = r;
       a.advance = last;
+      a.par = s->par;
       if (timer) timer(s, 0, true);
       HIP_TRY(s, launch_ns_stage(M, s->ns_cfg, a, st));
       if (timer) timer(s, 0, false);
@@ -107,6 +112,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
   }
   if (rk_stage(rk, 0).two_n) s->cur = (s->cur + S) % 2;
   else if (s->P.disc.limiter && s->P.phys.model == ADG_ONESTEP) s->cur = 1 - s->cur;
+  s->par ^= 1;   // the step's last launch wrote the next count into the other counter
   return ADG_OK;
 }
 
@@ -123,11 +129,14 @@ adg_status build_graph(adg_solver *s) {
   if (!s->cap_stream) HIP_TRY(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
   HIP_TRY(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
   adg_status rc = ADG_OK;
-  const int cur0 = s->cur;
+  const int cur0 = s->cur, par0 = s->par;
   for (int i = 0; i < s->graph_steps && rc == ADG_OK; ++i) rc = enqueue_step(s, s->cap_stream, nullptr);
   s->graph_cur = cur0;
   s->graph_cur_after = s->cur;
+  s->graph_par = par0;
+  s->graph_par_after = s->par;
   s->cur = cur0;   // nothing ran: capture only records
+  s->par = par0;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
   if (rc != ADG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -178,6 +187,7 @@ adg_status adg_set_state(adg_solver *s, const double *w, int64_t count, int32_t 
     return fail(s, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
   }
   s->cur = 0;
+  s->par = 0;
   HIP_TRY(s, reset_problem(s->P, s->stream));
   if (where == ADG_HOST) HIP_TRY(s, hipStreamSynchronize(s->stream));
   return ADG_OK;
@@ -190,13 +200,15 @@ adg_status adg_step(adg_solver *s, int32_t n_steps) {
       adg_status rc = build_graph(s);
       if (rc != ADG_OK) return rc;
     }
-    // the graph starts from the buffer it was captured with; a plain step realigns
-    // the alternating state buffer (2N schemes, limited Shu-Osher) when needed
+    // the graph starts from the state buffer and step counter parity it was captured
+    // with; a plain step realigns them (alternating state buffers of 2N schemes and
+    // limited Shu-Osher, an odd number of steps per graph) when needed
     int left = n_steps;
     while (left > 0) {
-      if (left >= s->graph_steps && s->cur == s->graph_cur) {
+      if (left >= s->graph_steps && s->cur == s->graph_cur && s->par == s->graph_par) {
         HIP_TRY(s, hipGraphLaunch(s->gexec, s->stream));
         s->cur = s->graph_cur_after;
+        s->par = s->graph_par_after;
         left -= s->graph_steps;
       } else {
         adg_status rc = enqueue_step(s, s->stream, nullptr);
@@ -253,7 +265,7 @@ int64_t adg_step_count(adg_solver *s) {
   if (!s) return -1;
   if (hipStreamSynchronize(s->stream) != hipSuccess) return -1;
   long long n = 0;
-  if (hipMemcpy(&n, s->P.step, sizeof n, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  if (hipMemcpy(&n, s->P.step + s->par, sizeof n, hipMemcpyDeviceToHost) != hipSuccess) return -1;
   return n;
 }
 
@@ -315,6 +327,7 @@ adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
   a.wout = s->P.W[bo];
   a.stage = 0;
   a.advance = 0;
+  a.par = s->par;
   // every candidate warmed up first, then timed in three interleaved rounds; each keeps
   // its fastest round (clock ramp-up and other transients then bias no candidate)
   double t[kNsConfigs];

@@ -66,9 +66,10 @@ struct adg_batch {
   std::vector<NsMech> mech_host = std::vector<NsMech>(kBatchMechs);
   std::vector<int> mech_ref = std::vector<int>(kBatchMechs, 0);
   int2 *d_tiles = nullptr;
-  long long *d_step = nullptr;
+  long long *d_step = nullptr;   // [slot][2]: each instance's step counters of the two parities
   int *d_err = nullptr;
-  unsigned *d_done = nullptr;
+  int par = 0;                   // step counter parity of the next batch step
+  int graph_par = 0;             // parity the captured graph starts from
   size_t heap_off = 0;
   std::map<size_t, size_t> free_list;  // offset -> bytes
   std::vector<Slot> slots;
@@ -91,7 +92,7 @@ struct adg_batch {
 namespace {
 
 struct Header {
-  size_t ns, eu, mech, tiles, step, err, done, total;
+  size_t ns, eu, mech, tiles, step, err, total;
 };
 
 Header header_layout(int max_inst, long long max_tiles) {
@@ -101,9 +102,8 @@ Header header_layout(int max_inst, long long max_tiles) {
   h.eu = off;    off += align256(sizeof(EulerSet) * (size_t)max_inst);
   h.mech = off;  off += align256(sizeof(NsMech) * (size_t)kBatchMechs);
   h.tiles = off; off += align256(sizeof(int2) * (size_t)max_tiles);
-  h.step = off;  off += align256(sizeof(long long) * (size_t)max_inst);
+  h.step = off;  off += align256(2 * sizeof(long long) * (size_t)max_inst);
   h.err = off;   off += align256(sizeof(int) * (size_t)max_inst);
-  h.done = off;  off += align256(sizeof(unsigned) * (size_t)max_inst);
   h.total = off;
   return h;
 }
@@ -200,10 +200,10 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
         BHIP(b, hipEventRecord(e0, st));
       }
       if (g.kind == 0) {
-        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->precision == ADG_MIXED_FP32, g.M,
-                                b->tile_elems, st));
+        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->par, b->precision == ADG_MIXED_FP32,
+                                g.M, b->tile_elems, st));
       } else {
-        BHIP(b, launch_euler_batch(g.M, g.flux, g.lim, b->d_eu, b->d_tiles + g.off, g.n, stage, st));
+        BHIP(b, launch_euler_batch(g.M, g.flux, g.lim, b->d_eu, b->d_tiles + g.off, g.n, stage, b->par, st));
       }
       if (timed) {
         BHIP(b, hipEventCreate(&e1));
@@ -214,6 +214,7 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
       }
     }
   }
+  b->par ^= 1;   // the step's last launches wrote the next counts into the other counters
   return ADG_OK;
 }
 
@@ -242,7 +243,10 @@ adg_status build_batch_graph(adg_batch *b) {
   if (!b->cap_stream) BHIP(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   adg_status rc = ADG_OK;
+  const int par0 = b->par;
   for (int i = 0; i < b->graph_steps && rc == ADG_OK; ++i) rc = enqueue_batch_step(b, b->cap_stream, false);
+  b->graph_par = par0;
+  b->par = par0;   // nothing ran: capture only records
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
   if (rc != ADG_OK) {
@@ -298,7 +302,6 @@ adg_status adg_batch_create(int32_t max_instances, int64_t max_elements, int32_t
   b->d_tiles = (int2 *)(b->ws + h.tiles);
   b->d_step = (long long *)(b->ws + h.step);
   b->d_err = (int *)(b->ws + h.err);
-  b->d_done = (unsigned *)(b->ws + h.done);
   b->heap_off = h.total;
   const size_t heap = (workspace_bytes - h.total) & ~(size_t)255;
   if (heap) b->free_list[h.total] = heap;
@@ -339,9 +342,8 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   s.target = n_steps > 0 ? n_steps : kNoTarget;
   // counters of the slot live in the header so that one copy reads them all
   Problem &P = s.P;
-  P.step = b->d_step + slot;
+  P.step = b->d_step + 2 * (size_t)slot;
   P.err = b->d_err + slot;
-  P.done = b->d_done + slot;
   auto fail_release = [&](hipError_t e, const char *what) {
     heap_give(b, off, need);
     return bfail(b, ADG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -371,7 +373,6 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
     na.mech = b->d_mech + ms;
     na.step = P.step;
     na.err = P.err;
-    na.done = P.done;
     na.target = s.target;
     he = hipMemcpy(b->d_ns + slot, &na, sizeof na, hipMemcpyHostToDevice);
     if (he != hipSuccess) return fail_release(he, "descriptor upload");
@@ -389,7 +390,6 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
       a.advance = st == 2;
       a.step = P.step;
       a.err = P.err;
-      a.done = P.done;
       a.target = s.target;
       es.st[st] = a;
     }
@@ -401,9 +401,8 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   if (where == ADG_HOST) he = upload_state_host(P, w0, b->stream);
   else he = launch_to_planes(w0, P.W[0], L.E, VM, b->stream);
   if (he == hipSuccess) he = reset_problem(P, b->stream);
-  if (he == hipSuccess) he = hipMemsetAsync(P.step, 0, sizeof(long long), b->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(P.step, 0, 2 * sizeof(long long), b->stream);
   if (he == hipSuccess) he = hipMemsetAsync(P.err, 0, sizeof(int), b->stream);
-  if (he == hipSuccess) he = hipMemsetAsync(P.done, 0, sizeof(unsigned), b->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(b->stream);
   if (he != hipSuccess) return fail_release(he, "initial state");
   b->slots[slot] = s;
@@ -439,7 +438,19 @@ adg_status adg_batch_step(adg_batch *b, int32_t n_steps) {
       rc = build_batch_graph(b);
       if (rc != ADG_OK) return rc;
     }
-    for (; done + b->graph_steps <= n_steps; done += b->graph_steps) BHIP(b, hipGraphLaunch(b->gexec, b->stream));
+    // the graph starts from the step counter parity it was captured with; with an odd
+    // number of steps per graph a plain step realigns the parity when needed
+    while (done + b->graph_steps <= n_steps) {
+      if (b->par == b->graph_par) {
+        BHIP(b, hipGraphLaunch(b->gexec, b->stream));
+        b->par ^= b->graph_steps & 1;
+        done += b->graph_steps;
+      } else {
+        rc = enqueue_batch_step(b, b->stream, false);
+        if (rc != ADG_OK) return rc;
+        done += 1;
+      }
+    }
   }
   for (; done < n_steps; ++done) {
     rc = enqueue_batch_step(b, b->stream, false);
@@ -451,13 +462,13 @@ adg_status adg_batch_step(adg_batch *b, int32_t n_steps) {
 adg_status adg_batch_poll(adg_batch *b, int64_t *steps, int32_t *state_err) {
   if (!b) return ADG_ERR_ARG;
   BHIP(b, hipStreamSynchronize(b->stream));
-  std::vector<long long> st(b->max_inst);
+  std::vector<long long> st(2 * (size_t)b->max_inst);
   std::vector<int> er(b->max_inst);
-  BHIP(b, hipMemcpy(st.data(), b->d_step, sizeof(long long) * b->max_inst, hipMemcpyDeviceToHost));
+  BHIP(b, hipMemcpy(st.data(), b->d_step, 2 * sizeof(long long) * b->max_inst, hipMemcpyDeviceToHost));
   BHIP(b, hipMemcpy(er.data(), b->d_err, sizeof(int) * b->max_inst, hipMemcpyDeviceToHost));
   for (int i = 0; i < b->max_inst; ++i) {
     const bool u = b->slots[i].used;
-    if (steps) steps[i] = u ? st[i] : -1;
+    if (steps) steps[i] = u ? st[2 * (size_t)i + b->par] : -1;
     if (state_err) state_err[i] = u ? (er[i] != 0) : 0;
   }
   return ADG_OK;
@@ -474,7 +485,7 @@ adg_status adg_batch_get_state(adg_batch *b, int32_t slot, double *w, int64_t co
   if (P.ea.alt) {
     long long n = 0;
     BHIP(b, hipStreamSynchronize(b->stream));
-    BHIP(b, hipMemcpy(&n, P.step, sizeof n, hipMemcpyDeviceToHost));
+    BHIP(b, hipMemcpy(&n, P.step + b->par, sizeof n, hipMemcpyDeviceToHost));
     src = P.W[n & 1];
   }
   if (where == ADG_HOST) {
@@ -547,11 +558,11 @@ adg_status adg_batch_autotune(adg_batch *b, int32_t n_reps, int32_t *choice) {
     hipEvent_t e0, e1;
     BHIP(b, hipEventCreate(&e0));
     BHIP(b, hipEventCreate(&e1));
-    BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->precision == ADG_MIXED_FP32, g->M,
+    BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->par, b->precision == ADG_MIXED_FP32, g->M,
                             b->tile_elems, b->stream));   // warm-up
     BHIP(b, hipEventRecord(e0, b->stream));
     for (int r = 0; r < n_reps; ++r)
-      BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->precision == ADG_MIXED_FP32, g->M,
+      BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->par, b->precision == ADG_MIXED_FP32, g->M,
                               b->tile_elems, b->stream));
     BHIP(b, hipEventRecord(e1, b->stream));
     BHIP(b, hipEventSynchronize(e1));

@@ -78,22 +78,12 @@ __device__ __forceinline__ double at_weight(int q, int k, int j) {
   return (double)num / (double)den;
 }
 
-// End of a time step, called by every one of the `nblocks` workgroups that work
-// on one problem in the step's last kernel, after its work: the last one to
-// finish advances the problem's step counter.  Every workgroup has read the
-// counter at its start, before it signs in here.  No memory fence: nothing in
-// this kernel reads what the others wrote (the stage's outputs are read by
-// later launches, after the kernel boundary), and a device-scope release here
-// would write back the whole L2 of the workgroup's XCD once per workgroup.
-__device__ __forceinline__ void finish_step(long long *step, unsigned *done, unsigned nblocks) {
-  __syncthreads();   // every wavefront of this workgroup has read the step counter
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(done, 1u);
-    if (prev == nblocks - 1) {
-      atomicAdd((unsigned long long *)step, 1ull);
-      atomicExch(done, 0u);
-    }
-  }
+// End of time step n in the step's last launch (parity par): the next step's
+// count goes to the other parity's counter.  Every launch of step n reads
+// step[par] only, so one workgroup's plain store needs no atomic, no barrier and
+// no wait; the next step's launches read it after this launch has ended.
+__device__ __forceinline__ void advance_step(long long *step, int par, long long n, bool first_workgroup) {
+  if (first_workgroup && threadIdx.x == 0) step[par ^ 1] = n + 1;
 }
 
 // ---------------------------------------------------------------- one-step model

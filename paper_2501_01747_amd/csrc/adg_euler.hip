@@ -443,7 +443,7 @@ __device__ __forceinline__ void gather_first_slots(const EulerArgs &a, int nmod,
 // element runs the indicator and, if troubled, the WENO reconstruction from them.
 template <int M, int FLUX, bool LIM>
 __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const LimiterArgs &l, double *lds, int *rounds,
-                                                 int blk, int nblk) {
+                                                 int blk, int par) {
   constexpr int V = 5, Q = M;
   constexpr int H = LIM ? 2 : 1;
   constexpr int WE = 64 - 2 * H;
@@ -469,7 +469,7 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
   // the PE interface at this lane's face: loaded first, beside the step counter (the
   // state's buffers and the delays depend on the step, the interface map does not)
   const int iface = face_lane ? a.face_if[fidx] : -1;
-  const long long n = *a.step;
+  const long long n = a.step[par];
   const int nmod = step_mod(n, a.ring.D);
   bool ok = true;
   const double *w0 = a.w0, *ws = a.ws;
@@ -683,36 +683,43 @@ __device__ __forceinline__ void euler_stage_body(const EulerArgs &a, const Limit
     }
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
-  if (a.advance) finish_step(a.step, a.done, nblk);
+  if (a.advance) advance_step(a.step, par, n, blk == 0);
 }
 
 template <int M, int FLUX>
 __global__ __launch_bounds__(kEulerBlock) void euler_stage_kernel(EulerArgs a) {
-  euler_stage_body<M, FLUX, false>(a, LimiterArgs{}, nullptr, nullptr, blockIdx.x, gridDim.x);
+  euler_stage_body<M, FLUX, false>(a, LimiterArgs{}, nullptr, nullptr, blockIdx.x, a.par);
 }
 
 template <int M, int FLUX>
 __global__ __launch_bounds__(kEulerBlock, M <= 4 ? 3 : 2) void euler_lim_kernel(EulerArgs a, LimiterArgs l) {
   __shared__ double lds[(kEulerBlock / 64) * lds_wave_doubles<M>()];
   __shared__ int rounds[kEulerBlock / 64];
-  euler_stage_body<M, FLUX, true>(a, l, lds, rounds, blockIdx.x, gridDim.x);
+  euler_stage_body<M, FLUX, true>(a, l, lds, rounds, blockIdx.x, a.par);
 }
 
 // Batched stage kernel: one workgroup per (instance, block) entry of the work
-// list, for instances of one order, flux and limiter choice; an instance whose
-// step count has reached its target is skipped by all of its workgroups alike.
+// list, for instances of one order, flux and limiter choice, all at step counter
+// parity par; an instance whose step count has reached its target is skipped by
+// all of its workgroups alike (its first one carries the count over to the
+// other parity at the step's last stage).
 template <int M, int FLUX, bool LIM>
 __global__ __launch_bounds__(kEulerBlock, M <= 4 ? 3 : 2) void euler_batch_kernel(const EulerSet *__restrict__ sets,
-                                                                  const int2 *__restrict__ tiles, int stage) {
+                                                                  const int2 *__restrict__ tiles, int stage,
+                                                                  int par) {
   const int2 tl = tiles[blockIdx.x];
   const EulerArgs &a = sets[tl.x].st[stage];
-  if (*a.step >= a.target) return;
+  const long long n = a.step[par];
+  if (n >= a.target) {
+    if (a.advance && tl.y == 0 && threadIdx.x == 0) a.step[par ^ 1] = n;
+    return;
+  }
   if constexpr (LIM) {
     __shared__ double lds[(kEulerBlock / 64) * lds_wave_doubles<M>()];
     __shared__ int rounds[kEulerBlock / 64];
-    euler_stage_body<M, FLUX, true>(a, sets[tl.x].lim, lds, rounds, tl.y, euler_blocks(a.E, true));
+    euler_stage_body<M, FLUX, true>(a, sets[tl.x].lim, lds, rounds, tl.y, par);
   } else {
-    euler_stage_body<M, FLUX, false>(a, sets[tl.x].lim, nullptr, nullptr, tl.y, euler_blocks(a.E, false));
+    euler_stage_body<M, FLUX, false>(a, sets[tl.x].lim, nullptr, nullptr, tl.y, par);
   }
 }
 
@@ -756,29 +763,30 @@ hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, const Limiter
 }
 
 template <int M, bool LIM>
-static hipError_t batch_ML(int flux, const EulerSet *sets, const int2 *tiles, int ntiles, int stage, hipStream_t s) {
+static hipError_t batch_ML(int flux, const EulerSet *sets, const int2 *tiles, int ntiles, int stage, int par,
+                           hipStream_t s) {
   if (flux == 1)
-    hipLaunchKernelGGL((euler_batch_kernel<M, 1, LIM>), dim3(ntiles), dim3(kEulerBlock), 0, s, sets, tiles, stage);
+    hipLaunchKernelGGL((euler_batch_kernel<M, 1, LIM>), dim3(ntiles), dim3(kEulerBlock), 0, s, sets, tiles, stage, par);
   else
-    hipLaunchKernelGGL((euler_batch_kernel<M, 0, LIM>), dim3(ntiles), dim3(kEulerBlock), 0, s, sets, tiles, stage);
+    hipLaunchKernelGGL((euler_batch_kernel<M, 0, LIM>), dim3(ntiles), dim3(kEulerBlock), 0, s, sets, tiles, stage, par);
   return hipGetLastError();
 }
 
 template <int M>
 static hipError_t batch_M(int flux, bool lim, const EulerSet *sets, const int2 *tiles, int ntiles, int stage,
-                          hipStream_t s) {
-  return lim ? batch_ML<M, true>(flux, sets, tiles, ntiles, stage, s)
-             : batch_ML<M, false>(flux, sets, tiles, ntiles, stage, s);
+                          int par, hipStream_t s) {
+  return lim ? batch_ML<M, true>(flux, sets, tiles, ntiles, stage, par, s)
+             : batch_ML<M, false>(flux, sets, tiles, ntiles, stage, par, s);
 }
 
 hipError_t launch_euler_batch(int M, int flux, bool lim, const EulerSet *sets, const int2 *tiles, int ntiles,
-                              int stage, hipStream_t s) {
+                              int stage, int par, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   switch (M) {
-    case 2: return batch_M<2>(flux, lim, sets, tiles, ntiles, stage, s);
-    case 3: return batch_M<3>(flux, lim, sets, tiles, ntiles, stage, s);
-    case 4: return batch_M<4>(flux, lim, sets, tiles, ntiles, stage, s);
-    case 5: return batch_M<5>(flux, lim, sets, tiles, ntiles, stage, s);
+    case 2: return batch_M<2>(flux, lim, sets, tiles, ntiles, stage, par, s);
+    case 3: return batch_M<3>(flux, lim, sets, tiles, ntiles, stage, par, s);
+    case 4: return batch_M<4>(flux, lim, sets, tiles, ntiles, stage, par, s);
+    case 5: return batch_M<5>(flux, lim, sets, tiles, ntiles, stage, par, s);
   }
   return hipErrorInvalidValue;
 }

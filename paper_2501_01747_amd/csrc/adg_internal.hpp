@@ -112,11 +112,14 @@ struct EulerArgs {
   const double *ws;     // stage input w^(s)
   double *wout;         // stage output (unlimited)
   const int *face_if;   // [E+1] interface index of face f, or -1
+  // step counters of the two parities: a launch of parity par works on step
+  // step[par], and the step's last launch writes step[par ^ 1] = step[par] + 1
+  // (plain stores by one workgroup: no launch of the step reads that counter)
   long long *step;
-  unsigned *done;       // workgroups finished in the step's last kernel
+  int par;              // parity of a single-problem launch (batched launches take theirs from the launch)
   int advance;          // this launch ends the time step
   int *err;
-  long long target;     // batched launches skip the instance once *step reaches it
+  long long target;     // batched launches skip the instance once its step reaches it
   int E;
   int periodic;
   int stage;
@@ -179,9 +182,10 @@ struct EulerSet {
 // the same kernel.
 hipError_t launch_euler_stage(int M, int flux, const EulerArgs &a, const LimiterArgs *lim, hipStream_t s);
 // Batched one-step stage over a work list of (instance, block) entries, all of
-// order M, flux `flux` (Rusanov/HLLC) and limiter choice `lim`.
+// order M, flux `flux` (Rusanov/HLLC) and limiter choice `lim`, at step counter
+// parity `par`.
 hipError_t launch_euler_batch(int M, int flux, bool lim, const EulerSet *sets, const int2 *tiles, int ntiles,
-                              int stage, hipStream_t s);
+                              int stage, int par, hipStream_t s);
 // Workgroups of the one-step stage kernel for E elements: a wavefront owns 62
 // elements, 60 with the limiter (two halo lanes on each side).
 __host__ __device__ inline int euler_blocks(int E, bool lim) {

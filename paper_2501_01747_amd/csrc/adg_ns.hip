@@ -130,7 +130,7 @@ struct NsLds {
 template <int M, int NS, typename OpT, int NTH, int TE, int LPP = 0>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
                                         double *wout, int stage, int advance, const RkStage rk, double *kbuf,
-                                        int e0, int ntiles,
+                                        int e0, int par,
                                         NsLds<M, NS, TE> &Ls, NsMech &smech) {
   constexpr int V = 3 + NS, Q = M;
   using Lds = NsLds<M, NS, TE>;
@@ -167,7 +167,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const int t = threadIdx.x;
   const int E = a.E;
   const int nloc = min(TE, E - e0);
-  const long long n = *a.step;
+  const long long n = a.step[par];
   const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
   const NsMech *__restrict__ mk = &smech;
   const int q_at = a.dl.q;
@@ -640,7 +640,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     wout[gi] = o;
   }
   if (!ok) atomicOr(a.err, (int)kErrState);
-  if (advance) finish_step(a.step, a.done, ntiles);
+  if (advance) advance_step(a.step, par, n, e0 == 0);
 }
 
 template <int M, int NS, int TE, int NTH>
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(NTH) void ns_stage_kernel(NsArgs a) {
   __shared__ NsLds<M, NS, TE> L;
   __shared__ NsMech smech;
   ns_tile<M, NS, double, NTH, TE>(a, a.ws, a.w0, a.wout, a.stage, a.advance, a.rk, a.kbuf,
-                                  xcd_item(blockIdx.x, gridDim.x) * TE, gridDim.x, L, smech);
+                                  xcd_item(blockIdx.x, gridDim.x) * TE, a.par, L, smech);
 }
 
 // LDS of the batched kernel: room for the largest order it serves.
@@ -679,33 +679,39 @@ union NsBatchLds<5, TE> {
 
 // Batched stage kernel: one workgroup per (instance, tile) entry of the work
 // list; instances differ in size, order (up to MMAX modes), PE layout and
-// delays.  Sizing the LDS for the largest order present keeps more workgroups
-// resident when the batch holds only low orders.
+// delays, and all are at step counter parity par.  Sizing the LDS for the
+// largest order present keeps more workgroups resident when the batch holds
+// only low orders.  An instance whose step count has reached its target is
+// skipped by all of its workgroups (its first tile carries the count over to
+// the other parity at the last stage).
 template <typename OpT, int MMAX, int TE>
 __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *__restrict__ insts,
-                                                            const int2 *__restrict__ tiles, int stage) {
+                                                            const int2 *__restrict__ tiles, int stage, int par) {
   __shared__ NsBatchLds<MMAX, TE> L;
   __shared__ NsMech smech;
   const int2 tl = tiles[blockIdx.x];
   const NsArgs &a = insts[tl.x];
-  if (*a.step >= a.target) return;
+  const long long n = a.step[par];
+  if (n >= a.target) {
+    if (stage == 2 && tl.y == 0 && threadIdx.x == 0) a.step[par ^ 1] = n;
+    return;
+  }
   const int in_buf = stage, out_buf = stage == 2 ? 0 : stage + 1;
   const double *ws = a.W[in_buf];
   const double *w0 = a.W[0];
   double *wout = a.W[out_buf];
-  const int ntiles = (a.E + TE - 1) / TE;
   const int M = a.M;
   const RkStage rk = rk_stage(ADG_SSPRK3, stage);   // batches run SSP-RK3
   if (M == 2) {
-    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m2, smech);
+    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m2, smech);
   } else if constexpr (MMAX >= 3) {
     if (M == 3) {
-      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m3, smech);
+      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m3, smech);
     } else if constexpr (MMAX >= 4) {
       if (M == 4) {
-        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m4, smech);
+        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m4, smech);
       } else if constexpr (MMAX >= 5) {
-        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, ntiles, L.m5, smech);
+        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m5, smech);
       }
     }
   }
@@ -719,7 +725,7 @@ bool ns_supported(int n_species, int n_reactions) {
 
 adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *d, int E, int M, bool periodic,
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
-                    long long *step, unsigned *done, int *err, NsMech *dev_mech) {
+                    long long *step, int *err, NsMech *dev_mech) {
   if (!periodic) return ADG_ERR_UNSUPPORTED;
   NsMech hm;
   const adg_status rc = ns_build_mech(ph, hm);
@@ -727,7 +733,6 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
   if (hipMemcpy(dev_mech, &hm, sizeof hm, hipMemcpyHostToDevice) != hipSuccess) return ADG_ERR_HIP;
   a.face_if = face_if;
   a.step = step;
-  a.done = done;
   a.err = err;
   a.mech = dev_mech;
   a.E = E;
@@ -828,25 +833,26 @@ static hipError_t ns_M(int cfg, const NsArgs &a, hipStream_t s) {
 }
 
 template <typename OpT, int TE>
-static void batch_launch(int max_m, const NsArgs *insts, const int2 *tiles, int ntiles, int stage, hipStream_t s) {
+static void batch_launch(int max_m, const NsArgs *insts, const int2 *tiles, int ntiles, int stage, int par,
+                         hipStream_t s) {
   switch (max_m) {
-    case 2: hipLaunchKernelGGL((ns_batch_kernel<OpT, 2, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
-    case 3: hipLaunchKernelGGL((ns_batch_kernel<OpT, 3, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
-    case 4: hipLaunchKernelGGL((ns_batch_kernel<OpT, 4, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
-    default: hipLaunchKernelGGL((ns_batch_kernel<OpT, 5, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage); break;
+    case 2: hipLaunchKernelGGL((ns_batch_kernel<OpT, 2, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage, par); break;
+    case 3: hipLaunchKernelGGL((ns_batch_kernel<OpT, 3, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage, par); break;
+    case 4: hipLaunchKernelGGL((ns_batch_kernel<OpT, 4, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage, par); break;
+    default: hipLaunchKernelGGL((ns_batch_kernel<OpT, 5, TE>), dim3(ntiles), dim3(kThreadsBatch), 0, s, insts, tiles, stage, par); break;
   }
 }
 
-hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, int max_m,
-                           int tile_elems, hipStream_t s) {
+hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, int par, bool mixed,
+                           int max_m, int tile_elems, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (max_m < 2 || max_m > kMaxM || (tile_elems != 4 && tile_elems != 8)) return hipErrorInvalidValue;
   if (tile_elems == 8) {
-    if (mixed) batch_launch<float, 8>(max_m, insts, tiles, ntiles, stage, s);
-    else batch_launch<double, 8>(max_m, insts, tiles, ntiles, stage, s);
+    if (mixed) batch_launch<float, 8>(max_m, insts, tiles, ntiles, stage, par, s);
+    else batch_launch<double, 8>(max_m, insts, tiles, ntiles, stage, par, s);
   } else {
-    if (mixed) batch_launch<float, 4>(max_m, insts, tiles, ntiles, stage, s);
-    else batch_launch<double, 4>(max_m, insts, tiles, ntiles, stage, s);
+    if (mixed) batch_launch<float, 4>(max_m, insts, tiles, ntiles, stage, par, s);
+    else batch_launch<double, 4>(max_m, insts, tiles, ntiles, stage, par, s);
   }
   return hipGetLastError();
 }

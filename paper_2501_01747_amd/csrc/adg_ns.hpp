@@ -48,11 +48,11 @@ struct NsArgs {
   double *W[3];         // the three state buffers (batched kernel picks them by stage)
   int M;                // N_p + 1
   const int *face_if;
-  long long *step;
-  unsigned *done;       // workgroups finished in the step's last kernel
+  long long *step;      // step counters of the two parities (as in EulerArgs)
+  int par;              // parity of a single-problem launch
   int advance;          // this launch ends the time step
   int *err;
-  long long target;     // batched launches skip the instance once *step reaches it
+  long long target;     // batched launches skip the instance once its step reaches it
   const NsMech *mech;
   int E;
   int stage;
@@ -69,17 +69,18 @@ struct NsArgs {
 bool ns_supported(int n_species, int n_reactions);
 adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *d, int E, int M, bool periodic,
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
-                    long long *step, unsigned *done, int *err, NsMech *dev_mech);
+                    long long *step, int *err, NsMech *dev_mech);
 // The device form of a mechanism (host side; validates it).
 adg_status ns_build_mech(const adg_physics *ph, NsMech &hm);
 // Work decompositions of the single-problem stage kernel: (tile elements, threads)
 // = (8, 512), (8, 256), (4, 256), (4, 512), (8, 1024).
 constexpr int kNsConfigs = 5;
 hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, hipStream_t s);
-// One stage for every (instance, tile) entry of `tiles` (device); mixed = FP32 modal operators;
-// max_m = the largest N_p + 1 among the listed instances; tiles of tile_elems (4 or 8) elements.
-hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, bool mixed, int max_m,
-                           int tile_elems, hipStream_t s);
+// One stage for every (instance, tile) entry of `tiles` (device), at step counter parity par;
+// mixed = FP32 modal operators; max_m = the largest N_p + 1 among the listed instances; tiles
+// of tile_elems (4 or 8) elements.
+hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, int stage, int par, bool mixed,
+                           int max_m, int tile_elems, hipStream_t s);
 constexpr int kNsMinTile = 4;
 
 }  // namespace adg

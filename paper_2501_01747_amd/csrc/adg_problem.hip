@@ -221,7 +221,6 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
   P.step = (long long *)(base + L.counters);
   P.err = (int *)(base + L.counters + 64);
   P.flag_count = (unsigned long long *)(base + L.counters + 128);
-  P.done = (unsigned *)(base + L.counters + 192);
   P.ring = (double *)(base + L.ring);
 
   const bool periodic = disc->bc == ADG_PERIODIC;
@@ -267,7 +266,6 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
     EulerArgs &a = P.ea;
     a.face_if = P.face_if;
     a.step = P.step;
-    a.done = P.done;
     a.err = P.err;
     a.target = kNoTarget;
     a.E = L.E;
@@ -296,7 +294,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
       build_limiter_tables(L.M, l);
     }
   } else {
-    adg_status rc = ns_setup(P.na, phys, disc, L.E, L.M, periodic, dx, dl, rp, tb, P.face_if, P.step, P.done, P.err,
+    adg_status rc = ns_setup(P.na, phys, disc, L.E, L.M, periodic, dx, dl, rp, tb, P.face_if, P.step, P.err,
                              (NsMech *)(base + L.mech));
     if (rc != ADG_OK) return rc;
     for (int b = 0; b < 3; ++b) P.na.W[b] = P.W[b];

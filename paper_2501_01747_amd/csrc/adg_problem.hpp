@@ -33,8 +33,7 @@ struct Problem {
   double *W[4] = {nullptr, nullptr, nullptr, nullptr};
   int8_t *flags = nullptr;
   int *face_if = nullptr;
-  long long *step = nullptr;
-  unsigned *done = nullptr;
+  long long *step = nullptr;   // [2]: the step counters of the two parities
   int *err = nullptr;
   unsigned long long *flag_count = nullptr;
   double *ring = nullptr;
