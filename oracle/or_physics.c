@@ -13,14 +13,20 @@
  *              reversible mass-action kinetics (equilibrium constants from the
  *              Gibbs energies), power-law viscosity, Pr and Le = 1 transport.
  *
- * Pins (tests/test_oracle_physics.py, tests/test_oracle_chemistry.py):
+ * Pins (tests/test_oracle_solver.py, tests/test_oracle_limiter.py,
+ * tests/test_oracle_chemistry.py, tests/test_oracle_transport.py):
  *   fluxes     f_hat(w, w) = f(w); HLLC keeps a stationary contact; L A R = Lambda
  *              with A from finite differences of the flux
  *   thermo     dh/dT = cp and ds/dT = cp/T (finite differences); T(e(T)) = T
  *   kinetics   mass and element conservation of the production rates; zero net
  *              rate at an equilibrium composition; van 't Hoff relation for K_c;
  *              Arrhenius parameters recovered from rates at several T
- *   transport  decay rate of a small diffusive mode against the linear theory
+ *   transport  linear theory of small modes on a periodic domain: an isobaric
+ *              temperature mode decays at chi k^2 (heat conduction); a sound wave
+ *              at k^2/2 (4 nu/3 + (gamma-1) chi) (the 4/3 of the stress); a
+ *              composition mode of two thermodynamically identical species at
+ *              D k^2 (J_i = -rho D dY_i/dx); with different formation enthalpies
+ *              the same mode stays isothermal (the enthalpy flux sum h_i J_i)
  */
 #include <math.h>
 #include <string.h>

@@ -34,7 +34,11 @@
  * delays; first order with the plain delayed flux; error growth with the number
  * of PEs; conservation of mass, momentum, energy and elements on periodic
  * domains under any delay pattern; sum_i rho Y_i = rho; Rankine-Hugoniot shock
- * speed; 0-D reactor against an ODE integration.
+ * speed; 0-D reactor against an ODE integration.  The troubled-cell indicator
+ * (or_indicator; tests/test_oracle_limiter.py): KXRCF on constructed cells whose
+ * indicator value is 0.9 or 1.1 at the inflow face, for both flow directions and
+ * N_p = 1..3, with a larger jump at the outflow face (pins the threshold, the
+ * exponent (N_p+1)/2 of h, the inflow face and the normaliser max_q |w(xi_q)|).
  */
 #include <math.h>
 #include <stdio.h>
@@ -615,6 +619,33 @@ int or_rhs_sync(const or_config *cfg, const double *w, double *rhs) {
   int rc = compute_rhs(s, 0, s->w, rhs);
   or_destroy(s);
   return rc;
+}
+
+/* Troubled-cell indicator of Sec. 3.3 for one cell with modal data we and
+   neighbours nbL, nbR ([V][M] each; a ghost neighbour is ignored by KXRCF and
+   taken as the cell's own mean by the minmod test, as in the limiter). */
+int or_indicator(const or_config *cfg, const double *nbL, const double *we, const double *nbR, int ghostL,
+                 int ghostR) {
+  or_config c = *cfg;
+  c.mode = OR_SYNC;
+  size_t nst = (size_t)cfg->n_elem * (3 + cfg->n_species) * (cfg->order_p + 1);
+  double *w0 = calloc(nst, sizeof(double));
+  or_solver *s;
+  int rc = or_create(&c, w0, 1, &s);
+  free(w0);
+  if (rc) return -1;
+  int V = s->V, M = s->M;
+  double gL[OR_MAXV * OR_MAXM], gR[OR_MAXV * OR_MAXM];
+  memcpy(gL, nbL, sizeof(double) * V * M);
+  memcpy(gR, nbR, sizeof(double) * V * M);
+  if (ghostL) { memset(gL, 0, sizeof gL); for (int v = 0; v < V; ++v) gL[v * M] = we[v * M]; }
+  if (ghostR) { memset(gR, 0, sizeof gR); for (int v = 0; v < V; ++v) gR[v * M] = we[v * M]; }
+  double trL[OR_MAXV], trR[OR_MAXV];
+  trace_of(s, gL, 1, trL);
+  trace_of(s, gR, 0, trR);
+  int fl = s->cfg.indicator == OR_MINMOD ? minmod_flag(s, we, gL, gR) : kxrcf_flag(s, we, trL, trR, ghostL, ghostR);
+  or_destroy(s);
+  return fl;
 }
 
 /* LDG gradient q of Sec. 3.1 with synchronous central traces. */

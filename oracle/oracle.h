@@ -105,5 +105,8 @@ void or_beta_matrix(int np, double *B);
 void or_translation(int np, int side, double *T);
 int or_rhs_sync(const or_config *cfg, const double *w, double *rhs);
 int or_gradient_sync(const or_config *cfg, const double *w, double *q);
+/* Troubled-cell flag (0/1) of the cell we between nbL and nbR ([V][M] each). */
+int or_indicator(const or_config *cfg, const double *nbL, const double *we, const double *nbR, int ghostL,
+                 int ghostR);
 
 #endif

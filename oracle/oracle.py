@@ -108,6 +108,7 @@ def lib() -> C.CDLL:
             "or_translation": (None, [C.c_int, C.c_int, P(d)]),
             "or_rhs_sync": (C.c_int, [cfgp, P(d), P(d)]),
             "or_gradient_sync": (C.c_int, [cfgp, P(d), P(d)]),
+            "or_indicator": (C.c_int, [cfgp, P(d), P(d), P(d), C.c_int, C.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

@@ -173,3 +173,80 @@ def test_minmod_flags_a_jump_and_smooth_extrema_only_when_tvd(orc):
     case, w0 = minmod_case(64, wave, bc="periodic", tvb_m=1e4)
     _, flags, total = run_limiter_once(orc, case, w0)
     assert total == 0
+
+
+def _kxrcf_cfg(orc, order_p, E=64):
+    case, _ = gen.case_c0(E=E, order_p=order_p, n_pe=1, mode="sync")
+    case["disc"]["limiter"] = 1
+    case["disc"]["indicator"] = "kxrcf"
+    return orc.Config(case)
+
+
+def _cell(rho_modes, u, p, gamma=1.4, q=1.0):
+    """Modal block [V][M] of a one-step state with the given density modes, constant u and p."""
+    rho = np.asarray(rho_modes, dtype=float)
+    M = len(rho)
+    w = np.zeros((5, M))
+    w[0] = rho
+    w[1] = rho * u
+    w[2] = 0.5 * rho * u * u
+    w[2, 0] += p / (gamma - 1.0) + q * rho[0]
+    w[2, 1:] += q * rho[1:]
+    w[3] = rho
+    return w
+
+
+def _flag(orc, cfg, nbL, we, nbR):
+    f = orc.lib().or_indicator(cfg.ref(), orc.vec(nbL.ravel()), orc.vec(we.ravel()), orc.vec(nbR.ravel()), 0, 0)
+    assert f in (0, 1)
+    return f
+
+
+@pytest.mark.parametrize("order_p", [1, 2, 3])
+@pytest.mark.parametrize("u", [0.7, -0.7])
+@pytest.mark.parametrize("target", [0.9, 1.1])
+def test_kxrcf_threshold_exponent_and_inflow_face(orc, order_p, u, target):
+    """KXRCF (config of the detonation workload): I = |jump at the inflow face| / (h^((N_p+1)/2) max_q |w_e(xi_q)|)
+    on rho (and rho E); troubled when I > 1.  The cell has a slope, so the normaliser is the largest value at
+    the Gauss nodes, not the mean.  A jump of I = target at the inflow face decides the flag; a jump ten times
+    larger at the outflow face changes nothing."""
+    E = 64
+    h = 1.0 / E
+    cfg = _kxrcf_cfg(orc, order_p, E)
+    M = order_p + 1
+    c0, c1 = 2.0, 0.4
+    rho_e = np.zeros(M)
+    rho_e[0], rho_e[1] = c0, c1
+    xq, _ = np.polynomial.legendre.leggauss(M)
+    norm = np.max(np.abs(c0 + c1 * xq))
+    we = _cell(rho_e, u, 1.0)
+    delta = target * h ** (0.5 * (order_p + 1)) * norm
+    inflow_left = u > 0
+    trace = c0 - c1 if inflow_left else c0 + c1       # the cell's density at its inflow face
+    out_trace = c0 + c1 if inflow_left else c0 - c1
+    # neighbours: constant states; the inflow neighbour's density differs by delta at the face, its
+    # energy equals the cell's trace there (no rho E jump), the outflow neighbour jumps by 10 delta
+    w_in = _cell([trace - delta] + [0.0] * (M - 1), u, 1.0)
+    w_out = _cell([out_trace + 10 * delta] + [0.0] * (M - 1), u, 1.0)
+    e_trace = np.sum(we[2] * (np.array([(-1.0) ** j for j in range(M)]) if inflow_left else np.ones(M)))
+    w_in[2, 0] = e_trace
+    w_out[2, 0] = np.sum(we[2] * (np.ones(M) if inflow_left else np.array([(-1.0) ** j for j in range(M)])))
+    nbL, nbR = (w_in, w_out) if inflow_left else (w_out, w_in)
+    assert _flag(orc, cfg, nbL, we, nbR) == (1 if target > 1 else 0)
+
+
+@pytest.mark.parametrize("target", [0.9, 1.1])
+def test_kxrcf_energy_jump(orc, target):
+    """The same test on rho E alone: no density jump, an energy jump of I = target (normalised by the
+    largest |rho E| at the Gauss nodes)."""
+    order_p, E, u = 2, 64, 0.5
+    h = 1.0 / E
+    cfg = _kxrcf_cfg(orc, order_p, E)
+    M = order_p + 1
+    we = _cell([1.5, 0.0, 0.0], u, 1.0)
+    norm = abs(we[2, 0])
+    delta = target * h ** 1.5 * norm
+    nbL = we.copy()
+    nbL[2, 0] -= delta
+    nbR = we.copy()
+    assert _flag(orc, cfg, nbL, we, nbR) == (1 if target > 1 else 0)
