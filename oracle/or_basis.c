@@ -149,6 +149,38 @@ int or_at_coeffs(int q, int k, double *c) {
 }
 
 /* ---------------------------------------------------------------------------
+ * Buffer-element DoFs of Eq. (11), temporal and hybrid (spatio-temporal).
+ *
+ * Sec. 3.3 closes by noting that the temporal stencil of the buffer element
+ * can be generalised to one that also uses delayed values at the element's
+ * other nodes, with fewer buffered time levels for the same order.  Reading:
+ * the Legendre coefficient j of a smooth field over an element of width dx
+ * carries the factor dx^j (only derivatives of order >= j contribute to it),
+ * and so do its time derivatives.  Extrapolating it in time from q_j levels
+ * with the weights of Eq. (8) for q_j levels leaves an error of order
+ * dt^{q_j} dx^j = dx^{r q_j + j} (dt ~ dx^r), so the order N_p + 1 of the
+ * full temporal stencil needs only q_j = ceil((N_p + 1 - j)/r) levels for
+ * mode j; for r = 1 and q levels in all, q_j = max(1, q - j).  In the values
+ * at the element's nodes this is a stencil over (node, level): each node's
+ * level-n value combines delayed values at all the element's nodes, and older
+ * levels contribute only the element's low modes (the oldest one its mean).
+ * ------------------------------------------------------------------------- */
+int or_at_buffer(int q, int k, int V, int M, int hybrid, const double *levels, double *out) {
+  if (q < 1 || q > 8 || k < 0 || V < 1 || M < 1) return -1;
+  double c[8];
+  for (int j = 0; j < M; ++j) {
+    int qj = hybrid ? (q - j > 1 ? q - j : 1) : q;
+    if (or_at_coeffs(qj, k, c)) return -1;
+    for (int v = 0; v < V; ++v) {
+      double acc = 0.0;
+      for (int l = 0; l < qj; ++l) acc += c[l] * levels[((size_t)l * V + v) * M + j];
+      out[v * M + j] = acc;
+    }
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
  * Delay models, Sec. 4.
  * ------------------------------------------------------------------------- */
 

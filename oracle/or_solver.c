@@ -138,6 +138,8 @@ int or_create(const or_config *cfg, const double *w0, int32_t max_steps, or_solv
   if (cfg->model == OR_ONESTEP && cfg->n_species != 2) return -1;
   if (cfg->limiter && cfg->model != OR_ONESTEP) return -1;
   if (cfg->mode != OR_SYNC && cfg->L < 1) return -1;
+  if (cfg->at_stencil != OR_AT_TEMPORAL && cfg->at_stencil != OR_AT_HYBRID) return -1;
+  if (cfg->limiter && (cfg->indicator < OR_KXRCF || cfg->indicator > OR_ALL)) return -1;
   or_solver *s = calloc(1, sizeof *s);
   s->cfg = *cfg;
   int ns = cfg->n_species, nr = cfg->n_reactions;
@@ -294,13 +296,21 @@ static int face_flux(or_solver *s, const double *wL, const double *wR, const dou
   return 0;
 }
 
-/* The AT combination of Eq. (7)/(11) over q past levels of a history record. */
+/* The AT combination of Eq. (7)/(11) over q past levels of a history record.  The
+   buffer-element DoFs (which = 2) follow the temporal or the hybrid stencil (or_at_buffer). */
 static void at_combine(or_solver *s, int i, int st, int which, int side, int len, double *out) {
   int k = s->kif[i];
+  if (which == 2) {
+    double lv[8 * OR_MAXV * OR_MAXM];
+    for (int j = 0; j < s->q; ++j)
+      memcpy(lv + (size_t)j * len, hist_U(s, s->n - k - j, st, i, side), sizeof(double) * len);
+    or_at_buffer(s->q, k, s->V, s->M, s->cfg.at_stencil == OR_AT_HYBRID, lv, out);
+    return;
+  }
   for (int t = 0; t < len; ++t) out[t] = 0.0;
   for (int j = 0; j < s->q; ++j) {
     int64_t m = s->n - k - j;
-    const double *h = which == 0 ? hist_F(s, m, st, i) : which == 1 ? hist_Wc(s, m, st, i) : hist_U(s, m, st, i, side);
+    const double *h = which == 0 ? hist_F(s, m, st, i) : hist_Wc(s, m, st, i);
     for (int t = 0; t < len; ++t) out[t] += s->cif[i * s->q + j] * h[t];
   }
 }
@@ -500,7 +510,9 @@ static int apply_limiter(or_solver *s, int st, const double *wu, double *wl) {
     double trL[OR_MAXV], trR[OR_MAXV];
     trace_of(s, nbL, 1, trL);
     trace_of(s, nbR, 0, trR);
-    int fl = s->cfg.indicator == OR_MINMOD ? minmod_flag(s, we, nbL, nbR) : kxrcf_flag(s, we, trL, trR, ghostL, ghostR);
+    int fl = s->cfg.indicator == OR_MINMOD ? minmod_flag(s, we, nbL, nbR)
+             : s->cfg.indicator == OR_ALL  ? 1
+                                           : kxrcf_flag(s, we, trL, trR, ghostL, ghostR);
     s->flags[e] = (int8_t)fl;
     if (fl) {
       s->nflag_total++;
@@ -643,7 +655,9 @@ int or_indicator(const or_config *cfg, const double *nbL, const double *we, cons
   double trL[OR_MAXV], trR[OR_MAXV];
   trace_of(s, gL, 1, trL);
   trace_of(s, gR, 0, trR);
-  int fl = s->cfg.indicator == OR_MINMOD ? minmod_flag(s, we, gL, gR) : kxrcf_flag(s, we, trL, trR, ghostL, ghostR);
+  int fl = s->cfg.indicator == OR_MINMOD ? minmod_flag(s, we, gL, gR)
+           : s->cfg.indicator == OR_ALL  ? 1
+                                         : kxrcf_flag(s, we, trL, trR, ghostL, ghostR);
   or_destroy(s);
   return fl;
 }

@@ -22,7 +22,8 @@ enum { OR_ONESTEP = 0, OR_DETAILED = 1 };
 enum { OR_PERIODIC = 0, OR_TRANSMISSIVE = 1 };
 enum { OR_RUSANOV = 0, OR_HLLC = 1 };
 enum { OR_SYNC = 0, OR_CAA = 1, OR_SAA = 2, OR_SCHEDULE = 3 };
-enum { OR_KXRCF = 0, OR_MINMOD = 1 };
+enum { OR_KXRCF = 0, OR_MINMOD = 1, OR_ALL = 2 };
+enum { OR_AT_TEMPORAL = 0, OR_AT_HYBRID = 1 };
 enum { OR_SSPRK3 = 0, OR_RK2 = 1, OR_LSERK4 = 2 };
 
 typedef struct {
@@ -49,7 +50,8 @@ typedef struct {
   int32_t bc;             /* OR_PERIODIC | OR_TRANSMISSIVE */
   int32_t flux;           /* OR_RUSANOV | OR_HLLC */
   int32_t limiter;        /* 1 = troubled-cell indicator + characteristic (AT-)WENO, Sec. 3.3 */
-  int32_t indicator;      /* OR_KXRCF | OR_MINMOD (TVB minmod on the conserved variables) */
+  int32_t indicator;      /* OR_KXRCF | OR_MINMOD (TVB minmod on the conserved variables) |
+                             OR_ALL (every cell limited: the accuracy-test setting of the WENO limiter) */
   double tvb_m;           /* TVB constant M of the minmod test (0 = TVD) */
   double weno_gamma[3];   /* linear weights gamma_{-1}, gamma_0, gamma_{+1} */
   double weno_eps;
@@ -65,6 +67,10 @@ typedef struct {
   const int8_t *schedule; /* [schedule_steps][n_if] explicit delays */
   int32_t schedule_steps;
   int32_t at_order;       /* q, the number of past levels in Eq. (7); 0 = N_p + 1 */
+  int32_t at_stencil;     /* buffer-element DoFs of Eq. (11) across delayed PE interfaces:
+                             OR_AT_TEMPORAL: every mode from the q levels n-k .. n-k-q+1;
+                             OR_AT_HYBRID: mode j from q_j = max(1, q - j) levels (the
+                             spatio-temporal stencil of Sec. 3.3, see or_at_buffer) */
 } or_config;
 
 typedef struct or_solver or_solver;
@@ -85,6 +91,10 @@ double or_legendre(int j, double x);
 double or_legendre_deriv(int j, int s, double x);   /* s-th derivative */
 void or_gauss_legendre(int n, double *x, double *w);
 int or_at_coeffs(int q, int k, double *c);          /* Eq. (8) solved exactly */
+/* Buffer-element DoFs of Eq. (11) at level n from the modal data of the levels n-k, n-k-1, ...
+   (levels[l] = [V][M] of level n-k-l, l < q): the temporal stencil (every mode from all q levels)
+   or the hybrid one (mode j from the first max(1, q - j) levels with the weights of that order). */
+int or_at_buffer(int q, int k, int V, int M, int hybrid, const double *levels, double *out);
 uint64_t or_splitmix64(uint64_t x);
 double or_saa_uniform(uint64_t seed, int64_t n, int32_t i, int32_t n_if);
 int or_raw_delay(const or_config *cfg, int32_t n_if, int64_t n, int32_t i);

@@ -59,7 +59,7 @@ class OrConfig(C.Structure):
         ("mode", C.c_int32), ("L", C.c_int32), ("pmf", C.POINTER(C.c_double)),
         ("seed", C.c_uint64),
         ("schedule", C.POINTER(C.c_int8)), ("schedule_steps", C.c_int32),
-        ("at_order", C.c_int32),
+        ("at_order", C.c_int32), ("at_stencil", C.c_int32),
     ]
 
 
@@ -89,6 +89,7 @@ def lib() -> C.CDLL:
             "or_legendre_deriv": (d, [C.c_int, C.c_int, d]),
             "or_gauss_legendre": (None, [C.c_int, P(d), P(d)]),
             "or_at_coeffs": (C.c_int, [C.c_int, C.c_int, P(d)]),
+            "or_at_buffer": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P(d), P(d)]),
             "or_splitmix64": (u64, [u64]),
             "or_saa_uniform": (d, [u64, i64, i32, i32]),
             "or_raw_delay": (C.c_int, [cfgp, i32, i64, i32]),
@@ -162,7 +163,7 @@ class Config:
         c.flux = HLLC if disc.get("flux", "rusanov") == "hllc" else RUSANOV
         c.limiter = int(disc.get("limiter", 0))
         c.rk = {"ssprk3": 0, "rk2": 1, "lserk4": 2}[disc.get("rk", "ssprk3")]
-        c.indicator = {"kxrcf": 0, "minmod": 1}[disc.get("indicator", "kxrcf")]
+        c.indicator = {"kxrcf": 0, "minmod": 1, "all": 2}[disc.get("indicator", "kxrcf")]
         c.tvb_m = float(disc.get("tvb_m", 0.0))
         g = disc.get("weno_gamma", (0.001, 0.998, 0.001))
         c.weno_gamma[0], c.weno_gamma[1], c.weno_gamma[2] = g
@@ -182,6 +183,7 @@ class Config:
             c.schedule = sch.ctypes.data_as(C.POINTER(C.c_int8))
             c.schedule_steps = int(sch.shape[0])
         c.at_order = int(asy.get("at_order", 0))
+        c.at_stencil = {"temporal": 0, "hybrid": 1}[asy.get("at_stencil", "temporal")]
         self.c = c
         self.V = 3 + c.n_species
         self.M = c.order_p + 1
