@@ -55,7 +55,8 @@ enum { ADG_PERIODIC = 0, ADG_TRANSMISSIVE = 1 };
 enum { ADG_RUSANOV = 0, ADG_HLLC = 1 };
 enum { ADG_SYNC = 0, ADG_CAA = 1, ADG_SAA = 2, ADG_SCHEDULE = 3 };
 enum { ADG_HOST = 0, ADG_DEVICE = 1 };
-enum { ADG_KXRCF = 0, ADG_MINMOD = 1 };
+enum { ADG_KXRCF = 0, ADG_MINMOD = 1, ADG_ALL_CELLS = 2 };
+enum { ADG_AT_TEMPORAL = 0, ADG_AT_HYBRID = 1 };
 enum { ADG_SSPRK3 = 0, ADG_RK2 = 1, ADG_LSERK4 = 2 };
 
 /* Detailed reaction mechanism (Sec. 2: mass-action kinetics with species
@@ -64,7 +65,10 @@ enum { ADG_SSPRK3 = 0, ADG_RK2 = 1, ADG_LSERK4 = 2 };
    K_c = exp(-Delta G/(Ru T)) (p_ref/(Ru T))^(sum nu).  Thermo: NASA
    7-coefficient polynomials, one temperature range.  Transport: viscosity
    mu = mu_ref (T/T_ref)^mu_exp, conductivity k = mu cp/Pr, unit Lewis number.
-   All arrays are read during adg_create only. */
+   All arrays are read during adg_create only.  Limits of the kernels (beyond
+   them ADG_ERR_UNSUPPORTED): 1..16 species, 1..32 reactions, at most two
+   molecules on either side of a reaction and at most four species whose net
+   coefficient is nonzero in one reaction (no third bodies). */
 typedef struct adg_mechanism {
   int32_t n_species, n_reactions;
   const double *W;        /* [Ns] kg/mol */
@@ -84,7 +88,7 @@ typedef struct {
                                 source W omega = -+ k_pre rho Y_R exp(-e_act/T), T = p/rho.
                              ADG_DETAILED: mixture of Ns thermally perfect species with the
                                 mechanism `mech`; viscous = 1 adds the Navier-Stokes terms. */
-  int32_t n_species;      /* Ns (2 for ADG_ONESTEP; the detailed-chemistry kernels take 9) */
+  int32_t n_species;      /* Ns: 2 for ADG_ONESTEP; 1..16 for ADG_DETAILED (up to 9 in batches) */
   int32_t viscous;
   double gamma, q_heat, e_act, k_pre;
   const adg_mechanism *mech;
@@ -96,14 +100,15 @@ typedef struct {
   int32_t n_quad;         /* Gauss-Legendre points per element: 0 = N_p + 1 (only value supported) */
   int32_t n_elem;         /* N_E >= 1 */
   double x_left, x_right;
-  int32_t bc;             /* ADG_PERIODIC | ADG_TRANSMISSIVE (ghost trace = interior trace; one-step
-                             model only, the detailed model returns ADG_ERR_UNSUPPORTED) */
+  int32_t bc;             /* ADG_PERIODIC | ADG_TRANSMISSIVE (ghost trace = interior trace for the
+                             state and, with LDG, for its gradient; the end faces are synchronous) */
   int32_t flux;           /* ADG_RUSANOV | ADG_HLLC (HLLC with ADG_ONESTEP only) */
   int32_t limiter;        /* 1 = troubled-cell indicator + characteristic (AT-)WENO after every
                              stage (ADG_ONESTEP) */
   int32_t indicator;      /* ADG_KXRCF: Krivodonova et al. on rho and rho E at inflow faces;
                              ADG_MINMOD: the TVB minmod test of the conserved variables (the
-                             TVD slope-limiter indicator of Sec. 3.3 when tvb_m = 0) */
+                             TVD slope-limiter indicator of Sec. 3.3 when tvb_m = 0);
+                             ADG_ALL_CELLS: every cell limited (accuracy tests of the limiter) */
   double tvb_m;           /* TVB constant M (>= 0) of ADG_MINMOD: face deviations up to M dx^2 pass */
   double weno_gamma[3];   /* linear weights of Eq. (10) */
   double weno_eps;        /* epsilon of Eq. (10) */
@@ -128,6 +133,13 @@ typedef struct {
                              schedule_steps; any other delay is ADG_ERR_ARG */
   int32_t schedule_steps;
   int32_t at_order;       /* q, number of levels in Eq. (7): 0 = N_p + 1; 1..6 */
+  int32_t at_stencil;     /* buffer-element DoFs of Eq. (11) across delayed PE interfaces (limiter):
+                             ADG_AT_TEMPORAL: every Legendre mode from the q levels n-k .. n-k-q+1;
+                             ADG_AT_HYBRID: the spatio-temporal stencil that closes Sec. 3.3, read
+                             from Eq. (8) with the dx^j size of mode j: mode j from the first
+                             max(1, q - j) of those levels, with the weights of that order (the
+                             same order of accuracy from fewer buffered values: the oldest level
+                             contributes only the element mean) */
 } adg_async;
 
 typedef struct adg_solver adg_solver;
@@ -178,9 +190,17 @@ int32_t adg_n_interfaces(const adg_solver *s);
    Synchronises. */
 adg_status adg_profile(adg_solver *s, int32_t n_steps, double *ms_out, int64_t *launches_out, int32_t n_classes);
 
-/* Use a captured HIP graph of `steps_per_graph` time steps for adg_step
-   (0 = plain launches, the default).  Takes effect at the next adg_step. */
+/* Use captured HIP graphs of `steps_per_graph` time steps for adg_step
+   (0 = plain launches, the default).  Takes effect at the next adg_step, which
+   captures two graphs: a step moves the solver between two alignments (step
+   counter parity, and the state buffer where it alternates), and each graph
+   replays from one of them, so adg_step(n) runs n / steps_per_graph graph
+   replays and n mod steps_per_graph plain steps whatever the alignment. */
 adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph);
+
+/* Number of graph replays adg_step has launched since adg_set_state (-1 for a
+   null solver): with adg_set_graph(g), adg_step(n) adds n / g. */
+int64_t adg_graph_replays(const adg_solver *s);
 
 /* Choose the stage kernel's work decomposition by measurement: for the
    detailed-chemistry model, the tile size (4 or 8 elements) and workgroup size
@@ -204,7 +224,10 @@ adg_status adg_set_kernel_config(adg_solver *s, int32_t config);
 /* Release the solver (the caller's workspace is not freed). */
 void adg_destroy(adg_solver *s);
 
+/* Message of the last error of solver s; with s = NULL, the message of the last
+   failed adg_create call on the calling thread. */
 const char *adg_last_error(const adg_solver *s);
+
 
 /* ------------------------------------------------------------------------
  * Batches of independent instances in one workspace.
@@ -228,8 +251,11 @@ const char *adg_last_error(const adg_solver *s);
  * step in FP64; ADG_MIXED_FP32 evaluates the modal operators (interpolation
  * to nodes and traces, LDG gradient, projection and lift) in FP32 with FP32
  * accumulation, while the temperature Newton inversion, the Arrhenius rates and
- * equilibrium constants, the interface fluxes and the RK update stay FP64.
- * One-step instances always run in FP64.
+ * equilibrium constants, the interface fluxes and the RK update stay FP64 --
+ * for N_p <= 3, where its error against the FP64 solution stays below a tenth
+ * of the discretisation error (measured: 4 % of it at N_p = 3); N_p = 4
+ * instances keep FP64 operators in a mixed batch (FP32 would be 11 times the
+ * discretisation error there).  One-step instances always run in FP64.
  *
  * Calls on one batch must not overlap.  adg_batch_add and adg_batch_remove
  * synchronise the batch's stream.
@@ -275,8 +301,10 @@ adg_status adg_batch_poll(adg_batch *b, int64_t *steps, int32_t *state_err);
    ADG_ERR_STATE if that instance latched a non-physical state. */
 adg_status adg_batch_get_state(adg_batch *b, int32_t slot, double *w, int64_t count, int32_t where);
 
-/* Use captured HIP graphs of steps_per_graph time steps (0 = plain launches);
-   the graph is rebuilt after the batch's composition changes. */
+/* Use captured HIP graphs of steps_per_graph time steps (0 = plain launches):
+   one graph per step counter parity, so adg_batch_step(n) replays
+   n / steps_per_graph graphs and runs n mod steps_per_graph plain steps; the
+   graphs are rebuilt after the batch's composition changes. */
 adg_status adg_batch_set_graph(adg_batch *b, int32_t steps_per_graph);
 
 /* Enqueue n_steps steps with HIP events around every launch; ms_out[c] is the

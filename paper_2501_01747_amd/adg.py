@@ -22,7 +22,8 @@ RUSANOV, HLLC = 0, 1
 SYNC, CAA, SAA, SCHEDULE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FP64, MIXED_FP32 = 0, 1
-KXRCF, MINMOD = 0, 1
+KXRCF, MINMOD, ALL_CELLS = 0, 1, 2
+AT_TEMPORAL, AT_HYBRID = 0, 1
 SSPRK3, RK2, LSERK4 = 0, 1, 2
 PROFILE_CLASSES = ("stage",)
 BATCH_PROFILE_CLASSES = ("detailed_stage", "onestep_stage")
@@ -69,7 +70,7 @@ class Async(C.Structure):
         ("mode", C.c_int32), ("L", C.c_int32), ("pmf", C.POINTER(C.c_double)),
         ("seed", C.c_uint64),
         ("schedule", C.POINTER(C.c_int8)), ("schedule_steps", C.c_int32),
-        ("at_order", C.c_int32),
+        ("at_order", C.c_int32), ("at_stencil", C.c_int32),
     ]
 
 
@@ -87,6 +88,7 @@ _sig = {
     "adg_n_interfaces": (C.c_int32, [C.c_void_p]),
     "adg_profile": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_int64), C.c_int32]),
     "adg_set_graph": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "adg_graph_replays": (C.c_int64, [C.c_void_p]),
     "adg_set_kernel_config": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_autotune": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_int32)]),
     "adg_destroy": (None, [C.c_void_p]),
@@ -159,7 +161,7 @@ class Problem:
         d.bc = TRANSMISSIVE if disc.get("bc", "periodic") == "transmissive" else PERIODIC
         d.flux = HLLC if disc.get("flux", "rusanov") == "hllc" else RUSANOV
         d.limiter = int(disc.get("limiter", 0))
-        d.indicator = {"kxrcf": KXRCF, "minmod": MINMOD}[disc.get("indicator", "kxrcf")]
+        d.indicator = {"kxrcf": KXRCF, "minmod": MINMOD, "all": ALL_CELLS}[disc.get("indicator", "kxrcf")]
         d.tvb_m = float(disc.get("tvb_m", 0.0))
         g = disc.get("weno_gamma", (0.001, 0.998, 0.001))
         d.weno_gamma[0], d.weno_gamma[1], d.weno_gamma[2] = g
@@ -181,6 +183,7 @@ class Problem:
             a.schedule = sch.ctypes.data_as(C.POINTER(C.c_int8))
             a.schedule_steps = int(sch.shape[0])
         a.at_order = int(asy.get("at_order", 0))
+        a.at_stencil = {"temporal": AT_TEMPORAL, "hybrid": AT_HYBRID}[asy.get("at_stencil", "temporal")]
         self.phys, self.disc, self.asyn = p, d, a
         self.E = d.n_elem
         self.V = 3 + p.n_species
@@ -208,6 +211,7 @@ class Solver:
         import torch
 
         self.problem = Problem(case)
+        h = C.c_void_p()
         nbytes = self.problem.workspace_bytes()
         if nbytes == 0:
             raise AdgError(ADG_ERR_ARG, "invalid problem description")
@@ -215,12 +219,11 @@ class Solver:
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) & ~255
         self.stream = torch.cuda.current_stream(self.workspace.device)
-        h = C.c_void_p()
         rc = adg_create(C.byref(self.problem.phys), C.byref(self.problem.disc), C.byref(self.problem.asyn),
                         C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
                         C.byref(h))
         if rc != ADG_OK:
-            raise AdgError(rc, "adg_create failed")
+            raise AdgError(rc, adg_last_error(None).decode())
         self.h = h
         self.shape = (self.problem.E, self.problem.V, self.problem.M)
 
@@ -269,6 +272,10 @@ class Solver:
 
     def set_graph(self, steps_per_graph: int):
         self._check(adg_set_graph(self.h, int(steps_per_graph)))
+
+    @property
+    def graph_replays(self) -> int:
+        return int(adg_graph_replays(self.h))
 
     def autotune(self, n_reps: int = 20) -> int:
         """Pick the stage kernel's work decomposition by timing (state unchanged)."""

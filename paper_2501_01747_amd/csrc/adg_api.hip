@@ -24,22 +24,34 @@ struct adg_solver {
   Problem P;
   hipStream_t stream = nullptr;
   int cur = 0;            // state buffer at the start of the next step (2N schemes alternate 0 and 1)
-  int graph_cur = 0;      // state buffer the captured graph starts from
-  int graph_cur_after = 0;
   int par = 0;            // step counter parity of the next step (P.step[par] holds its count)
-  int graph_par = 0;      // parity the captured graph starts from
-  int graph_par_after = 0;
+  // Captured graphs of graph_steps time steps.  A step moves (cur, par) to the other of two
+  // alignments (the counter parity flips every step; the state buffer, where it moves, flips
+  // with it), and a graph replays only from the alignment it was captured at: graph k starts
+  // from (graph_cur[k], graph_par[k]), graph 1 from the alignment one step after graph 0's,
+  // so every alignment has a graph and no realigning plain step is ever needed.
+  int graph_cur[2] = {0, 0}, graph_cur_after[2] = {0, 0};
+  int graph_par[2] = {0, 0}, graph_par_after[2] = {0, 0};
   int ns_cfg = 0;   // work decomposition of the detailed-chemistry stage kernel
   int graph_steps = 0;
   int graph_built_for = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  long long graph_replays = 0;   // graphs launched since set_state (adg_graph_replays)
   hipStream_t cap_stream = nullptr;
   std::vector<hipEvent_t> prof_events;
   std::string msg;
 };
 
 namespace {
+
+// Message of the last failed create call on this thread (adg_last_error(NULL)).
+thread_local std::string g_create_msg = "no error";
+
+adg_status create_fail(adg_status code, const std::string &m) {
+  g_create_msg = m;
+  return code;
+}
 
 adg_status fail(adg_solver *s, adg_status code, const std::string &m) {
   if (s) s->msg = m;
@@ -59,6 +71,14 @@ adg_status hip_fail(adg_solver *s, hipError_t e, const char *where) {
 // Launch the kernels of one time step.  `timer` (optional) records an event
 // pair around each launch for adg_profile.
 typedef void (*TimerFn)(adg_solver *, int cls, bool begin);
+
+// The state buffer and step counter parity after one time step from (cur, par).
+void next_alignment(const adg_solver *s, int &cur, int &par) {
+  const int S = s->P.lay.S;
+  if (rk_stage(s->P.disc.rk, 0).two_n) cur = (cur + S) % 2;
+  else if (s->P.disc.limiter && s->P.phys.model == ADG_ONESTEP) cur = 1 - cur;
+  par ^= 1;   // the step's last launch wrote the next count into the other counter
+}
 
 adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
   const int M = s->P.lay.M, S = s->P.lay.S;
@@ -110,39 +130,51 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       if (timer) timer(s, 0, false);
     }
   }
-  if (rk_stage(rk, 0).two_n) s->cur = (s->cur + S) % 2;
-  else if (s->P.disc.limiter && s->P.phys.model == ADG_ONESTEP) s->cur = 1 - s->cur;
-  s->par ^= 1;   // the step's last launch wrote the next count into the other counter
+  next_alignment(s, s->cur, s->par);
   return ADG_OK;
 }
 
 void destroy_graph(adg_solver *s) {
-  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
-  s->gexec = nullptr;
-  s->graph = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (s->gexec[k]) (void)hipGraphExecDestroy(s->gexec[k]);
+    if (s->graph[k]) (void)hipGraphDestroy(s->graph[k]);
+    s->gexec[k] = nullptr;
+    s->graph[k] = nullptr;
+  }
   s->graph_built_for = 0;
+}
+
+// Capture graph k from alignment (cur0, par0); nothing runs, the capture only records.
+adg_status capture_graph(adg_solver *s, int k, int cur0, int par0) {
+  const int cur_keep = s->cur, par_keep = s->par;
+  s->cur = cur0;
+  s->par = par0;
+  HIP_TRY(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  adg_status rc = ADG_OK;
+  for (int i = 0; i < s->graph_steps && rc == ADG_OK; ++i) rc = enqueue_step(s, s->cap_stream, nullptr);
+  s->graph_cur[k] = cur0;
+  s->graph_par[k] = par0;
+  s->graph_cur_after[k] = s->cur;
+  s->graph_par_after[k] = s->par;
+  s->cur = cur_keep;
+  s->par = par_keep;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+  if (rc != ADG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+  s->graph[k] = g;
+  HIP_TRY(s, hipGraphInstantiate(&s->gexec[k], g, nullptr, nullptr, 0));
+  return ADG_OK;
 }
 
 adg_status build_graph(adg_solver *s) {
   destroy_graph(s);
   if (!s->cap_stream) HIP_TRY(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-  HIP_TRY(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-  adg_status rc = ADG_OK;
-  const int cur0 = s->cur, par0 = s->par;
-  for (int i = 0; i < s->graph_steps && rc == ADG_OK; ++i) rc = enqueue_step(s, s->cap_stream, nullptr);
-  s->graph_cur = cur0;
-  s->graph_cur_after = s->cur;
-  s->graph_par = par0;
-  s->graph_par_after = s->par;
-  s->cur = cur0;   // nothing ran: capture only records
-  s->par = par0;
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
-  if (rc != ADG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
-  if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
-  s->graph = g;
-  HIP_TRY(s, hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+  int cur1 = s->cur, par1 = s->par;
+  next_alignment(s, cur1, par1);
+  adg_status rc = capture_graph(s, 0, s->cur, s->par);
+  if (rc == ADG_OK) rc = capture_graph(s, 1, cur1, par1);
+  if (rc != ADG_OK) { destroy_graph(s); return rc; }
   s->graph_built_for = s->graph_steps;
   return ADG_OK;
 }
@@ -159,16 +191,17 @@ size_t adg_workspace_bytes(const adg_physics *phys, const adg_discretization *di
 
 adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, const adg_async *as,
                       void *device_workspace, size_t workspace_bytes, void *hip_stream, adg_solver **out) {
-  if (!out) return ADG_ERR_ARG;
+  if (!out) return create_fail(ADG_ERR_ARG, "out is null");
   *out = nullptr;
   Layout L;
   std::string why;
-  if (!make_layout(phys, disc, as, L, &why)) return ADG_ERR_ARG;
-  if (!device_workspace || ((uintptr_t)device_workspace & 255)) return ADG_ERR_ARG;
-  if (workspace_bytes < L.total) return ADG_ERR_NOMEM;
+  if (!make_layout(phys, disc, as, L, &why)) return create_fail(ADG_ERR_ARG, why);
+  if (!device_workspace || ((uintptr_t)device_workspace & 255))
+    return create_fail(ADG_ERR_ARG, "workspace must be a non-null 256-byte aligned device pointer");
+  if (workspace_bytes < L.total) return create_fail(ADG_ERR_NOMEM, "workspace smaller than adg_workspace_bytes()");
   adg_solver *s = new adg_solver();
   adg_status rc = setup_problem(phys, disc, as, (char *)device_workspace, L, s->P);
-  if (rc != ADG_OK) { delete s; return rc; }
+  if (rc != ADG_OK) { delete s; return create_fail(rc, "problem set-up failed (unsupported combination or HIP error)"); }
   s->stream = (hipStream_t)hip_stream;
   *out = s;
   return ADG_OK;
@@ -188,6 +221,7 @@ adg_status adg_set_state(adg_solver *s, const double *w, int64_t count, int32_t 
   }
   s->cur = 0;
   s->par = 0;
+  s->graph_replays = 0;
   HIP_TRY(s, reset_problem(s->P, s->stream));
   if (where == ADG_HOST) HIP_TRY(s, hipStreamSynchronize(s->stream));
   return ADG_OK;
@@ -200,16 +234,18 @@ adg_status adg_step(adg_solver *s, int32_t n_steps) {
       adg_status rc = build_graph(s);
       if (rc != ADG_OK) return rc;
     }
-    // the graph starts from the state buffer and step counter parity it was captured
-    // with; a plain step realigns them (alternating state buffers of 2N schemes and
-    // limited Shu-Osher, an odd number of steps per graph) when needed
+    // whole graphs from the graph of the current alignment, then plain steps for the rest
     int left = n_steps;
     while (left > 0) {
-      if (left >= s->graph_steps && s->cur == s->graph_cur && s->par == s->graph_par) {
-        HIP_TRY(s, hipGraphLaunch(s->gexec, s->stream));
-        s->cur = s->graph_cur_after;
-        s->par = s->graph_par_after;
+      int k = -1;
+      for (int c = 0; c < 2; ++c)
+        if (s->cur == s->graph_cur[c] && s->par == s->graph_par[c]) k = c;
+      if (left >= s->graph_steps && k >= 0) {
+        HIP_TRY(s, hipGraphLaunch(s->gexec[k], s->stream));
+        s->cur = s->graph_cur_after[k];
+        s->par = s->graph_par_after[k];
         left -= s->graph_steps;
+        s->graph_replays += 1;
       } else {
         adg_status rc = enqueue_step(s, s->stream, nullptr);
         if (rc != ADG_OK) return rc;
@@ -375,6 +411,8 @@ adg_status adg_set_kernel_config(adg_solver *s, int32_t config) {
   return ADG_OK;
 }
 
+int64_t adg_graph_replays(const adg_solver *s) { return s ? s->graph_replays : -1; }
+
 adg_status adg_set_graph(adg_solver *s, int32_t steps_per_graph) {
   if (!s || steps_per_graph < 0) return ADG_ERR_ARG;
   s->graph_steps = steps_per_graph;
@@ -386,9 +424,10 @@ void adg_destroy(adg_solver *s) {
   if (!s) return;
   destroy_graph(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  s->cap_stream = nullptr;
   delete s;
 }
 
-const char *adg_last_error(const adg_solver *s) { return s ? s->msg.c_str() : "null solver"; }
+const char *adg_last_error(const adg_solver *s) { return s ? s->msg.c_str() : g_create_msg.c_str(); }
 
 }  // extern "C"

@@ -69,7 +69,6 @@ struct adg_batch {
   long long *d_step = nullptr;   // [slot][2]: each instance's step counters of the two parities
   int *d_err = nullptr;
   int par = 0;                   // step counter parity of the next batch step
-  int graph_par = 0;             // parity the captured graph starts from
   size_t heap_off = 0;
   std::map<size_t, size_t> free_list;  // offset -> bytes
   std::vector<Slot> slots;
@@ -81,8 +80,10 @@ struct adg_batch {
   std::vector<int2> h_tiles;
   int graph_steps = 0;
   bool graph_valid = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // graph p replays graph_steps steps from step counter parity p (launch arguments of the
+  // batched kernels), so a replay never waits for a realigning plain step
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
   std::vector<hipEvent_t> prof_events;
   std::vector<int> prof_class;
@@ -219,10 +220,12 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
 }
 
 void destroy_batch_graph(adg_batch *b) {
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->gexec = nullptr;
-  b->graph = nullptr;
+  for (int p = 0; p < 2; ++p) {
+    if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+    if (b->graph[p]) (void)hipGraphDestroy(b->graph[p]);
+    b->gexec[p] = nullptr;
+    b->graph[p] = nullptr;
+  }
   b->graph_valid = false;
 }
 
@@ -241,21 +244,31 @@ adg_status prepare(adg_batch *b) {
 adg_status build_batch_graph(adg_batch *b) {
   destroy_batch_graph(b);
   if (!b->cap_stream) BHIP(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-  BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  adg_status rc = ADG_OK;
-  const int par0 = b->par;
-  for (int i = 0; i < b->graph_steps && rc == ADG_OK; ++i) rc = enqueue_batch_step(b, b->cap_stream, false);
-  b->graph_par = par0;
-  b->par = par0;   // nothing ran: capture only records
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
-  if (rc != ADG_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc;
+  const int par_keep = b->par;
+  for (int p = 0; p < 2; ++p) {
+    b->par = p;
+    BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    adg_status rc = ADG_OK;
+    for (int i = 0; i < b->graph_steps && rc == ADG_OK; ++i) rc = enqueue_batch_step(b, b->cap_stream, false);
+    b->par = par_keep;   // nothing ran: capture only records
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc != ADG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      destroy_batch_graph(b);
+      return rc;
+    }
+    if (e != hipSuccess) {
+      destroy_batch_graph(b);
+      return bfail(b, ADG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    b->graph[p] = g;
+    e = hipGraphInstantiate(&b->gexec[p], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      destroy_batch_graph(b);
+      return bfail(b, ADG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
   }
-  if (e != hipSuccess) return bfail(b, ADG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  b->graph = g;
-  BHIP(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
   b->graph_valid = true;
   return ADG_OK;
 }
@@ -320,6 +333,8 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   if (count != (int64_t)L.E * L.V * L.M) return bfail(b, ADG_ERR_ARG, "state size mismatch");
   if (where != ADG_HOST && where != ADG_DEVICE) return bfail(b, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
   if (disc->rk != ADG_SSPRK3) return bfail(b, ADG_ERR_UNSUPPORTED, "batches run SSP-RK3 only");
+  if (phys->model == ADG_DETAILED && phys->n_species > kNsMaxSpecies)
+    return bfail(b, ADG_ERR_UNSUPPORTED, "batched detailed-chemistry instances take up to 9 species");
   int slot = -1;
   for (int i = 0; i < b->max_inst; ++i)
     if (!b->slots[i].used) { slot = i; break; }
@@ -401,8 +416,8 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   if (where == ADG_HOST) he = upload_state_host(P, w0, b->stream);
   else he = launch_to_planes(w0, P.W[0], L.E, VM, b->stream);
   if (he == hipSuccess) he = reset_problem(P, b->stream);
-  if (he == hipSuccess) he = hipMemsetAsync(P.step, 0, 2 * sizeof(long long), b->stream);
-  if (he == hipSuccess) he = hipMemsetAsync(P.err, 0, sizeof(int), b->stream);
+  if (he == hipSuccess) he = launch_zero(P.step, 2 * sizeof(long long), b->stream);
+  if (he == hipSuccess) he = launch_zero(P.err, sizeof(int), b->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(b->stream);
   if (he != hipSuccess) return fail_release(he, "initial state");
   b->slots[slot] = s;
@@ -438,18 +453,11 @@ adg_status adg_batch_step(adg_batch *b, int32_t n_steps) {
       rc = build_batch_graph(b);
       if (rc != ADG_OK) return rc;
     }
-    // the graph starts from the step counter parity it was captured with; with an odd
-    // number of steps per graph a plain step realigns the parity when needed
+    // whole graphs from the graph of the current parity, then plain steps for the rest
     while (done + b->graph_steps <= n_steps) {
-      if (b->par == b->graph_par) {
-        BHIP(b, hipGraphLaunch(b->gexec, b->stream));
-        b->par ^= b->graph_steps & 1;
-        done += b->graph_steps;
-      } else {
-        rc = enqueue_batch_step(b, b->stream, false);
-        if (rc != ADG_OK) return rc;
-        done += 1;
-      }
+      BHIP(b, hipGraphLaunch(b->gexec[b->par], b->stream));
+      b->par ^= b->graph_steps & 1;
+      done += b->graph_steps;
     }
   }
   for (; done < n_steps; ++done) {

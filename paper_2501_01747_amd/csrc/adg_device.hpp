@@ -78,6 +78,16 @@ __device__ __forceinline__ double at_weight(int q, int k, int j) {
   return (double)num / (double)den;
 }
 
+// Weight of level n-k-l for Legendre mode j of a buffer element (Eq. (11)): the temporal
+// stencil uses all q levels for every mode; the hybrid spatio-temporal one extrapolates mode j,
+// which carries the factor dx^j, from q_j = max(1, q - j) levels with the weights of that order
+// (0 for the levels it does not use).
+__device__ __forceinline__ double buffer_weight(const DelayParams &d, int k, int j, int l) {
+  const int qj = d.hybrid ? max(1, d.q - j) : d.q;
+  return l < qj ? at_weight(qj, k, l) : 0.0;
+}
+__device__ __forceinline__ int buffer_levels(const DelayParams &d, int j) { return d.hybrid ? max(1, d.q - j) : d.q; }
+
 // End of time step n in the step's last launch (parity par): the next step's
 // count goes to the other parity's counter.  Every launch of step n reads
 // step[par] only, so one workgroup's plain store needs no atomic, no barrier and

@@ -177,16 +177,19 @@ __device__ __forceinline__ void at_neighbour(const EulerArgs &a, long long n, in
 #pragma unroll
   for (int t = 0; t < 5 * M; ++t) c[t] = 0.0;
   const int off = a.ring.off_U + (side == 0 ? 0 : 5 * M);
-  // two levels per round trip (a level past q reads level n-k with weight 0)
+  // two levels per round trip (a level past q reads level n-k with weight 0); mode j of the
+  // hybrid stencil takes weight 0 past its own max(1, q - j) levels
   for (int j0 = 0; j0 < a.dl.q; j0 += 2) {
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const int jj = j0 + d;
       const bool in = jj < a.dl.q;
-      const double w = in ? at_weight(a.dl.q, k, jj) : 0.0;
+      double w[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) w[m] = in ? buffer_weight(a.dl, k, m, jj) : 0.0;
       const double *h = ring_at(a.ring, ring_slot(nmod, k + (in ? jj : 0), a.ring.D), a.stage, a.dl.nif, i) + off;
 #pragma unroll
-      for (int t = 0; t < 5 * M; ++t) c[t] += w * h[t];
+      for (int t = 0; t < 5 * M; ++t) c[t] += w[t % M] * h[t];
     }
   }
 }
@@ -206,7 +209,9 @@ __device__ __forceinline__ bool troubled(const EulerArgs &a, const LimiterArgs &
                                          int lane) {
   const bool ghostL = sd[0].ghost, ghostR = sd[1].ghost;
   bool flag = false;
-  if (l.indicator == 1) {
+  if (l.indicator == 2) {
+    flag = true;   // every cell limited (the accuracy-test setting of the WENO limiter)
+  } else if (l.indicator == 1) {
     // TVB minmod: the face deviations from the mean against the mean differences, every
     // variable; differences within 1e-10 of the largest |mean| of any variable in the
     // stencil count as equal (round-off in a constant state is not a slope)
@@ -402,7 +407,6 @@ template <int M>
 __device__ __forceinline__ void gather_first_slots(const EulerArgs &a, int nmod, const NbSide (&sd)[2],
                                                    unsigned long long nball, double *ls, int lane) {
   constexpr int C = 5 * M;
-  const int q = a.dl.q;
 #pragma unroll
   for (int q0 = 0; q0 < kNbSlots * C; q0 += 64) {
     const int pair = q0 + lane;
@@ -416,15 +420,19 @@ __device__ __forceinline__ void gather_first_slots(const EulerArgs &a, int nmod,
     const int i = side ? i1 : i0, k = side ? k1 : k0;   // a ghost side has i = -1, k = 0
     if (pair < kNbSlots * C && m != 0 && i >= 0 && k > 0) {
       const int off = a.ring.off_U + (side == 0 ? 0 : C) + comp;
+      const int mode = comp % M;
+      const int qm = buffer_levels(a.dl, mode);   // levels this mode uses (q, or max(1, q - mode))
       double acc = 0.0;
+      // levels past qm read level n-k (no further load) with weight 0
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool in = j < q;
-        const double w = in ? at_weight(q, k, j) : 0.0;
+        const bool in = j < qm;
+        const double w = in ? buffer_weight(a.dl, k, mode, j) : 0.0;
         acc += w * ring_at(a.ring, ring_slot(nmod, k + (in ? j : 0), a.ring.D), a.stage, a.dl.nif, i)[off];
       }
-      for (int j = 4; j < q; ++j)
-        acc += at_weight(q, k, j) * ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), a.stage, a.dl.nif, i)[off];
+      for (int j = 4; j < qm; ++j)
+        acc += buffer_weight(a.dl, k, mode, j) *
+               ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), a.stage, a.dl.nif, i)[off];
       ls[5 * M * 64 + s * C + comp] = acc;
     }
   }

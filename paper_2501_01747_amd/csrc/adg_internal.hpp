@@ -23,6 +23,7 @@ struct DelayParams {
   double cum[kMaxL];            // cumulative SAA probabilities (summed left to right)
   unsigned long long seed;
   const int8_t *sched;          // device [sched_steps][nif]
+  int hybrid;                   // buffer-element DoFs (Eq. (11)): mode j from max(1, q - j) levels
 };
 
 // History of past levels at PE interfaces: D slots (level n lives in slot n mod D),

@@ -131,7 +131,7 @@ template <int M, int NS, typename OpT, int NTH, int TE, int LPP = 0>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
                                         double *wout, int stage, int advance, const RkStage rk, double *kbuf,
                                         int e0, int par,
-                                        NsLds<M, NS, TE> &Ls, NsMech &smech) {
+                                        NsLds<M, NS, TE> &Ls, NsMechT<NS> &smech) {
   constexpr int V = 3 + NS, Q = M;
   using Lds = NsLds<M, NS, TE>;
   constexpr int NH = Lds::NH, NF = Lds::NF, NQ = Lds::NQ, NN = Lds::NN;
@@ -169,7 +169,10 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const int nloc = min(TE, E - e0);
   const long long n = a.step[par];
   const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
-  const NsMech *__restrict__ mk = &smech;
+  const NsMechT<NS> *__restrict__ mk = &smech;
+  // variables stored per element in HBM and in the ring (the capacity NS may pad species)
+  const int Vg = 3 + a.ns, VMg = Vg * M;
+  const bool periodic = a.periodic != 0;
   const int q_at = a.dl.q;
   bool ok = true;
 
@@ -183,7 +186,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const double *prev = rk.two_n ? kbuf : w0;
   double w0pre[kOut];
   {
-    constexpr int nwords = (int)(sizeof(NsMech) / 8);
+    constexpr int nwords = (int)(sizeof(NsMechT<NS>) / 8);
     constexpr int kMw = (nwords + NTH - 1) / NTH;
     constexpr int kSw = (V * M * NH + NTH - 1) / NTH;
     const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.mech);
@@ -202,24 +205,29 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       if (idx < V * M * NH) {
         const int c = idx / NH, l = idx % NH;
         int e = e0 - 2 + l;   // periodic: within a few periods of [0, E)
-        while (e < 0) e += E;
-        while (e >= E) e -= E;
-        sw[m] = ws[sidx(e, c, V * M)];
+        if (periodic) {
+          while (e < 0) e += E;
+          while (e >= E) e -= E;
+        }
+        // padded species, and elements past a transmissive end, stay zero
+        if (c < VMg && e >= 0 && e < E) sw[m] = ws[sidx(e, c, VMg)];
       }
     }
     int fi = -1;
     if (t < NF) {
       int f = e0 - 1 + t;
-      while (f < 0) f += E;
-      while (f >= E) f -= E;
-      fi = a.face_if[f];
+      if (periodic) {
+        while (f < 0) f += E;
+        while (f >= E) f -= E;
+      }
+      fi = f >= 0 && f <= E ? a.face_if[f] : -1;
     }
 #pragma unroll
     for (int m = 0; m < kOut; ++m) {
       const int idx = t + m * NTH;
       const int c = idx / TE, el = idx % TE;
       w0pre[m] = 0.0;
-      if (use_prev && idx < V * M * TE && el < nloc) w0pre[m] = prev[sidx(e0 + el, c, V * M)];
+      if (use_prev && idx < V * M * TE && el < nloc && c < VMg) w0pre[m] = prev[sidx(e0 + el, c, VMg)];
     }
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
@@ -250,26 +258,46 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   //    traces and of the fluxes at delayed PE interfaces are gathered from the ring
   for (int idx = t; idx < V * NH; idx += NTH) {
     const int v = idx / NH, l = idx % NH;
+    // transmissive ends: the ghost element beyond a boundary face carries the interior trace
+    // at that face on both of its sides (ghost trace = interior trace); elements further out
+    // are never read
+    int src = l, ghost = 0;
+    if (!periodic) {
+      const int e = e0 - 2 + l;
+      if (e < 0) { ghost = e == -1 ? 1 : 3; src = l + 1; }
+      else if (e >= E) { ghost = e == E ? 2 : 3; src = l - 1; }
+    }
     OpT sm = 0, sp = 0;
 #pragma unroll
     for (int j = kMixed ? 1 : 0; j < M; ++j) {
-      const OpT c = (OpT)sW[v * M + j][l];
+      const OpT c = (OpT)sW[v * M + j][src];
       sp += c;
       sm += (j & 1) ? -c : c;
     }
+    double tm, tp;
     if constexpr (kMixed) {
-      sTm[v][l] = sW[v * M][l] + (double)sm;
-      sTp[v][l] = sW[v * M][l] + (double)sp;
+      tm = sW[v * M][src] + (double)sm;
+      tp = sW[v * M][src] + (double)sp;
     } else {
-      sTm[v][l] = (double)sm;
-      sTp[v][l] = (double)sp;
+      tm = (double)sm;
+      tp = (double)sp;
     }
+    if (ghost == 1) tp = tm;
+    else if (ghost == 2) tm = tp;
+    else if (ghost == 3) tm = tp = 0.0;
+    sTm[v][l] = tm;
+    sTp[v][l] = tp;
   }
   for (int idx = t; idx < V * NF; idx += NTH) {
     const int v = idx / NF, fl = idx % NF;
     const int i = sI[fl], k = sK[fl];
     if (i < 0 || k == 0) continue;
     double acw = 0.0, acf = 0.0;
+    if (v >= Vg) {   // padded species: nothing in the ring
+      sWa[v][fl] = 0.0;
+      if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = 0.0;
+      continue;
+    }
     // levels 0..3 loaded together (a level past q reads level n-k with weight 0), later
     // ones (q > 4) one at a time
 #pragma unroll
@@ -298,7 +326,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const double wc = kMixed ? 0.5 * (sTp[v][fl] + sTm[v][fl + 1])
                              : (double)((OpT)0.5 * ((OpT)sTp[v][fl] + (OpT)sTm[v][fl + 1]));
     const int i = sI[fl];
-    if (i >= 0 && fl >= 1 && fl <= nloc)   // faces e0 .. e0+nloc-1 are owned by this tile
+    if (i >= 0 && fl >= 1 && fl <= nloc && v < Vg)   // faces e0 .. e0+nloc-1 are owned by this tile
       ring_at(a.ring, nmod, stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
     sWc[v][fl] = wc;
     if (i < 0 || sK[fl] == 0) sWa[v][fl] = wc;
@@ -344,7 +372,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const int p = min(t / LP, NP - 1);          // spare groups redo the last point and write nothing
       const bool writer = t / LP < NP;
       const bool node = p < NN;
-      int qn = 0, ff = 0, side = 0, l, lq;
+      int qn = 0, ff = 0, side = 0, es = 0, l, lq;
       if (node) {
         qn = p % Q;
         l = p / Q + 2;
@@ -353,9 +381,16 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
         const int pp = p - NN;
         ff = pp >> 1;                             // face e0 + ff
         side = pp & 1;                            // 0: the element left of the face (its xi = +1)
-        l = ff + 1 + side;
-        lq = ff + side;                           // gradient slot; its faces are lq and lq + 1
+        es = side;                                // the side whose element is evaluated
+        if (!periodic) {                          // a transmissive end: the ghost side takes the
+          if (e0 + ff == 0 && side == 0) es = 1;  // interior's trace and gradient trace
+          else if (e0 + ff == E && side == 1) es = 0;
+        }
+        l = ff + 1 + es;
+        lq = ff + es;                             // gradient slot; its faces are lq and lq + 1
       }
+      // points of a transmissive mesh past its last element carry no state (never read)
+      const bool valid = periodic || (node ? p / Q < nloc : e0 + ff <= E);
       const bool pe = !node && sI[ff + 1] >= 0;
       // value, gradient and synchronous gradient (PE-interface traces) of variable v
       auto eval = [&](int v, double &x, double &d, double &ds) {
@@ -370,14 +405,14 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
           d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
           ds = d;
         } else {
-          const OpT sgn = side ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
+          const OpT sgn = es ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
           OpT dO = 0, pj = kMixed ? sgn : (OpT)1;
 #pragma unroll
           for (int j = kMixed ? 1 : 0; j < M; ++j) {
             dO += pj * (OpT)sQ[v * M + j][lq];
             pj *= sgn;
           }
-          x = side ? sTm[v][l] : sTp[v][l];
+          x = es ? sTm[v][l] : sTp[v][l];
           d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
           ds = d;
           if (pe) {
@@ -387,7 +422,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 #pragma unroll
             for (int j = 0; j < M; ++j) {
               corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
-              pk *= side ? -1.0 : 1.0;
+              pk *= es ? -1.0 : 1.0;
             }
             ds = d + corr;
           }
@@ -430,7 +465,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const double cp = cv + Rmix;
       const double pr = wr * Rmix * T;
       const double snd = sqrt(cp / cv * pr * rho_inv);
-      if (writer) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
+      if (writer && valid) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
       double g0 = wm, g1 = wm * u + pr, g2 = u * (we + pr);
       double gs1 = g1, gs2 = g2;
       double gy[NO], gsy[NO];
@@ -568,7 +603,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     double F;
     if (i >= 0) {
       const double Fs = 0.5 * (sGs[0][v][ff] + sGs[1][v][ff] - diss);
-      if (ff < nloc) ring_at(a.ring, nmod, stage, a.dl.nif, i)[a.ring.off_F + v] = Fs;
+      if (ff < nloc && v < Vg) ring_at(a.ring, nmod, stage, a.dl.nif, i)[a.ring.off_F + v] = Fs;
       F = sK[ff + 1] > 0 ? sFat[v][ff] : Fs;
     } else {
       F = 0.5 * (sGf[0][v][ff] + sGf[1][v][ff] - diss);
@@ -604,7 +639,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const int idx = t + m * NTH;
     if (idx >= V * M * TE) break;
     const int c = idx / TE, el = idx % TE;   // output component c of local element el
-    if (el >= nloc) continue;
+    if (el >= nloc || c >= VMg) continue;
     const int v = c / M, j = c % M;
     OpT vol = 0;
     double srcs = 0.0;
@@ -626,7 +661,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       b = (double)vol - sF[v][el + 1] + ((j & 1) ? -sF[v][el] : sF[v][el]);
     }
     const double L = 2.0 * a.inv_dx * (half2j1 * b) + half2j1 * src;
-    const size_t gi = sidx(e0 + el, c, V * M);
+    const size_t gi = sidx(e0 + el, c, VMg);
     double o;
     // explicit fused multiply-adds: the single-problem and batched kernels round alike
     if (rk.two_n) {
@@ -646,7 +681,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 template <int M, int NS, int TE, int NTH>
 __global__ __launch_bounds__(NTH) void ns_stage_kernel(NsArgs a) {
   __shared__ NsLds<M, NS, TE> L;
-  __shared__ NsMech smech;
+  __shared__ NsMechT<NS> smech;
   ns_tile<M, NS, double, NTH, TE>(a, a.ws, a.w0, a.wout, a.stage, a.advance, a.rk, a.kbuf,
                                   xcd_item(blockIdx.x, gridDim.x) * TE, a.par, L, smech);
 }
@@ -711,7 +746,9 @@ __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *_
       if (M == 4) {
         ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m4, smech);
       } else if constexpr (MMAX >= 5) {
-        ns_tile<5, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m5, smech);
+        // N_p = 4 keeps FP64 operators in a mixed batch: FP32 rounding would exceed a tenth of the
+        // discretisation error there
+        ns_tile<5, kNsMaxSpecies, double, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m5, smech);
       }
     }
   }
@@ -720,17 +757,31 @@ __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *_
 // ------------------------------------------------------------------ host side
 
 bool ns_supported(int n_species, int n_reactions) {
-  return n_species == kNsMaxSpecies && n_reactions >= 1 && n_reactions <= kNsMaxReactions;
+  return n_species >= 1 && n_species <= kNsWideSpecies && n_reactions >= 1 && n_reactions <= kNsMaxReactions;
+}
+
+size_t ns_mech_bytes(int n_species) {
+  return ns_capacity(n_species) == kNsMaxSpecies ? sizeof(NsMech) : sizeof(NsMechWide);
+}
+
+template <int NSC>
+static adg_status upload_mech(const adg_physics *ph, void *dev_mech) {
+  NsMechT<NSC> hm;
+  const adg_status rc = ns_build_mech(ph, hm);
+  if (rc != ADG_OK) return rc;
+  if (hipMemcpy(dev_mech, &hm, sizeof hm, hipMemcpyHostToDevice) != hipSuccess) return ADG_ERR_HIP;
+  return ADG_OK;
 }
 
 adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *d, int E, int M, bool periodic,
                     double dx, const DelayParams &dl, const RingParams &rp, const Tables &tb, const int *face_if,
-                    long long *step, int *err, NsMech *dev_mech) {
-  if (!periodic) return ADG_ERR_UNSUPPORTED;
-  NsMech hm;
-  const adg_status rc = ns_build_mech(ph, hm);
+                    long long *step, int *err, void *dev_mech) {
+  const int ns = ph->mech->n_species;
+  const adg_status rc = ns_capacity(ns) == kNsMaxSpecies ? upload_mech<kNsMaxSpecies>(ph, dev_mech)
+                                                         : upload_mech<kNsWideSpecies>(ph, dev_mech);
   if (rc != ADG_OK) return rc;
-  if (hipMemcpy(dev_mech, &hm, sizeof hm, hipMemcpyHostToDevice) != hipSuccess) return ADG_ERR_HIP;
+  a.ns = ns;
+  a.periodic = periodic ? 1 : 0;
   a.face_if = face_if;
   a.step = step;
   a.err = err;
@@ -746,10 +797,13 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
   return ADG_OK;
 }
 
-adg_status ns_build_mech(const adg_physics *ph, NsMech &hm) {
+template <int NSC>
+adg_status ns_build_mech(const adg_physics *ph, NsMechT<NSC> &hm) {
   const adg_mechanism *m = ph->mech;
-  if (!ns_supported(m->n_species, m->n_reactions)) return ADG_ERR_UNSUPPORTED;
+  if (!ns_supported(m->n_species, m->n_reactions) || m->n_species > NSC) return ADG_ERR_UNSUPPORTED;
   std::memset(&hm, 0, sizeof hm);
+  // padded species: zero thermo, no reactions, unit molecular weight (finite 1/W)
+  for (int i = m->n_species; i < NSC; ++i) hm.W[i] = hm.invW[i] = 1.0;
   hm.ns = m->n_species;
   hm.nr = m->n_reactions;
   hm.Ru = m->Ru;
@@ -813,21 +867,21 @@ adg_status ns_build_mech(const adg_physics *ph, NsMech &hm) {
   return ADG_OK;
 }
 
-template <int M, int TE, int NTH>
+template <int M, int NS, int TE, int NTH>
 static hipError_t ns_launch(const NsArgs &a, hipStream_t s) {
   const int blocks = (a.E + TE - 1) / TE;
-  hipLaunchKernelGGL((ns_stage_kernel<M, kNsMaxSpecies, TE, NTH>), dim3(blocks), dim3(NTH), 0, s, a);
+  hipLaunchKernelGGL((ns_stage_kernel<M, NS, TE, NTH>), dim3(blocks), dim3(NTH), 0, s, a);
   return hipGetLastError();
 }
 
-template <int M>
+template <int M, int NS>
 static hipError_t ns_M(int cfg, const NsArgs &a, hipStream_t s) {
   switch (cfg) {
-    case 0: return ns_launch<M, 8, 512>(a, s);
-    case 1: return ns_launch<M, 8, 256>(a, s);
-    case 2: return ns_launch<M, 4, 256>(a, s);
-    case 3: return ns_launch<M, 4, 512>(a, s);
-    case 4: return ns_launch<M, 8, 1024>(a, s);
+    case 0: return ns_launch<M, NS, 8, 512>(a, s);
+    case 1: return ns_launch<M, NS, 8, 256>(a, s);
+    case 2: return ns_launch<M, NS, 4, 256>(a, s);
+    case 3: return ns_launch<M, NS, 4, 512>(a, s);
+    case 4: return ns_launch<M, NS, 8, 1024>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -857,14 +911,23 @@ hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, i
   return hipGetLastError();
 }
 
-hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, hipStream_t s) {
+template <int NS>
+static hipError_t ns_stage_ns(int M, int cfg, const NsArgs &a, hipStream_t s) {
   switch (M) {
-    case 2: return ns_M<2>(cfg, a, s);
-    case 3: return ns_M<3>(cfg, a, s);
-    case 4: return ns_M<4>(cfg, a, s);
-    case 5: return ns_M<5>(cfg, a, s);
+    case 2: return ns_M<2, NS>(cfg, a, s);
+    case 3: return ns_M<3, NS>(cfg, a, s);
+    case 4: return ns_M<4, NS>(cfg, a, s);
+    case 5: return ns_M<5, NS>(cfg, a, s);
   }
   return hipErrorInvalidValue;
 }
+
+hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, hipStream_t s) {
+  return ns_capacity(a.ns) == kNsMaxSpecies ? ns_stage_ns<kNsMaxSpecies>(M, cfg, a, s)
+                                            : ns_stage_ns<kNsWideSpecies>(M, cfg, a, s);
+}
+
+template adg_status ns_build_mech<kNsMaxSpecies>(const adg_physics *, NsMech &);
+template adg_status ns_build_mech<kNsWideSpecies>(const adg_physics *, NsMechWide &);
 
 }  // namespace adg

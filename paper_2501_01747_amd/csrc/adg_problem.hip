@@ -134,13 +134,16 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   } else if (ph->model == ADG_DETAILED) {
     if (!ph->mech) return bad("detailed model needs a mechanism");
     if (ph->n_species != ph->mech->n_species) return bad("n_species differs from the mechanism");
+    if (ph->n_species < 1 || ph->n_species > kNsWideSpecies) return bad("the detailed model takes 1..16 species");
     if (d->limiter) return bad("the limiter supports the one-step model only");
     if (d->flux != ADG_RUSANOV) return bad("the detailed model uses the Rusanov flux");
   } else {
     return bad("unknown model");
   }
   if (d->rk != ADG_SSPRK3 && d->rk != ADG_RK2 && d->rk != ADG_LSERK4) return bad("unknown integrator");
-  if (d->limiter && d->indicator != ADG_KXRCF && d->indicator != ADG_MINMOD) return bad("unknown indicator");
+  if (d->limiter && d->indicator != ADG_KXRCF && d->indicator != ADG_MINMOD && d->indicator != ADG_ALL_CELLS)
+    return bad("unknown indicator");
+  if (as->at_stencil != ADG_AT_TEMPORAL && as->at_stencil != ADG_AT_HYBRID) return bad("unknown at_stencil");
   if (d->limiter && !(d->tvb_m >= 0.0)) return bad("tvb_m must be >= 0");
   if (as->mode == ADG_SAA) {
     if (!as->pmf) return bad("SAA needs pmf");
@@ -192,7 +195,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   L.counters = off; off += 256;
   L.ring = off;   off += align256(sizeof(double) * (size_t)L.D * L.S * (L.nif > 0 ? L.nif : 1) * L.rec);
   L.sched = off;  off += as->mode == ADG_SCHEDULE ? align256((size_t)as->schedule_steps * (L.nif > 0 ? L.nif : 1)) : 0;
-  L.mech = off;   off += ph->model == ADG_DETAILED ? align256(sizeof(NsMech)) : 0;
+  L.mech = off;   off += ph->model == ADG_DETAILED ? align256(ns_mech_bytes(ph->n_species)) : 0;
   L.total = off;
   return true;
 }
@@ -240,6 +243,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
   dl.nif = L.nif;
   dl.q = L.q;
   dl.seed = as->seed;
+  dl.hybrid = as->at_stencil == ADG_AT_HYBRID;
   if (as->mode == ADG_SAA) {
     double cum = 0.0;
     for (int k = 0; k < as->L; ++k) { cum += as->pmf[k]; dl.cum[k] = cum; }
@@ -295,7 +299,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
     }
   } else {
     adg_status rc = ns_setup(P.na, phys, disc, L.E, L.M, periodic, dx, dl, rp, tb, P.face_if, P.step, P.err,
-                             (NsMech *)(base + L.mech));
+                             (void *)(base + L.mech));
     if (rc != ADG_OK) return rc;
     for (int b = 0; b < 3; ++b) P.na.W[b] = P.W[b];
     P.na.kbuf = P.W[2];
@@ -329,12 +333,45 @@ hipError_t download_state_host(const Problem &P, const double *buf, double *w, h
   return hipSuccess;
 }
 
+// Zero fill by a kernel (not hipMemsetAsync): a caller may capture the reset of a problem into
+// a HIP graph, and fill kernels replay like any other node.  Eight-byte words where the region
+// is 8-byte aligned and long, single bytes otherwise (per-slot counters of a batch are 4-byte
+// aligned).
+__global__ void zero_words_kernel(unsigned long long *__restrict__ p, size_t nwords, unsigned char *__restrict__ tail,
+                                  int ntail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) p[i] = 0ull;
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ void zero_bytes_kernel(unsigned char *__restrict__ p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  const int threads = 256;
+  if (((uintptr_t)p & 7) || bytes < 64) {
+    size_t blocks = (bytes + threads - 1) / threads;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(zero_bytes_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, (unsigned char *)p, bytes);
+    return hipGetLastError();
+  }
+  const size_t nwords = bytes / 8;
+  size_t blocks = (nwords + threads - 1) / threads;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, (unsigned long long *)p, nwords,
+                     (unsigned char *)p + nwords * 8, (int)(bytes % 8));
+  return hipGetLastError();
+}
+
 hipError_t reset_problem(const Problem &P, hipStream_t st) {
   const Layout &L = P.lay;
-  hipError_t e = hipMemsetAsync(P.base + L.counters, 0, 256, st);
+  hipError_t e = launch_zero(P.base + L.counters, 256, st);
   if (e == hipSuccess)
-    e = hipMemsetAsync(P.ring, 0, sizeof(double) * (size_t)L.D * L.S * (L.nif > 0 ? L.nif : 1) * L.rec, st);
-  if (e == hipSuccess) e = hipMemsetAsync(P.flags, 0, (size_t)L.E, st);
+    e = launch_zero(P.ring, sizeof(double) * (size_t)L.D * L.S * (L.nif > 0 ? L.nif : 1) * L.rec, st);
+  if (e == hipSuccess) e = launch_zero(P.flags, (size_t)L.E, st);
   return e;
 }
 

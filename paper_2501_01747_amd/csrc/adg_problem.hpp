@@ -53,5 +53,7 @@ hipError_t upload_state_host(const Problem &P, const double *w, hipStream_t st);
 hipError_t download_state_host(const Problem &P, const double *buf, double *w, hipStream_t st);
 // Step counter, error flag, history ring and flags back to zero.
 hipError_t reset_problem(const Problem &P, hipStream_t st);
+// Zero `bytes` bytes at p with a fill kernel on stream st (capturable, unlike hipMemsetAsync).
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 
 }  // namespace adg
