@@ -238,9 +238,10 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
     b, cases = build_c3_batch(precision, n_inst)
     elems = sum(c["disc"]["n_elem"] for c, _ in cases)
     tuned = b.autotune()
+    graph = min(graph, steps)   # the timed steps: steps // graph replays, steps mod graph plain steps
     if graph:
         b.set_graph(graph)
-    b.step(warmup)
+    b.step(max(warmup, 1))      # the first step after set_graph captures the graphs
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -261,7 +262,8 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
         "value": dof * 3 * steps / el, "unit": "DOF-updates/s", "ms_per_step": el * 1e3 / steps,
         "steps": steps, "warmup": warmup, "precision": precision,
         "config": {"workload": "c3_batched_ignition", "instances": len(cases), "elements": elems, "dof": dof,
-                   "order_p": [2, 3], "graph_steps": graph, "tile_elems": (8, 4)[tuned]},
+                   "order_p": [2, 3], "graph_steps": graph,
+                   "timed_graph_replays": steps // graph if graph else 0, "tile_elems": (8, 4)[tuned]},
         "state_errors": int(er.sum()), "steps_done_min": int(st[st >= 0].min()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -333,6 +335,28 @@ def region_stage_ms(s, steps: int, graph: int = 10) -> float:
     return ev0.elapsed_time(ev1) / (3 * steps)
 
 
+def hbm_points(steps: int = 20):
+    """The one-step stage kernels at sizes where HBM bounds them (the C0 physics at E = 2^22 without
+    the limiter, the C2 physics at E = 2^21 with it), each with its roofline against 8 TB/s: mean
+    launch time from HIP events over graph-replayed steps on the solver's stream."""
+    out = {}
+    for key, res, kernel in (("c0_physics_E4194304", sweep_euler([2**22], steps)[0], "euler_stage_kernel"),
+                             ("c2_physics_E2097152", sweep_limiter([2**21], steps)[0], "euler_lim_kernel")):
+        out[key] = {"n_elem": res["n_elem"], "dof": res["dof"], "launch_ms": res["stage_ms"],
+                    "roofline": {"bound": "hbm", "kernel": kernel, "achieved": res["GBps"], "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": res["frac_hbm"], "bytes_per_launch": res["bytes"]}}
+    return out
+
+
+def served_short(n_req: int, rate: float, precision: str):
+    """A short served stream (n_req requests at the fixed arrival rate) for the default line."""
+    out = bench_serve(n_req, rate, 16.0, 1024, 10, precision)
+    keep = ("requests", "completed_ok", "failed", "p50_latency_s", "p99_latency_s", "mean_latency_s", "mean_queue_s",
+            "makespan_s", "requests_per_s", "dof_updates_per_s", "latency_by_kind", "rate_req_per_s", "max_active",
+            "rounds", "precision")
+    return {k: out[k] for k in keep}
+
+
 def sweep_euler(sizes, steps=20):
     """Size sweep of the one-step Euler stage kernel (C0 physics, N_p = 2, 8 PEs, SAA) into the
     HBM-bound regime: per size, the stage kernel's mean launch time (HIP graphs, events over
@@ -358,7 +382,7 @@ def sweep_euler(sizes, steps=20):
         ms = region_stage_ms(s, steps)
         nbytes = euler_stage_bytes(case)
         out.append({"n_elem": E, "dof": gen.dof(case), "stage_ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9,
-                    "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                    "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes": nbytes})
         s.close()
         del s
         torch.cuda.empty_cache()
@@ -383,7 +407,7 @@ def sweep_limiter(sizes, steps=20):
         ms = region_stage_ms(s, steps)
         nbytes = euler_stage_bytes(case)
         out.append({"n_elem": E, "dof": gen.dof(case), "stage_ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9,
-                    "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                    "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes": nbytes})
         s.close()
         del s
         torch.cuda.empty_cache()
@@ -413,6 +437,9 @@ def main():
     ap.add_argument("--serve-heap-gib", type=float, default=16.0)
     ap.add_argument("--serve-slots", type=int, default=1024)
     ap.add_argument("--serve-chunk", type=int, default=10)
+    ap.add_argument("--served-requests", type=int, default=160,
+                    help="default line: requests of the short served stream (0 = skip)")
+    ap.add_argument("--no-hbm-points", action="store_true", help="default line: skip the HBM-bound Euler points")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -457,10 +484,14 @@ def main():
     s = adg.Solver(case)
     s.set_state(w0)
     tuned = s.autotune()
-    if args.graph:
-        s.set_graph(args.graph)
-    s.step(args.warmup)
+    # graphs of min(--graph, K) steps: the timed K steps are K // g replays and K mod g plain
+    # steps (the library keeps a graph for each step alignment, so none realigns)
+    graph = min(args.graph, args.steps)
+    if graph:
+        s.set_graph(graph)
+    s.step(max(args.warmup, 1))   # captures the graphs (the first step after set_graph)
     s.sync()
+    replays0 = s.graph_replays
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -470,6 +501,7 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     s.sync()
+    replays = s.graph_replays - replays0
     dof = gen.dof(case)
     value = dof * 3 * args.steps / el
     ms_per_step = el * 1e3 / args.steps
@@ -504,7 +536,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": case["name"], "n_elem": d["n_elem"], "order_p": d["order_p"],
                    "n_vars": 3 + case["physics"]["n_species"], "n_pe": case["async"]["n_pe"],
-                   "delays": case["async"]["mode"], "dof": dof, "graph_steps": args.graph,
+                   "delays": case["async"]["mode"], "dof": dof, "graph_steps": graph,
+                   "timed_graph_replays": replays, "timed_plain_steps": args.steps - replays * graph,
+                   "dt": d["dt"], "cfl": case.get("cfl"),
+                   "dt_convention": "dt = CFL dx / ((2 N_p + 1) lambda_0), lambda_0 = max |u| + a of the initial state",
                    "kernel_config": tuned},
         "roofline": roof,
         "isolated_launch_ms": {k: v[0] for k, v in prof.items()},
@@ -523,6 +558,10 @@ def main():
         bb = bench_batched(args.batch_steps, 5, args.graph, args.precision, cpu=not args.no_cpu_baseline)
         out["batched_mixed"] = bb
         out["batched_over_plain"] = bb["value"] / value
+    if args.served_requests > 0 and detailed:
+        out["served"] = served_short(args.served_requests, args.rate or C4_RATE, args.precision)
+    if not args.no_hbm_points:
+        out["hbm_points"] = hbm_points()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, w0)
     print(json.dumps(out), flush=True)

@@ -4,6 +4,7 @@ oracle, admission by workspace footprint, per-instance step targets and graph re
 import numpy as np
 import pytest
 
+from _parity import check, var_errors
 from workloads import gen
 
 pytestmark = pytest.mark.gpu
@@ -27,17 +28,6 @@ def mech():
     return gen.c1_mechanism()
 
 
-def var_errors(a, b):
-    """Per-variable L2 error against the variable's physical scale (momentum: sqrt(||rho|| ||rho E||))."""
-    V = a.shape[1]
-    num = np.linalg.norm((a - b).transpose(1, 0, 2).reshape(V, -1), axis=1)
-    nrm = np.linalg.norm(b.transpose(1, 0, 2).reshape(V, -1), axis=1)
-    scale = np.full(V, nrm[0])
-    scale[1] = np.sqrt(nrm[0] * nrm[2])
-    scale[2] = nrm[2]
-    return num / scale
-
-
 def ns_case(mech, E, P, n_pe, mode, seed):
     case, w0 = gen.case_c1(E=E, order_p=P, n_pe=n_pe, mode=mode, mech=mech, seed=seed, cfl=CFL[P],
                            Lx=0.01 * E / 2048)
@@ -52,12 +42,17 @@ def mixed_cases(mech):
 
 
 def onestep_cases():
+    """One-step instances of every order with and without the limiter (N_p = 1..4 each)."""
     c0, w0 = gen.case_c0(E=100, n_pe=5)
     c0b, w0b = gen.case_c0(E=37, order_p=3, n_pe=4, mode="caa", cfl=0.04)
     c0b["async"]["L"] = 2
     c2, w2 = gen.case_c2(E=256, n_pe=8, length=8.0, shock_x=2.0)
     c2h, w2h = gen.case_c2(E=128, order_p=1, n_pe=3, length=4.0, shock_x=1.0)   # shock on a face
-    return [(c0, w0), (c0b, w0b), (c2, w2), (c2h, w2h)]
+    c01, w01 = gen.case_c0(E=50, order_p=1, n_pe=3, cfl=0.2)
+    c04, w04 = gen.case_c0(E=60, order_p=4, n_pe=4, cfl=0.025)
+    c24, w24 = gen.case_shock(256, 4, n_pe=8)                                      # N_p = 4, limited
+    c22, w22 = gen.case_shock(160, 2, n_pe=5)
+    return [(c0, w0), (c0b, w0b), (c2, w2), (c2h, w2h), (c01, w01), (c04, w04), (c24, w24), (c22, w22)]
 
 
 def make_batch(adg, cases, precision="fp64", spare=0):
@@ -94,18 +89,18 @@ def test_fp64_batch_equals_single_solver(adg, mech):
 
 
 def test_fp64_batch_against_oracle(adg, orc, mech):
-    cases = mixed_cases(mech)[:3] + onestep_cases()[:1]
+    """Instances of both models, every order, limited and unlimited, against the oracle."""
+    cases = mixed_cases(mech) + onestep_cases()
     b = make_batch(adg, cases)
     slots = [b.add(c, w) for c, w in cases]
     b.step(10)
     for (c, w), sl in zip(cases, slots):
+        print(f"[batch-oracle] {c['name']} E={c['disc']['n_elem']} Np={c['disc']['order_p']} "
+              f"lim={c['disc'].get('limiter', 0)}", flush=True)
         o = orc.OracleSolver(c, w, 11)
         o.step(10)
-        ref = o.state()
-        err = float(np.max(var_errors(b.state(sl), ref))) if c["physics"]["model"] == "detailed" else \
-            float(np.linalg.norm(b.state(sl) - ref) / np.linalg.norm(ref))
-        print(f"[batch-oracle] {c['name']} E={c['disc']['n_elem']} err={err:.2e}", flush=True)
-        assert err < 1e-10
+        err = check(b.state(sl), o.state(), c, 1e-10, c["name"])
+        print(f"[batch-oracle]   err={err:.2e}", flush=True)
     b.close()
 
 
@@ -120,7 +115,7 @@ def test_alone_equals_in_the_mix(adg, mech, precision):
     wa = alone.state(sa)
     alone.close()
     mix = make_batch(adg, cases, precision)
-    order = [1, 0, 5, 7, 3, 4, 2, 6, 8, 9]
+    order = [1, 0, 5, 7, 3, 4, 2, 6, 8, 9, 13, 10, 12, 11]
     slots = {i: mix.add(*cases[i], n_steps=(3 if i == 0 else 0)) for i in order}
     mix.step(7)
     wm = mix.state(slots[probe])
@@ -147,14 +142,19 @@ def restrict_to_coarse(w_fine, order_p):
     return out * ((2 * np.arange(M) + 1) / 2.0)[None, None, :]
 
 
-def test_mixed_precision_error_budget(adg, orc, mech):
-    """Error of the FP32-operator path against the FP64 oracle, next to the FP64 path's and
-    next to the oracle's own discretisation error (solution on E against 2E elements)."""
-    E, P, steps = 64, 3, 120
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_mixed_precision_error_budget(adg, orc, mech, P):
+    """Error of the mixed path against the FP64 oracle, next to the FP64 path's and next to the
+    oracle's own discretisation error (solution on E against 2E elements), for every order the
+    batched and served workloads use (N_p = 4 keeps FP64 operators in a mixed batch: measured with
+    FP32 ones, the error was 11 times the discretisation error, 5.9e-11 against 5.2e-12)."""
+    E, steps = 64, 120
     case, w0 = ns_case(mech, E, P, 8, "saa", 21)
     # the same run on twice the elements; both use the finer mesh's time step
     case2, w02 = gen.case_c1(E=2 * E, order_p=P, n_pe=8, mode="saa", mech=mech, seed=21, cfl=CFL[P],
                              Lx=0.01 * E / 2048)
+    # and the diffusive limit of the finer mesh (at N_p = 4 the acoustic step exceeds it there)
+    case2["disc"]["dt"] = min(case2["disc"]["dt"], gen.diffusive_dt(mech, 0.01 * E / 2048 / (2 * E), P))
     case["disc"]["dt"] = case2["disc"]["dt"]
     b64 = make_batch(adg, [(case, w0)], "fp64")
     s64 = b64.add(case, w0)
@@ -166,14 +166,16 @@ def test_mixed_precision_error_budget(adg, orc, mech):
     o.step(steps)
     ref = o.state()
     e64 = float(np.max(var_errors(b64.state(s64), ref)))
-    emx = float(np.max(var_errors(bmx.state(smx), ref)))
+    emx_v = var_errors(bmx.state(smx), ref)
+    emx = float(np.max(emx_v))
     o2 = orc.OracleSolver(case2, w02, steps + 1)
     o2.step(steps)
-    edisc = float(np.max(var_errors(ref, restrict_to_coarse(o2.state(), P))))
-    print(f"[mixed-budget] fp64 {e64:.2e}  mixed {emx:.2e}  discretisation(E vs 2E) {edisc:.2e}", flush=True)
-    print("[mixed-budget] mixed per variable", np.array2string(var_errors(bmx.state(smx), ref), precision=2))
-    print("[mixed-budget] discretisation per variable",
-          np.array2string(var_errors(ref, restrict_to_coarse(o2.state(), P)), precision=2), flush=True)
+    ed_v = var_errors(ref, restrict_to_coarse(o2.state(), P))
+    edisc = float(np.max(ed_v))
+    print(f"[mixed-budget] Np={P} fp64 {e64:.2e}  mixed {emx:.2e}  discretisation(E vs 2E) {edisc:.2e}  "
+          f"ratio {emx / edisc:.3f}", flush=True)
+    print("[mixed-budget] mixed per variable", np.array2string(emx_v, precision=2))
+    print("[mixed-budget] discretisation per variable", np.array2string(ed_v, precision=2), flush=True)
     assert e64 < 1e-10
     assert emx < 0.1 * edisc
     b64.close()
@@ -267,31 +269,42 @@ def test_graph_replay_matches_plain_launches(adg, mech):
             np.testing.assert_array_equal(x, y)
 
 
-def test_batched_ignition_full_size_sampled(adg, orc):
-    """The full batched workload (4096 instances, mixed precision) for a few steps; sampled
-    instances (smallest, largest, one of each order) against the FP64 oracle."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_ignition_full_size_sampled(adg, orc, precision):
+    """The full batched workload (4096 instances) in the benchmark's launch configuration (batch
+    autotuned, 20 steps from captured graphs); sampled instances (smallest, largest, one of each
+    order, and the first of each PE count at the ends of its range) against the FP64 oracle.
+    FP64: the parity bar; mixed: within the error the mixed path is allowed, 1e-8 per variable
+    (the per-order budget test bounds it by a tenth of the discretisation error)."""
     mech = gen.c1_mechanism()
     cases = list(gen.case_c3(mech=mech))
     heap = sum(adg.Batch.instance_bytes(c) for c, _ in cases)
     elems = sum(c["disc"]["n_elem"] for c, _ in cases)
-    print(f"[c3] {len(cases)} instances, {elems} elements, heap {heap / 2**30:.2f} GiB", flush=True)
-    b = adg.Batch(len(cases), elems, heap, precision="mixed")
+    print(f"[c3] {precision}: {len(cases)} instances, {elems} elements, heap {heap / 2**30:.2f} GiB", flush=True)
+    b = adg.Batch(len(cases), elems, heap, precision=precision)
     slots = [b.add(c, w) for c, w in cases]
-    b.set_graph(2)
-    b.step(2)
+    b.autotune(2)
+    b.set_graph(10)
+    b.step(20)
     steps, errs = b.poll()
-    assert (steps[: len(cases)] == 2).all() and not errs.any()
+    assert (steps[: len(cases)] == 20).all() and not errs.any()
     E = np.array([c["disc"]["n_elem"] for c, _ in cases])
-    pick = {int(np.argmin(E)), int(np.argmax(E))}
+    npe = np.array([c["async"]["n_pe"] for c, _ in cases])
+    pick = {int(np.argmin(E)), int(np.argmax(E)), int(np.argmin(npe)), int(np.argmax(npe))}
     pick |= {next(i for i, (c, _) in enumerate(cases) if c["disc"]["order_p"] == p) for p in (2, 3)}
+    tol = 1e-10 if precision == "fp64" else 1e-8
     for i in sorted(pick):
         c, w = cases[i]
-        o = orc.OracleSolver(c, w, 3)
-        o.step(2)
-        err = float(np.max(var_errors(b.state(slots[i]), o.state())))
-        print(f"[c3] instance {i} E={c['disc']['n_elem']} Np={c['disc']['order_p']} mixed err {err:.2e}",
-              flush=True)
-        assert err < 1e-6
+        o = orc.OracleSolver(c, w, 21)
+        o.step(20)
+        ref = o.state()
+        got = b.state(slots[i])
+        err = float(np.max(var_errors(got, ref)))
+        print(f"[c3] {precision} instance {i} E={c['disc']['n_elem']} Np={c['disc']['order_p']} "
+              f"PEs={c['async']['n_pe']} err {err:.2e}", flush=True)
+        if precision == "fp64":
+            check(got, ref, c, tol, f"c3 instance {i}")
+        assert err < tol
     b.close()
 
 

@@ -3,6 +3,7 @@ AT fluxes and AT central traces) against the oracle, through the C ABI."""
 import numpy as np
 import pytest
 
+from _parity import check, var_errors
 from workloads import gen
 
 pytestmark = pytest.mark.gpu
@@ -24,20 +25,6 @@ def mech():
     return gen.synthetic_mechanism(1747, dt=1e-10)
 
 
-def var_errors(a, b):
-    """L2 error of each conserved variable relative to that variable's physical scale:
-    ||rho|| for rho and the partial densities, ||rho E|| for the energy and
-    sqrt(||rho|| ||rho E||) (density times a velocity of the order of the sound
-    speed) for the momentum, which is near zero in these quiescent states."""
-    V = a.shape[1]
-    num = np.linalg.norm((a - b).transpose(1, 0, 2).reshape(V, -1), axis=1)
-    nrm = np.linalg.norm(b.transpose(1, 0, 2).reshape(V, -1), axis=1)
-    scale = np.full(V, nrm[0])
-    scale[1] = np.sqrt(nrm[0] * nrm[2])
-    scale[2] = nrm[2]
-    return num / scale
-
-
 def rel_per_var(a, b):
     err = var_errors(a, b)
     if np.max(err) >= 1e-10:
@@ -57,9 +44,8 @@ def compare(adg, orc, case, w0, steps, every, tol=1e-10):
         s.step(k)
         o.step(k)
         done += k
-        r = rel_per_var(s.state(), o.state())
+        r = check(s.state(), o.state(), case, tol, f"step {done}")
         worst = max(worst, r)
-        assert r < tol, (done, r)
     s.close()
     return worst
 
@@ -107,20 +93,23 @@ def test_worst_case_schedule(adg, orc, mech):
 
 def test_c1_full_size(adg, orc, mech):
     """The C1 workload at full size (E = 2048, N_p = 3, 16 PEs, SAA set-1) in the launch
-    configuration the benchmark times (steps replayed from a captured HIP graph)."""
+    configuration the benchmark times (autotuned decomposition, steps replayed from captured
+    HIP graphs of 50 steps), over the benchmark's 200 steps."""
     case, w0 = gen.case_c1()
     s = adg.Solver(case)
-    s.set_graph(10)
     s.set_state(w0)
-    o = orc.OracleSolver(case, w0, 21)
-    s.step(10)
-    o.step(10)
-    r1 = rel_per_var(s.state(), o.state())
-    s.step(10)
-    o.step(10)
-    r2 = rel_per_var(s.state(), o.state())
-    print(f"[parity-ns] c1 full size: rel {r1:.2e} after 10 steps, {r2:.2e} after 20")
-    assert r1 < 1e-10 and r2 < 1e-10
+    s.autotune(5)
+    s.set_graph(50)
+    o = orc.OracleSolver(case, w0, 201)
+    done = 0
+    for k in (50, 50, 100):
+        s.step(k)
+        o.step(k)
+        done += k
+        r = check(s.state(), o.state(), case, 1e-10, f"c1 step {done}")
+        print(f"[parity-ns] c1 full size: worst {r:.2e} after {done} steps", flush=True)
+    assert s.step_count() == 200
+    s.close()
 
 
 def test_conservation_on_gpu(adg, mech):
@@ -182,3 +171,77 @@ def test_low_storage_integrators_detailed(adg, orc, mech, rk):
     case, w0 = gen.case_c1(E=40, order_p=2, n_pe=5, mech=mech, cfl=0.08, Lx=0.01 * 40 / 2048)
     case["disc"]["rk"] = rk
     compare(adg, orc, case, w0, 9, every=3)
+
+
+def test_odd_graph_length(adg, mech):
+    """Detailed chemistry with a graph of 3 steps (the step counters' parity flips per replay):
+    7 + 6 steps equal plain launches bit for bit, step count included."""
+    case, w0 = gen.case_c1(E=72, n_pe=6, mech=mech, Lx=0.01 * 72 / 2048)
+    ref = None
+    for graph in (0, 3):
+        s = adg.Solver(case)
+        s.set_state(w0)
+        s.set_graph(graph)
+        s.step(7)
+        s.step(6)
+        w = s.state()
+        assert s.step_count() == 13
+        s.close()
+        if ref is None:
+            ref = w
+        else:
+            np.testing.assert_array_equal(w, ref)
+
+
+SPECIES_SETS = {
+    5: ["A2", "B2", "A", "AB", "Z"],
+    12: ["A2", "B2", "A", "B", "AB", "A2B", "AB2", "A2B2", "A3", "B3", "A3B", "Z"],
+    16: ["A2", "B2", "A", "B", "AB", "A2B", "AB2", "A2B2", "A3", "B3", "A3B", "AB3", "A2B3", "A3B2", "A4", "Z"],
+}
+
+
+def mechanism_of(ns):
+    """Seeded synthetic mechanism over `ns` species (as many atom-balanced reactions as exist, at
+    most 30): the kernels pad it to their species capacity (9 or 16)."""
+    for nr in range(30, 0, -1):
+        try:
+            return gen.synthetic_mechanism(1747 + ns, n_reactions=nr, dt=1e-10, species=SPECIES_SETS[ns])
+        except RuntimeError:
+            continue
+    raise RuntimeError("no mechanism")
+
+
+@pytest.mark.parametrize("ns", [5, 12, 16])
+@pytest.mark.parametrize("order_p,mode", [(2, "saa"), (3, "caa")])
+def test_other_species_counts(adg, orc, ns, order_p, mode):
+    """Mechanisms of 5, 12 and 16 species (padded in the kernels of capacity 9 and 16) against the
+    oracle, with delays, on a mesh with a ragged last tile."""
+    mech = mechanism_of(ns)
+    case, w0 = gen.case_c1(E=45, order_p=order_p, n_pe=5, mech=mech, mode=mode, cfl={2: 0.08, 3: 0.04}[order_p],
+                           Lx=0.01 * 45 / 2048)
+    if mode == "caa":
+        case["async"]["L"] = 3
+    print(f"[species] ns={ns} nr={mech['n_reactions']}", flush=True)
+    compare(adg, orc, case, w0, 10, every=5)
+
+
+@pytest.mark.parametrize("ns", [9, 12])
+@pytest.mark.parametrize("E,n_pe", [(37, 4), (8, 2), (1, 1)])
+def test_transmissive_ends(adg, orc, ns, E, n_pe):
+    """Transmissive ends (ghost trace = interior trace for the state and the LDG gradient, the
+    boundary faces synchronous): a temperature ramp through both ends, against the oracle; tiles at
+    either end, one element, and a mesh shorter than a tile."""
+    mech = gen.c1_mechanism() if ns == 9 else mechanism_of(ns)
+    case, w0 = gen.case_c1(E=E, order_p=3, n_pe=n_pe, mech=mech, mode="saa", Lx=0.01 * max(E, 8) / 2048,
+                           phase=0.7)
+    case["disc"]["bc"] = "transmissive"
+    compare(adg, orc, case, w0, 10, every=5)
+
+
+def test_batch_refuses_more_than_nine_species(adg):
+    case, w0 = gen.case_c1(E=16, mech=mechanism_of(12), n_pe=2, Lx=0.01 * 16 / 2048)
+    b = adg.Batch(2, 100, adg.Batch.instance_bytes(case))
+    with pytest.raises(adg.AdgError) as ei:
+        b.add(case, w0)
+    assert ei.value.code == adg.ADG_ERR_UNSUPPORTED
+    b.close()

@@ -103,6 +103,7 @@ def case_c0(E=512, order_p=2, steps=500, n_pe=8, mode="saa", pmf=(0.5, 0.5), see
         "async": {"n_pe": n_pe, "pe_offsets": None, "mode": mode, "L": len(pmf), "pmf": list(pmf),
                   "seed": seed, "at_order": at_order},
         "steps": steps,
+        "cfl": cfl,
     }
     w0 = project(lambda x: onestep_conserved(1.0 + 0.2 * np.sin(2 * np.pi * x), 1.0, 1.0, 1.0, phys),
                  E, order_p, 0.0, 1.0)
@@ -188,6 +189,7 @@ def case_c2(E=8192, order_p=3, steps=200, n_pe=64, mode="saa", L=4, seed=2503, l
         "async": {"n_pe": n_pe, "pe_offsets": None, "mode": mode, "L": L, "pmf": [1.0 / L] * L,
                   "seed": seed, "at_order": at_order},
         "steps": steps,
+        "cfl": cfl,
     }
     w0 = project(fn, E, order_p, 0.0, length)
     return case, _fix_density_modes(w0)
@@ -208,6 +210,16 @@ _SPECIES = [
     ("A2B2", (2, 2, 0), (-1.5e5, -1.2e5)),
     ("Z", (0, 0, 1), (0.0, 0.0)),
 ]
+# further species of the same two elements, for mechanisms of more than 9 species
+_SPECIES_EXTRA = [
+    ("A3", (3, 0, 0), (1.1e5, 1.5e5)),
+    ("B3", (0, 3, 0), (1.3e5, 1.6e5)),
+    ("A3B", (3, 1, 0), (-0.9e5, -0.5e5)),
+    ("AB3", (1, 3, 0), (0.2e5, 0.6e5)),
+    ("A2B3", (2, 3, 0), (-1.0e5, -0.6e5)),
+    ("A3B2", (3, 2, 0), (-1.6e5, -1.2e5)),
+    ("A4", (4, 0, 0), (0.8e5, 1.2e5)),
+]
 T0 = 298.15
 
 
@@ -224,8 +236,10 @@ def _nasa_s_R(a, T):
 
 
 def synthetic_mechanism(seed: int = 1747, n_reactions: int = 21, dt: float = 8.0e-10,
-                        p: float = P_ATM) -> dict:
-    """9 species over two reactive elements and an inert diluent, 21 reversible reactions.
+                        p: float = P_ATM, species: list[str] | None = None) -> dict:
+    """9 species over two reactive elements and an inert diluent, 21 reversible reactions
+    (`species`: other species by name, from the 9 and a few larger molecules of the same elements;
+    A2, B2 and Z are needed for the premix).
 
     * NASA-7 single-range thermo: a1..a5 drawn and redrawn until cp(T) is
       non-decreasing on [200, 4000] K; a6, a7 set the formation enthalpy and the
@@ -238,12 +252,14 @@ def synthetic_mechanism(seed: int = 1747, n_reactions: int = 21, dt: float = 8.0
       pressure p; otherwise the parameters (then the channel) are redrawn.
     """
     rng = np.random.default_rng(seed)
-    ns = len(_SPECIES)
-    W = np.array([sum(n * _ELEMENT_W[el] for n, el in zip(comp, "ABZ")) for _, comp, _ in _SPECIES])
-    comp = np.array([c for _, c, _ in _SPECIES], dtype=np.int64)
+    catalogue = {sp[0]: sp for sp in _SPECIES + _SPECIES_EXTRA}
+    table = _SPECIES if species is None else [catalogue[n] for n in species]
+    ns = len(table)
+    W = np.array([sum(n * _ELEMENT_W[el] for n, el in zip(comp, "ABZ")) for _, comp, _ in table])
+    comp = np.array([c for _, c, _ in table], dtype=np.int64)
     nasa = np.zeros((ns, 7))
     Tg = np.linspace(200.0, 4000.0, 400)
-    for i, (name, c, (hlo, hhi)) in enumerate(_SPECIES):
+    for i, (name, c, (hlo, hhi)) in enumerate(table):
         atoms = sum(c)
         while True:
             a = np.array([rng.uniform(2.5, 3.5) + 0.6 * (atoms - 1),
@@ -313,7 +329,7 @@ def synthetic_mechanism(seed: int = 1747, n_reactions: int = 21, dt: float = 8.0
                 break
     if r < n_reactions:
         raise RuntimeError("synthetic mechanism: not enough admissible channels")
-    return {"n_species": ns, "n_reactions": n_reactions, "names": [s[0] for s in _SPECIES],
+    return {"n_species": ns, "n_reactions": n_reactions, "names": [s[0] for s in table],
             "W": W, "nasa7": nasa, "nu_f": nu_f, "nu_r": nu_r, "A": A, "b": b, "Ea": Ea,
             "Ru": RU, "p_ref": P_ATM, "mu_ref": 1.8e-5, "T_ref": 300.0, "mu_exp": 0.7,
             "prandtl": 0.7, "T_guess": 1500.0, "composition": comp}
@@ -377,6 +393,7 @@ def case_c1(E=2048, order_p=3, steps=200, n_pe=16, mode="saa", pmf=(0.3, 0.4, 0.
         "async": {"n_pe": n_pe, "pe_offsets": None, "mode": mode, "L": len(pmf), "pmf": list(pmf),
                   "seed": seed, "at_order": at_order},
         "steps": steps,
+        "cfl": cfl,
     }
     w0 = project(lambda x: ignition_state(mech, x, Lx, phase=phase), E, order_p, 0.0, Lx)
     return case, _fix_density_modes(w0)
@@ -446,7 +463,6 @@ def c4_requests(n, rate, seed=42, arrival_seed=7, e_range=(256, 65536), steps_ra
     rng = np.random.default_rng(seed)
     arr = np.random.default_rng(arrival_seed)
     mech = mech if mech is not None else c1_mechanism()
-    dt_chem = default_dt(0.04, 0.01 / 2048, 750.0, 3)
     lo, hi = math.log(e_range[0]), math.log(e_range[1])
     t = 0.0
     for i in range(n):
@@ -456,15 +472,28 @@ def c4_requests(n, rate, seed=42, arrival_seed=7, e_range=(256, 65536), steps_ra
         E = int(round(math.exp(rng.uniform(lo, hi))))
         order_p = int(rng.integers(1, 5))
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
-        if kind == "ignition":
-            case, w0 = case_c1(E=E, order_p=order_p, steps=steps, n_pe=min(16, E), seed=(delay_seed << 20) + i,
-                               cfl=IGNITION_CFL[order_p], mech=mech, phase=float(rng.uniform(0.0, 2.0 * math.pi)))
-            case["disc"]["dt"] = min(case["disc"]["dt"], dt_chem, diffusive_dt(mech, 0.01 / E, order_p))
-        else:
+        phase = float(rng.uniform(0.0, 2.0 * math.pi)) if kind == "ignition" else 0.0
+        if kind == "shock":
             E = max(e_range[0], 16 * int(round(E / 16)))
-            case, w0 = case_shock(E, order_p, seed=(delay_seed << 20) + i)
-        case["name"] = "c4_" + kind
+        case, w0 = c4_request(kind, E, order_p, steps, (delay_seed << 20) + i, mech=mech, phase=phase)
         yield {"rid": i, "kind": kind, "case": case, "w0": w0, "steps": steps, "arrival": t}
+
+
+def c4_request(kind, E, order_p, steps, seed, mech=None, phase=0.0):
+    """One request of the served stream: an ignition solve (Navier-Stokes, detailed chemistry, 1 cm,
+    16 PEs, SAA k <= 2, time step capped by the mechanism's screening step and the diffusive limit)
+    or a reacting shock (one-step Euler with the limiter at dx = 1/32, 64 PEs, k <= 3; E a multiple
+    of 16)."""
+    if kind == "ignition":
+        mech = mech if mech is not None else c1_mechanism()
+        dt_chem = default_dt(0.04, 0.01 / 2048, 750.0, 3)
+        case, w0 = case_c1(E=E, order_p=order_p, steps=steps, n_pe=min(16, E), seed=seed,
+                           cfl=IGNITION_CFL[order_p], mech=mech, phase=phase)
+        case["disc"]["dt"] = min(case["disc"]["dt"], dt_chem, diffusive_dt(mech, 0.01 / E, order_p))
+    else:
+        case, w0 = case_shock(E, order_p, seed=seed)
+    case["name"] = "c4_" + kind
+    return case, w0
 
 
 def dof(case: dict) -> int:
