@@ -225,8 +225,25 @@ adg_status adg_set_kernel_config(adg_solver *s, int32_t config);
 void adg_destroy(adg_solver *s);
 
 /* Message of the last error of solver s; with s = NULL, the message of the last
-   failed adg_create call on the calling thread. */
+   failed adg_create / adg_create_noalloc call on the calling thread. */
 const char *adg_last_error(const adg_solver *s);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): adg_create without a
+   workspace.  The solver's device memory (state buffers, history ring, counters,
+   constant tables) is a static array of 64 MiB per device, part of the library,
+   whose address is taken once per device; nothing is allocated on the device
+   (no hipMalloc, hipFree or allocating library routine, torch's included, is
+   called; set-up uses host memory only, for small tables).  Problems larger than
+   64 MiB (adg_workspace_bytes) return ADG_ERR_NOMEM.  One such solver may be alive
+   per device: a second call before adg_destroy of the first returns ADG_ERR_STATE.
+   The array keeps the contents of the previous solver; adg_set_state clears what
+   must start at zero (step counters, error flag, history ring, flags) with fill
+   kernels, which may be captured.  Calls that use one device's array from
+   several threads or streams at once race.  Every other call works on the
+   solver as on one from adg_create; adg_destroy frees the array for the next. */
+adg_status adg_create_noalloc(const adg_physics *phys, const adg_discretization *disc, const adg_async *as,
+                              void *hip_stream, adg_solver **out);
 
 
 /* ------------------------------------------------------------------------

@@ -79,6 +79,7 @@ _sig = {
     "adg_workspace_bytes": (C.c_size_t, [_P(Physics), _P(Discretization), _P(Async)]),
     "adg_create": (C.c_int32, [_P(Physics), _P(Discretization), _P(Async), C.c_void_p, C.c_size_t,
                                C.c_void_p, _P(C.c_void_p)]),
+    "adg_create_noalloc": (C.c_int32, [_P(Physics), _P(Discretization), _P(Async), C.c_void_p, _P(C.c_void_p)]),
     "adg_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "adg_step": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
@@ -207,21 +208,29 @@ class Solver:
     """One ADG problem on the current HIP device: torch owns the workspace, the
     library runs every step on the current torch stream."""
 
-    def __init__(self, case: dict, device: str = "cuda"):
+    def __init__(self, case: dict, device: str = "cuda", noalloc: bool = False):
+        """noalloc: place the solver in the library's static device scratch (adg_create_noalloc)
+        instead of a torch workspace."""
         import torch
 
         self.problem = Problem(case)
         h = C.c_void_p()
-        nbytes = self.problem.workspace_bytes()
-        if nbytes == 0:
-            raise AdgError(ADG_ERR_ARG, "invalid problem description")
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) & ~255
-        self.stream = torch.cuda.current_stream(self.workspace.device)
-        rc = adg_create(C.byref(self.problem.phys), C.byref(self.problem.disc), C.byref(self.problem.asyn),
-                        C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
-                        C.byref(h))
+        if noalloc:
+            self.workspace = None
+            self.stream = torch.cuda.current_stream(torch.device(device))
+            rc = adg_create_noalloc(C.byref(self.problem.phys), C.byref(self.problem.disc),
+                                    C.byref(self.problem.asyn), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        else:
+            nbytes = self.problem.workspace_bytes()
+            if nbytes == 0:
+                raise AdgError(ADG_ERR_ARG, "invalid problem description")
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) & ~255
+            self.stream = torch.cuda.current_stream(self.workspace.device)
+            rc = adg_create(C.byref(self.problem.phys), C.byref(self.problem.disc), C.byref(self.problem.asyn),
+                            C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
+                            C.byref(h))
         if rc != ADG_OK:
             raise AdgError(rc, adg_last_error(None).decode())
         self.h = h

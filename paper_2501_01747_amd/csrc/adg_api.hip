@@ -20,6 +20,14 @@
 
 using namespace adg;
 
+// Device memory of the solver that adg_create_noalloc places without allocating: one
+// array per device (every device the library runs on holds it until the process ends).
+// In host code `scratch` names a host-side stand-in, not the device array: its device
+// address comes from hipGetSymbolAddress, once per device with that device current, and
+// only that address is ever passed on.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct adg_solver {
   Problem P;
   hipStream_t stream = nullptr;
@@ -41,6 +49,7 @@ struct adg_solver {
   hipStream_t cap_stream = nullptr;
   std::vector<hipEvent_t> prof_events;
   std::string msg;
+  int noalloc_dev = -1;   // device whose static scratch holds this solver (adg_create_noalloc), else -1
 };
 
 namespace {
@@ -52,6 +61,11 @@ adg_status create_fail(adg_status code, const std::string &m) {
   g_create_msg = m;
   return code;
 }
+
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` per device (hipGetSymbolAddress)
+adg_solver g_noalloc_solver[kMaxDevices];
+bool g_noalloc_busy[kMaxDevices] = {};
 
 adg_status fail(adg_solver *s, adg_status code, const std::string &m) {
   if (s) s->msg = m;
@@ -203,6 +217,40 @@ adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, c
   adg_status rc = setup_problem(phys, disc, as, (char *)device_workspace, L, s->P);
   if (rc != ADG_OK) { delete s; return create_fail(rc, "problem set-up failed (unsupported combination or HIP error)"); }
   s->stream = (hipStream_t)hip_stream;
+  *out = s;
+  return ADG_OK;
+}
+
+adg_status adg_create_noalloc(const adg_physics *phys, const adg_discretization *disc, const adg_async *as,
+                              void *hip_stream, adg_solver **out) {
+  if (!out) return create_fail(ADG_ERR_ARG, "out is null");
+  *out = nullptr;
+  Layout L;
+  std::string why;
+  if (!make_layout(phys, disc, as, L, &why)) return create_fail(ADG_ERR_ARG, why);
+  if (L.total > kScratchBytes)
+    return create_fail(ADG_ERR_NOMEM, "problem needs " + std::to_string(L.total) + " bytes; the static scratch of "
+                                          "adg_create_noalloc holds " + std::to_string(kScratchBytes));
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return create_fail(ADG_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return create_fail(ADG_ERR_UNSUPPORTED, "device index beyond 63");
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return create_fail(ADG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  if (g_noalloc_busy[dev])
+    return create_fail(ADG_ERR_STATE, "a solver of adg_create_noalloc is alive on this device (destroy it first)");
+  adg_solver *s = &g_noalloc_solver[dev];
+  *s = adg_solver();
+  adg_status rc = setup_problem(phys, disc, as, (char *)g_scratch_ptr[dev], L, s->P);
+  if (rc != ADG_OK) return create_fail(rc, "problem set-up failed (unsupported combination or HIP error)");
+  s->stream = (hipStream_t)hip_stream;
+  s->noalloc_dev = dev;
+  g_noalloc_busy[dev] = true;
   *out = s;
   return ADG_OK;
 }
@@ -425,6 +473,11 @@ void adg_destroy(adg_solver *s) {
   destroy_graph(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   s->cap_stream = nullptr;
+  if (s->noalloc_dev >= 0) {
+    g_noalloc_busy[s->noalloc_dev] = false;   // the static solver and scratch are free again
+    s->noalloc_dev = -1;
+    return;
+  }
   delete s;
 }
 
