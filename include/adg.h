@@ -58,6 +58,7 @@ enum { ADG_HOST = 0, ADG_DEVICE = 1 };
 enum { ADG_KXRCF = 0, ADG_MINMOD = 1, ADG_ALL_CELLS = 2 };
 enum { ADG_AT_TEMPORAL = 0, ADG_AT_HYBRID = 1 };
 enum { ADG_SSPRK3 = 0, ADG_RK2 = 1, ADG_LSERK4 = 2 };
+enum { ADG_FP64 = 0, ADG_MIXED_FP32 = 1, ADG_MIXED_BF16 = 2 };
 
 /* Detailed reaction mechanism (Sec. 2: mass-action kinetics with species
    molecular weights W_i and molar production rates omega_i).  Reversible
@@ -119,6 +120,21 @@ typedef struct {
                              2N-storage form k <- A_s k + dt L(u), u <- u + B_s k (the LSERK
                              integrators of Sec. 3.1).  Stage s of step n reads the stage-s data of
                              past levels (Eq. (7)); batches support ADG_SSPRK3 only. */
+  int32_t precision;      /* ADG_FP64: every step in FP64.
+                             ADG_MIXED_FP32 (detailed model): the modal operators (interpolation to
+                             nodes and traces, LDG gradient, volume integral) in FP32 with FP32
+                             accumulation, on deviations from the element mean; the temperature
+                             Newton, transport, Arrhenius rates and equilibrium constants, interface
+                             fluxes, source projection and RK update in FP64.  Applied for N_p <= 3,
+                             where the error against the FP64 solution stays below a tenth of the
+                             discretisation error (4 % of it measured at N_p = 3); N_p = 4 keeps FP64
+                             operators (FP32 measured 11 times the discretisation error there).  The
+                             one-step model returns ADG_ERR_UNSUPPORTED.
+                             ADG_MIXED_BF16: ADG_ERR_UNSUPPORTED: BF16 (8-bit significand) operators
+                             would raise the FP32 path's operator error by about 2^16, past the
+                             discretisation error at every order of these workloads.
+                             In a batch the batch's precision applies: an instance passes ADG_FP64
+                             or the batch's precision (one-step instances run in FP64 in any batch). */
 } adg_discretization;
 
 /* Emulated PEs and delay model, Sec. 3.2 and 4. */
@@ -264,21 +280,14 @@ adg_status adg_create_noalloc(const adg_physics *phys, const adg_discretization 
  * footprint: adg_batch_add fails with ADG_ERR_NOMEM when no free region, slot
  * or element capacity is left, and succeeds again once removals free space.
  *
- * Precision (per batch, detailed-chemistry instances): ADG_FP64 runs every
- * step in FP64; ADG_MIXED_FP32 evaluates the modal operators (interpolation
- * to nodes and traces, LDG gradient, projection and lift) in FP32 with FP32
- * accumulation, while the temperature Newton inversion, the Arrhenius rates and
- * equilibrium constants, the interface fluxes and the RK update stay FP64 --
- * for N_p <= 3, where its error against the FP64 solution stays below a tenth
- * of the discretisation error (measured: 4 % of it at N_p = 3); N_p = 4
- * instances keep FP64 operators in a mixed batch (FP32 would be 11 times the
- * discretisation error there).  One-step instances always run in FP64.
+ * Precision (per batch, detailed-chemistry instances): ADG_FP64 or
+ * ADG_MIXED_FP32, as adg_discretization.precision describes (FP32 operators
+ * for N_p <= 3, FP64 ones for N_p = 4); ADG_MIXED_BF16 returns
+ * ADG_ERR_UNSUPPORTED.  One-step instances always run in FP64.
  *
  * Calls on one batch must not overlap.  adg_batch_add and adg_batch_remove
  * synchronise the batch's stream.
  * ---------------------------------------------------------------------- */
-enum { ADG_FP64 = 0, ADG_MIXED_FP32 = 1 };
-
 typedef struct adg_batch adg_batch;
 
 /* Header bytes of a batch with up to max_instances instances whose element

@@ -21,7 +21,8 @@ PERIODIC, TRANSMISSIVE = 0, 1
 RUSANOV, HLLC = 0, 1
 SYNC, CAA, SAA, SCHEDULE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
-FP64, MIXED_FP32 = 0, 1
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "mixed": MIXED_FP32, "bf16": MIXED_BF16}
 KXRCF, MINMOD, ALL_CELLS = 0, 1, 2
 AT_TEMPORAL, AT_HYBRID = 0, 1
 SSPRK3, RK2, LSERK4 = 0, 1, 2
@@ -60,7 +61,7 @@ class Discretization(C.Structure):
         ("bc", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
         ("indicator", C.c_int32), ("tvb_m", C.c_double),
         ("weno_gamma", C.c_double * 3), ("weno_eps", C.c_double),
-        ("dt", C.c_double), ("rk", C.c_int32),
+        ("dt", C.c_double), ("rk", C.c_int32), ("precision", C.c_int32),
     ]
 
 
@@ -169,6 +170,7 @@ class Problem:
         d.weno_eps = float(disc.get("weno_eps", 1e-6))
         d.dt = float(disc["dt"])
         d.rk = {"ssprk3": SSPRK3, "rk2": RK2, "lserk4": LSERK4}[disc.get("rk", "ssprk3")]
+        d.precision = PRECISIONS[disc.get("precision", "fp64")]
         a = Async()
         a.n_pe = int(asy["n_pe"])
         if asy.get("pe_offsets") is not None:
@@ -324,7 +326,7 @@ class Batch:
                  device: str = "cuda"):
         import torch
 
-        prec = {"fp64": FP64, "mixed": MIXED_FP32}[precision]
+        prec = PRECISIONS[precision]
         hdr = int(adg_batch_header_bytes(int(max_instances), int(max_elements)))
         if hdr == 0:
             raise AdgError(ADG_ERR_ARG, "invalid batch capacity")

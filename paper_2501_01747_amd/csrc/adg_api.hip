@@ -140,7 +140,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       a.advance = last;
       a.par = s->par;
       if (timer) timer(s, 0, true);
-      HIP_TRY(s, launch_ns_stage(M, s->ns_cfg, a, st));
+      HIP_TRY(s, launch_ns_stage(M, s->ns_cfg, a, s->P.disc.precision == ADG_MIXED_FP32, st));
       if (timer) timer(s, 0, false);
     }
   }
@@ -210,6 +210,7 @@ adg_status adg_create(const adg_physics *phys, const adg_discretization *disc, c
   Layout L;
   std::string why;
   if (!make_layout(phys, disc, as, L, &why)) return create_fail(ADG_ERR_ARG, why);
+  if (check_precision(phys, disc, &why) != ADG_OK) return create_fail(ADG_ERR_UNSUPPORTED, why);
   if (!device_workspace || ((uintptr_t)device_workspace & 255))
     return create_fail(ADG_ERR_ARG, "workspace must be a non-null 256-byte aligned device pointer");
   if (workspace_bytes < L.total) return create_fail(ADG_ERR_NOMEM, "workspace smaller than adg_workspace_bytes()");
@@ -228,6 +229,7 @@ adg_status adg_create_noalloc(const adg_physics *phys, const adg_discretization 
   Layout L;
   std::string why;
   if (!make_layout(phys, disc, as, L, &why)) return create_fail(ADG_ERR_ARG, why);
+  if (check_precision(phys, disc, &why) != ADG_OK) return create_fail(ADG_ERR_UNSUPPORTED, why);
   if (L.total > kScratchBytes)
     return create_fail(ADG_ERR_NOMEM, "problem needs " + std::to_string(L.total) + " bytes; the static scratch of "
                                           "adg_create_noalloc holds " + std::to_string(kScratchBytes));
@@ -404,6 +406,7 @@ adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
   // buffer (and the 2N register, whose old value the first stage does not read) and the
   // level's first-stage history, all of which the next step recomputes; the state is untouched
   NsArgs a = s->P.na;
+  const bool mixed = s->P.disc.precision == ADG_MIXED_FP32;
   a.rk = rk_stage(s->P.disc.rk, 0);
   const int bi = a.rk.two_n ? s->cur : 0, bo = a.rk.two_n ? (s->cur + 1) % 2 : 1;
   a.w0 = s->P.W[0];
@@ -419,13 +422,13 @@ adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
   HIP_TRY(s, hipEventCreate(&e0));
   HIP_TRY(s, hipEventCreate(&e1));
   for (int c = 0; c < kNsConfigs; ++c) {
-    for (int r = 0; r < 2; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));
+    for (int r = 0; r < 2; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, mixed, s->stream));
     t[c] = 1e30;
   }
   for (int round = 0; round < 3; ++round)
     for (int c = 0; c < kNsConfigs; ++c) {
       HIP_TRY(s, hipEventRecord(e0, s->stream));
-      for (int r = 0; r < n_reps; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, s->stream));
+      for (int r = 0; r < n_reps; ++r) HIP_TRY(s, launch_ns_stage(M, c, a, mixed, s->stream));
       HIP_TRY(s, hipEventRecord(e1, s->stream));
       HIP_TRY(s, hipEventSynchronize(e1));
       float ms = 0.0f;

@@ -295,6 +295,7 @@ adg_status adg_batch_create(int32_t max_instances, int64_t max_elements, int32_t
   if (!out) return ADG_ERR_ARG;
   *out = nullptr;
   if (max_instances < 1 || max_elements < 1) return ADG_ERR_ARG;
+  if (precision == ADG_MIXED_BF16) return ADG_ERR_UNSUPPORTED;   // beyond the error budget (adg.h)
   if (precision != ADG_FP64 && precision != ADG_MIXED_FP32) return ADG_ERR_ARG;
   if (!device_workspace || ((uintptr_t)device_workspace & 255)) return ADG_ERR_ARG;
   const long long max_tiles = tile_bound(max_instances, max_elements);
@@ -333,6 +334,9 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   if (count != (int64_t)L.E * L.V * L.M) return bfail(b, ADG_ERR_ARG, "state size mismatch");
   if (where != ADG_HOST && where != ADG_DEVICE) return bfail(b, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
   if (disc->rk != ADG_SSPRK3) return bfail(b, ADG_ERR_UNSUPPORTED, "batches run SSP-RK3 only");
+  if (disc->precision == ADG_MIXED_BF16) return bfail(b, ADG_ERR_UNSUPPORTED, "ADG_MIXED_BF16 is not supported");
+  if (disc->precision != ADG_FP64 && disc->precision != b->precision)
+    return bfail(b, ADG_ERR_ARG, "instance precision differs from the batch's");
   if (phys->model == ADG_DETAILED && phys->n_species > kNsMaxSpecies)
     return bfail(b, ADG_ERR_UNSUPPORTED, "batched detailed-chemistry instances take up to 9 species");
   int slot = -1;

@@ -678,12 +678,12 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   if (advance) advance_step(a.step, par, n, e0 == 0);
 }
 
-template <int M, int NS, int TE, int NTH>
+template <int M, int NS, int TE, int NTH, typename OpT>
 __global__ __launch_bounds__(NTH) void ns_stage_kernel(NsArgs a) {
   __shared__ NsLds<M, NS, TE> L;
   __shared__ NsMechT<NS> smech;
-  ns_tile<M, NS, double, NTH, TE>(a, a.ws, a.w0, a.wout, a.stage, a.advance, a.rk, a.kbuf,
-                                  xcd_item(blockIdx.x, gridDim.x) * TE, a.par, L, smech);
+  ns_tile<M, NS, OpT, NTH, TE>(a, a.ws, a.w0, a.wout, a.stage, a.advance, a.rk, a.kbuf,
+                               xcd_item(blockIdx.x, gridDim.x) * TE, a.par, L, smech);
 }
 
 // LDS of the batched kernel: room for the largest order it serves.
@@ -867,21 +867,21 @@ adg_status ns_build_mech(const adg_physics *ph, NsMechT<NSC> &hm) {
   return ADG_OK;
 }
 
-template <int M, int NS, int TE, int NTH>
+template <int M, int NS, int TE, int NTH, typename OpT>
 static hipError_t ns_launch(const NsArgs &a, hipStream_t s) {
   const int blocks = (a.E + TE - 1) / TE;
-  hipLaunchKernelGGL((ns_stage_kernel<M, NS, TE, NTH>), dim3(blocks), dim3(NTH), 0, s, a);
+  hipLaunchKernelGGL((ns_stage_kernel<M, NS, TE, NTH, OpT>), dim3(blocks), dim3(NTH), 0, s, a);
   return hipGetLastError();
 }
 
-template <int M, int NS>
+template <int M, int NS, typename OpT>
 static hipError_t ns_M(int cfg, const NsArgs &a, hipStream_t s) {
   switch (cfg) {
-    case 0: return ns_launch<M, NS, 8, 512>(a, s);
-    case 1: return ns_launch<M, NS, 8, 256>(a, s);
-    case 2: return ns_launch<M, NS, 4, 256>(a, s);
-    case 3: return ns_launch<M, NS, 4, 512>(a, s);
-    case 4: return ns_launch<M, NS, 8, 1024>(a, s);
+    case 0: return ns_launch<M, NS, 8, 512, OpT>(a, s);
+    case 1: return ns_launch<M, NS, 8, 256, OpT>(a, s);
+    case 2: return ns_launch<M, NS, 4, 256, OpT>(a, s);
+    case 3: return ns_launch<M, NS, 4, 512, OpT>(a, s);
+    case 4: return ns_launch<M, NS, 8, 1024, OpT>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -912,19 +912,20 @@ hipError_t launch_ns_batch(const NsArgs *insts, const int2 *tiles, int ntiles, i
 }
 
 template <int NS>
-static hipError_t ns_stage_ns(int M, int cfg, const NsArgs &a, hipStream_t s) {
+static hipError_t ns_stage_ns(int M, int cfg, const NsArgs &a, bool mixed, hipStream_t s) {
+  // FP32 operators for N_p <= 3 only (N_p = 4 keeps FP64 ones: error budget)
   switch (M) {
-    case 2: return ns_M<2, NS>(cfg, a, s);
-    case 3: return ns_M<3, NS>(cfg, a, s);
-    case 4: return ns_M<4, NS>(cfg, a, s);
-    case 5: return ns_M<5, NS>(cfg, a, s);
+    case 2: return mixed ? ns_M<2, NS, float>(cfg, a, s) : ns_M<2, NS, double>(cfg, a, s);
+    case 3: return mixed ? ns_M<3, NS, float>(cfg, a, s) : ns_M<3, NS, double>(cfg, a, s);
+    case 4: return mixed ? ns_M<4, NS, float>(cfg, a, s) : ns_M<4, NS, double>(cfg, a, s);
+    case 5: return ns_M<5, NS, double>(cfg, a, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, hipStream_t s) {
-  return ns_capacity(a.ns) == kNsMaxSpecies ? ns_stage_ns<kNsMaxSpecies>(M, cfg, a, s)
-                                            : ns_stage_ns<kNsWideSpecies>(M, cfg, a, s);
+hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, bool mixed, hipStream_t s) {
+  return ns_capacity(a.ns) == kNsMaxSpecies ? ns_stage_ns<kNsMaxSpecies>(M, cfg, a, mixed, s)
+                                            : ns_stage_ns<kNsWideSpecies>(M, cfg, a, mixed, s);
 }
 
 template adg_status ns_build_mech<kNsMaxSpecies>(const adg_physics *, NsMech &);

@@ -90,7 +90,8 @@ adg_status ns_build_mech(const adg_physics *ph, NsMechT<NSC> &hm);
 // Work decompositions of the single-problem stage kernel: (tile elements, threads)
 // = (8, 512), (8, 256), (4, 256), (4, 512), (8, 1024).
 constexpr int kNsConfigs = 5;
-hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, hipStream_t s);   // capacity from a.ns
+// Capacity from a.ns; mixed = FP32 modal operators (for N_p <= 3; N_p = 4 keeps FP64 ones).
+hipError_t launch_ns_stage(int M, int cfg, const NsArgs &a, bool mixed, hipStream_t s);
 // One stage for every (instance, tile) entry of `tiles` (device), at step counter parity par;
 // mixed = FP32 modal operators; max_m = the largest N_p + 1 among the listed instances; tiles
 // of tile_elems (4 or 8) elements.

@@ -141,6 +141,8 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
     return bad("unknown model");
   }
   if (d->rk != ADG_SSPRK3 && d->rk != ADG_RK2 && d->rk != ADG_LSERK4) return bad("unknown integrator");
+  if (d->precision != ADG_FP64 && d->precision != ADG_MIXED_FP32 && d->precision != ADG_MIXED_BF16)
+    return bad("unknown precision");
   if (d->limiter && d->indicator != ADG_KXRCF && d->indicator != ADG_MINMOD && d->indicator != ADG_ALL_CELLS)
     return bad("unknown indicator");
   if (as->at_stencil != ADG_AT_TEMPORAL && as->at_stencil != ADG_AT_HYBRID) return bad("unknown at_stencil");
@@ -200,6 +202,18 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   return true;
 }
 
+
+adg_status check_precision(const adg_physics *ph, const adg_discretization *d, std::string *why) {
+  if (d->precision == ADG_MIXED_BF16) {
+    if (why) *why = "ADG_MIXED_BF16 is not supported: BF16 operators would exceed the error budget";
+    return ADG_ERR_UNSUPPORTED;
+  }
+  if (d->precision == ADG_MIXED_FP32 && ph->model != ADG_DETAILED) {
+    if (why) *why = "the one-step model runs in FP64 only";
+    return ADG_ERR_UNSUPPORTED;
+  }
+  return ADG_OK;
+}
 
 adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc, const adg_async *as, char *base,
                          const Layout &L, Problem &P) {

@@ -45,6 +45,9 @@ struct Problem {
 // Validates a problem and computes the layout of its device region (bytes in L.total).
 bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_async *as, Layout &L,
                  std::string *why);
+// ADG_ERR_UNSUPPORTED for precisions a single problem cannot run (MIXED_BF16; MIXED_FP32 with
+// the one-step model), with the reason in *why.
+adg_status check_precision(const adg_physics *ph, const adg_discretization *d, std::string *why);
 // Places the problem at `base` (256-byte aligned, L.total bytes), uploads its
 // constant data and fills the kernel arguments.
 adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc, const adg_async *as, char *base,

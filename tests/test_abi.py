@@ -101,3 +101,24 @@ def test_argument_validation():
         bad[2, 1] = bad_value
         c = dict(case, **{"async": dict(case["async"], mode="schedule", L=3, schedule=bad)})
         assert adg.Problem(c).workspace_bytes() == 0, bad_value
+
+
+def test_precision_checks_before_any_device_work():
+    """MIXED_BF16 is refused (error budget), and so is MIXED_FP32 for the one-step model; both before
+    the workspace is looked at (no GPU needed)."""
+    import ctypes as C
+
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    case, _ = gen.case_c0(E=64, n_pe=2)
+    mech = gen.synthetic_mechanism(1747, dt=1e-10)
+    ign, _ = gen.case_c1(E=16, n_pe=2, mech=mech, Lx=0.01 * 16 / 2048)
+    for c, prec, code in ((ign, "bf16", adg.ADG_ERR_UNSUPPORTED), (case, "mixed", adg.ADG_ERR_UNSUPPORTED),
+                          (case, "bf16", adg.ADG_ERR_UNSUPPORTED)):
+        c = dict(c, disc=dict(c["disc"], precision=prec))
+        p = adg.Problem(c)
+        h = C.c_void_p()
+        rc = adg.adg_create(C.byref(p.phys), C.byref(p.disc), C.byref(p.asyn), None, 0, None, C.byref(h))
+        assert rc == code, (prec, rc)
+        assert b"supported" in adg.adg_last_error(None) or b"FP64" in adg.adg_last_error(None)

@@ -245,3 +245,28 @@ def test_batch_refuses_more_than_nine_species(adg):
         b.add(case, w0)
     assert ei.value.code == adg.ADG_ERR_UNSUPPORTED
     b.close()
+
+
+@pytest.mark.parametrize("order_p", [1, 2, 3, 4])
+def test_single_problem_mixed_precision(adg, orc, mech, order_p):
+    """precision = MIXED_FP32 on one problem: FP32 operators for N_p <= 3, within the mixed path's
+    stated 1e-8 per variable of the FP64 oracle; N_p = 4 keeps FP64 operators, so it is the FP64
+    run bit for bit."""
+    cfl = {1: 0.1, 2: 0.08, 3: 0.04, 4: 0.02}[order_p]
+    case, w0 = gen.case_c1(E=56, order_p=order_p, n_pe=7, mech=mech, cfl=cfl, Lx=0.01 * 56 / 2048)
+    mixed = dict(case, disc=dict(case["disc"], precision="mixed"))
+    s = adg.Solver(mixed)
+    s.set_state(w0)
+    s.step(15)
+    w = s.state()
+    s.close()
+    ref = orc.run(case, w0, 15)
+    err = float(np.max(var_errors(w, ref)))
+    print(f"[mixed-single] Np={order_p} err {err:.2e}", flush=True)
+    if order_p == 4:
+        s = adg.Solver(case)
+        s.set_state(w0)
+        s.step(15)
+        np.testing.assert_array_equal(w, s.state())
+    else:
+        assert 0 < err < 1e-8
