@@ -314,7 +314,7 @@ def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, preci
                              "p99_latency_s": float(np.percentile(lat, 99))}
     out.update({"failed_by_kind_order": fails, "latency_by_kind": by_kind, "rate_req_per_s": rate, "heap_gib": heap_gib, "slots": slots, "chunk": chunk,
                 "precision": precision, "rounds": srv.rounds, "max_active": srv.max_active,
-                "input_generation_s": t_gen})
+                "input_generation_s": t_gen, "loop_seconds": srv.time_in})
     return out
 
 
@@ -353,7 +353,7 @@ def served_short(n_req: int, rate: float, precision: str):
     out = bench_serve(n_req, rate, 16.0, 1024, 10, precision)
     keep = ("requests", "completed_ok", "failed", "p50_latency_s", "p99_latency_s", "mean_latency_s", "mean_queue_s",
             "makespan_s", "requests_per_s", "dof_updates_per_s", "latency_by_kind", "rate_req_per_s", "max_active",
-            "rounds", "precision")
+            "rounds", "precision", "loop_seconds")
     return {k: out[k] for k in keep}
 
 

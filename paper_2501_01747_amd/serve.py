@@ -71,6 +71,9 @@ class Server:
         self.nomem_code = nomem_code
         self.rounds = 0
         self.max_active = 0
+        # wall seconds of the loop's parts: enqueueing steps, waiting for them (poll), copying
+        # finished states out and releasing them, admitting (placement and upload)
+        self.time_in = {"enqueue": 0.0, "wait": 0.0, "retire": 0.0, "admit": 0.0}
 
     def run(self, requests: list[Request]) -> list[Result]:
         arrivals = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
@@ -83,6 +86,7 @@ class Server:
             now = self.clock() - t0
             while arrivals and arrivals[0].arrival <= now:
                 waiting.append(arrivals.popleft())
+            t_adm0 = self.clock()
             while waiting:
                 r = waiting[0]
                 try:
@@ -96,18 +100,24 @@ class Server:
                     continue
                 waiting.popleft()
                 active[slot] = [r, self.clock() - t0, 0]
+            self.time_in["admit"] += self.clock() - t_adm0
             self.max_active = max(self.max_active, len(active))
             if not active:
                 if arrivals:
                     self.sleep(max(0.0, arrivals[0].arrival - (self.clock() - t0)))
                 continue
             n = max(1, min(self.chunk, min(a[0].steps - a[2] for a in active.values())))
+            t1 = self.clock()
             self.batch.step(n)
+            t2 = self.clock()
             self.rounds += 1
             for a in active.values():
                 a[2] = min(a[0].steps, a[2] + n)
             steps_now, errs = self.batch.poll()
-            t_done = self.clock() - t0
+            t3 = self.clock()
+            self.time_in["enqueue"] += t2 - t1
+            self.time_in["wait"] += t3 - t2
+            t_done = t3 - t0
             for slot in list(active):
                 r, t_adm, _ = active[slot]
                 if errs[slot] or steps_now[slot] >= r.steps:
@@ -119,6 +129,7 @@ class Server:
                     del active[slot]
                     done.append(Result(r.rid, r.arrival, t_adm, t_done, int(steps_now[slot]),
                                        request_dof(r.case), ok, state))
+            self.time_in["retire"] += self.clock() - t3
         return sorted(done, key=lambda x: x.rid)
 
 
