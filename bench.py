@@ -226,6 +226,28 @@ def build_c3_batch(precision: str, n_inst: int = 4096):
     return b, cases
 
 
+def batch_decompositions(steps: int, precision: str):
+    """Time every work decomposition of the batched kernel on the batched workload (the
+    autotuner's candidates): HIP events over `steps` plain steps each, after one untimed step."""
+    import torch
+
+    b, cases = build_c3_batch(precision)
+    out = {}
+    for cfg in range(2):
+        b.set_decomposition(cfg)
+        b.step(1)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(b.stream)
+        b.step(steps)
+        ev1.record(b.stream)
+        torch.cuda.synchronize()
+        out[cfg] = ev0.elapsed_time(ev1) / (3 * steps)
+        print(json.dumps({"decomposition": cfg, "tile_elems": (8, 4)[cfg], "launch_ms": out[cfg]}), flush=True)
+    b.close()
+    return out
+
+
 def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed", n_inst: int = 4096,
                   cpu: bool = False):
     """The batched ignition workload: n_inst instances (element counts log-uniform in
@@ -440,6 +462,8 @@ def main():
     ap.add_argument("--served-requests", type=int, default=160,
                     help="default line: requests of the short served stream (0 = skip)")
     ap.add_argument("--no-hbm-points", action="store_true", help="default line: skip the HBM-bound Euler points")
+    ap.add_argument("--batch-decompositions", action="store_true",
+                    help="time every work decomposition of the batched kernel (no benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -452,6 +476,9 @@ def main():
     from workloads import gen
 
     torch.cuda.set_device(0)
+    if args.batch_decompositions:
+        batch_decompositions(args.steps, args.precision)
+        return
     if args.workload == "c3" and not args.pmc_probe:
         out = bench_batched(args.steps, args.warmup, args.graph, args.precision, cpu=not args.no_cpu_baseline)
         out.update({"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "scaling": "weak",

@@ -67,7 +67,8 @@ enum { ADG_FP64 = 0, ADG_MIXED_FP32 = 1, ADG_MIXED_BF16 = 2 };
    7-coefficient polynomials, one temperature range.  Transport: viscosity
    mu = mu_ref (T/T_ref)^mu_exp, conductivity k = mu cp/Pr, unit Lewis number.
    All arrays are read during adg_create only.  Limits of the kernels (beyond
-   them ADG_ERR_UNSUPPORTED): 1..16 species, 1..32 reactions, at most two
+   them ADG_ERR_UNSUPPORTED): 1..16 species (9 in batches), 1..32 reactions
+   (24 in batches), at most two
    molecules on either side of a reaction and at most four species whose net
    coefficient is nonzero in one reaction (no third bodies). */
 typedef struct adg_mechanism {
@@ -342,9 +343,15 @@ adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int6
 
 /* Choose the tile size (8 or 4 elements) of the batched detailed-chemistry
    kernel by timing n_reps launches of its first RK stage for the current batch
-   (state unchanged, as for adg_autotune); kept until the next call.  *choice
+   (state unchanged, as for adg_autotune; three interleaved rounds, each
+   candidate's fastest counting); kept until the next call.  *choice
    (optional): 0 = 8 elements, 1 = 4.  Synchronises. */
 adg_status adg_batch_autotune(adg_batch *b, int32_t n_reps, int32_t *choice);
+
+/* Use work decomposition `config` of the batched detailed-chemistry kernel
+   (adg_batch_autotune's numbering, 0 or 1; ADG_ERR_ARG otherwise) from the next
+   step on.  Results do not depend on it beyond the order of floating-point sums. */
+adg_status adg_batch_set_kernel_config(adg_batch *b, int32_t config);
 
 /* Number of admitted instances. */
 int32_t adg_batch_active(const adg_batch *b);

@@ -108,6 +108,7 @@ _sig = {
     "adg_batch_set_graph": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_int64), C.c_int32]),
     "adg_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_int32)]),
+    "adg_batch_set_kernel_config": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_batch_active": (C.c_int32, [C.c_void_p]),
     "adg_batch_free_bytes": (C.c_int64, [C.c_void_p]),
     "adg_batch_destroy": (None, [C.c_void_p]),
@@ -404,6 +405,10 @@ class Batch:
         c = C.c_int32(0)
         self._check(adg_batch_autotune(self.h, int(n_reps), C.byref(c)))
         return c.value
+
+    def set_decomposition(self, config: int):
+        """Use the batched kernel's work decomposition `config` (autotune's numbering)."""
+        self._check(adg_batch_set_kernel_config(self.h, int(config)))
 
     def profile(self, n_steps: int) -> dict:
         k = len(BATCH_PROFILE_CLASSES)

@@ -339,6 +339,8 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
     return bfail(b, ADG_ERR_ARG, "instance precision differs from the batch's");
   if (phys->model == ADG_DETAILED && phys->n_species > kNsMaxSpecies)
     return bfail(b, ADG_ERR_UNSUPPORTED, "batched detailed-chemistry instances take up to 9 species");
+  if (phys->model == ADG_DETAILED && phys->mech && phys->mech->n_reactions > kNsBatchReactions)
+    return bfail(b, ADG_ERR_UNSUPPORTED, "batched detailed-chemistry instances take up to 24 reactions");
   int slot = -1;
   for (int i = 0; i < b->max_inst; ++i)
     if (!b->slots[i].used) { slot = i; break; }
@@ -552,42 +554,54 @@ adg_status adg_batch_profile(adg_batch *b, int32_t n_steps, double *ms_out, int6
 adg_status adg_batch_autotune(adg_batch *b, int32_t n_reps, int32_t *choice) {
   if (!b || n_reps < 1) return ADG_ERR_ARG;
   static const int kTiles[2] = {8, 4};
-  double best_ms = 0.0;
-  int best = 0;
+  double t[2] = {1e30, 1e30};
   bool any = false;
-  for (int c = 0; c < 2; ++c) {
-    b->tile_elems = kTiles[c];
-    b->dirty = true;
-    adg_status rc = prepare(b);
-    if (rc != ADG_OK) return rc;
-    const Group *g = nullptr;
-    for (const Group &x : b->groups)
-      if (x.kind == 0) g = &x;
-    if (!g) break;   // no detailed-chemistry instance: nothing to choose
-    any = true;
-    // stage-0 launches only: they read w^n and write the first stage buffer and the
-    // level's stage-0 history, which the next step recomputes; the state is untouched
-    hipEvent_t e0, e1;
-    BHIP(b, hipEventCreate(&e0));
-    BHIP(b, hipEventCreate(&e1));
-    BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->par, b->precision == ADG_MIXED_FP32, g->M,
-                            b->tile_elems, b->stream));   // warm-up
-    BHIP(b, hipEventRecord(e0, b->stream));
-    for (int r = 0; r < n_reps; ++r)
+  // both candidates timed in three interleaved rounds, each keeping its fastest round
+  for (int round = 0; round < 3; ++round) {
+    for (int c = 0; c < 2; ++c) {
+      b->tile_elems = kTiles[c];
+      b->dirty = true;
+      adg_status rc = prepare(b);
+      if (rc != ADG_OK) return rc;
+      const Group *g = nullptr;
+      for (const Group &x : b->groups)
+        if (x.kind == 0) g = &x;
+      if (!g) break;   // no detailed-chemistry instance: nothing to choose
+      any = true;
+      // stage-0 launches only: they read w^n and write the first stage buffer and the
+      // level's stage-0 history, which the next step recomputes; the state is untouched
+      hipEvent_t e0, e1;
+      BHIP(b, hipEventCreate(&e0));
+      BHIP(b, hipEventCreate(&e1));
       BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->par, b->precision == ADG_MIXED_FP32, g->M,
-                              b->tile_elems, b->stream));
-    BHIP(b, hipEventRecord(e1, b->stream));
-    BHIP(b, hipEventSynchronize(e1));
-    float ms = 0.0f;
-    BHIP(b, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (c == 0 || ms < best_ms) { best_ms = ms; best = c; }
+                              b->tile_elems, b->stream));   // warm-up
+      BHIP(b, hipEventRecord(e0, b->stream));
+      for (int r = 0; r < n_reps; ++r)
+        BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g->off, g->n, 0, b->par, b->precision == ADG_MIXED_FP32, g->M,
+                                b->tile_elems, b->stream));
+      BHIP(b, hipEventRecord(e1, b->stream));
+      BHIP(b, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      t[c] = std::min(t[c], (double)ms);
+    }
+    if (!any) break;
   }
-  b->tile_elems = kTiles[any ? best : 0];
+  const int best = any && t[1] < t[0] ? 1 : 0;
+  b->tile_elems = kTiles[best];
   b->dirty = true;
-  if (choice) *choice = any ? best : 0;
+  if (choice) *choice = best;
   return prepare(b);
+}
+
+adg_status adg_batch_set_kernel_config(adg_batch *b, int32_t config) {
+  if (!b) return ADG_ERR_ARG;
+  if (config < 0 || config > 1) return bfail(b, ADG_ERR_ARG, "no such work decomposition");
+  b->tile_elems = config ? 4 : 8;
+  b->dirty = true;
+  return ADG_OK;
 }
 
 int32_t adg_batch_active(const adg_batch *b) { return b ? b->active : -1; }

@@ -73,14 +73,14 @@ __device__ __forceinline__ bool newton_T(const double (&c)[6], double T0, double
 }
 
 // LDS arena of one tile.
-template <int M, int NS, int TE>
+template <int M, int NS, int TE, int NRC = kNsMaxReactions>
 struct NsLds {
   static constexpr int V = 3 + NS, Q = M;
   static constexpr int NH = TE + 4;   // tile + 2 halo elements per side; local l <-> element e0 - 2 + l
   static constexpr int NF = TE + 3;   // faces e0-1 .. e0+TE+1; local fl <-> face e0 - 1 + fl
   static constexpr int NQ = TE + 2;   // gradients of elements e0-1 .. e0+TE; local lq <-> element e0 - 1 + lq
   static constexpr int NN = TE * Q;   // quadrature nodes of the tile; node p <-> element p / Q, node p % Q
-  static constexpr int NR = kNsMaxReactions;
+  static constexpr int NR = NRC;   // reaction capacity of the rate storage
   // rows padded to an odd number of doubles: the lanes of a point group read or write one
   // row each (their species) at the same column, and rows an even number of doubles apart
   // would put several of them on the same LDS banks
@@ -127,13 +127,13 @@ struct NsLds {
 // traces are likewise mode 0 plus the FP32 sum of the higher modes.
 // LPP: lanes per point of the point phase (0: the workgroup's lanes spread over
 // 32 or 64 point slots).
-template <int M, int NS, typename OpT, int NTH, int TE, int LPP = 0>
+template <int M, int NS, typename OpT, int NTH, int TE, int LPP = 0, int NRC = kNsMaxReactions>
 __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restrict__ ws, const double *w0,
                                         double *wout, int stage, int advance, const RkStage rk, double *kbuf,
                                         int e0, int par,
-                                        NsLds<M, NS, TE> &Ls, NsMechT<NS> &smech) {
+                                        NsLds<M, NS, TE, NRC> &Ls, NsMechT<NS> &smech) {
   constexpr int V = 3 + NS, Q = M;
-  using Lds = NsLds<M, NS, TE>;
+  using Lds = NsLds<M, NS, TE, NRC>;
   constexpr int NH = Lds::NH, NF = Lds::NF, NQ = Lds::NQ, NN = Lds::NN;
   constexpr int NT = 2 * (TE + 1);  // face traces; trace pp <-> face e0 + pp/2, side pp%2
   auto &sW = Ls.sW;
@@ -370,7 +370,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     if ((t & ~63) / LP < NP) {
       const int k = t % LP;
       const int p = min(t / LP, NP - 1);          // spare groups redo the last point and write nothing
-      const bool writer = t / LP < NP;
+      bool writer = t / LP < NP;
       const bool node = p < NN;
       int qn = 0, ff = 0, side = 0, es = 0, l, lq;
       if (node) {
@@ -389,8 +389,9 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
         l = ff + 1 + es;
         lq = ff + es;                             // gradient slot; its faces are lq and lq + 1
       }
-      // points of a transmissive mesh past its last element carry no state (never read)
-      const bool valid = periodic || (node ? p / Q < nloc : e0 + ff <= E);
+      // points of a transmissive mesh past its last element carry no state: nothing is stored
+      // for them and they do not enter the error flag
+      writer = writer && (periodic || (node ? p / Q < nloc : e0 + ff <= E));
       const bool pe = !node && sI[ff + 1] >= 0;
       // value, gradient and synchronous gradient (PE-interface traces) of variable v
       auto eval = [&](int v, double &x, double &d, double &ds) {
@@ -465,7 +466,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const double cp = cv + Rmix;
       const double pr = wr * Rmix * T;
       const double snd = sqrt(cp / cv * pr * rho_inv);
-      if (writer && valid) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
+      if (writer) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
       double g0 = wm, g1 = wm * u + pr, g2 = u * (we + pr);
       double gs1 = g1, gs2 = g2;
       double gy[NO], gsy[NO];
@@ -686,30 +687,31 @@ __global__ __launch_bounds__(NTH) void ns_stage_kernel(NsArgs a) {
                                xcd_item(blockIdx.x, gridDim.x) * TE, a.par, L, smech);
 }
 
-// LDS of the batched kernel: room for the largest order it serves.
+// LDS of the batched kernel: room for the largest order it serves, rates of up to
+// kNsBatchReactions reactions.
 template <int MMAX, int TE>
 union NsBatchLds;
 template <int TE>
 union NsBatchLds<2, TE> {
-  NsLds<2, kNsMaxSpecies, TE> m2;
+  NsLds<2, kNsMaxSpecies, TE, kNsBatchReactions> m2;
 };
 template <int TE>
 union NsBatchLds<3, TE> {
-  NsLds<2, kNsMaxSpecies, TE> m2;
-  NsLds<3, kNsMaxSpecies, TE> m3;
+  NsLds<2, kNsMaxSpecies, TE, kNsBatchReactions> m2;
+  NsLds<3, kNsMaxSpecies, TE, kNsBatchReactions> m3;
 };
 template <int TE>
 union NsBatchLds<4, TE> {
-  NsLds<2, kNsMaxSpecies, TE> m2;
-  NsLds<3, kNsMaxSpecies, TE> m3;
-  NsLds<4, kNsMaxSpecies, TE> m4;
+  NsLds<2, kNsMaxSpecies, TE, kNsBatchReactions> m2;
+  NsLds<3, kNsMaxSpecies, TE, kNsBatchReactions> m3;
+  NsLds<4, kNsMaxSpecies, TE, kNsBatchReactions> m4;
 };
 template <int TE>
 union NsBatchLds<5, TE> {
-  NsLds<2, kNsMaxSpecies, TE> m2;
-  NsLds<3, kNsMaxSpecies, TE> m3;
-  NsLds<4, kNsMaxSpecies, TE> m4;
-  NsLds<5, kNsMaxSpecies, TE> m5;
+  NsLds<2, kNsMaxSpecies, TE, kNsBatchReactions> m2;
+  NsLds<3, kNsMaxSpecies, TE, kNsBatchReactions> m3;
+  NsLds<4, kNsMaxSpecies, TE, kNsBatchReactions> m4;
+  NsLds<5, kNsMaxSpecies, TE, kNsBatchReactions> m5;
 };
 
 // Batched stage kernel: one workgroup per (instance, tile) entry of the work
@@ -719,8 +721,10 @@ union NsBatchLds<5, TE> {
 // only low orders.  An instance whose step count has reached its target is
 // skipped by all of its workgroups (its first tile carries the count over to
 // the other parity at the last stage).
+// At most 128 VGPRs (four wavefronts per SIMD): with four tiles' LDS per CU, more registers would
+// leave only three of them resident (measured: 24 % slower at 132 VGPRs).
 template <typename OpT, int MMAX, int TE>
-__global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *__restrict__ insts,
+__global__ __launch_bounds__(kThreadsBatch, 4) void ns_batch_kernel(const NsArgs *__restrict__ insts,
                                                             const int2 *__restrict__ tiles, int stage, int par) {
   __shared__ NsBatchLds<MMAX, TE> L;
   __shared__ NsMech smech;
@@ -737,18 +741,20 @@ __global__ __launch_bounds__(kThreadsBatch) void ns_batch_kernel(const NsArgs *_
   double *wout = a.W[out_buf];
   const int M = a.M;
   const RkStage rk = rk_stage(ADG_SSPRK3, stage);   // batches run SSP-RK3
+  constexpr int LP = kBatchLanesPerPoint, NR = kNsBatchReactions, NTH = kThreadsBatch;
+  constexpr int NS = kNsMaxSpecies;
   if (M == 2) {
-    ns_tile<2, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m2, smech);
+    ns_tile<2, NS, OpT, NTH, TE, LP, NR>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m2, smech);
   } else if constexpr (MMAX >= 3) {
     if (M == 3) {
-      ns_tile<3, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m3, smech);
+      ns_tile<3, NS, OpT, NTH, TE, LP, NR>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m3, smech);
     } else if constexpr (MMAX >= 4) {
       if (M == 4) {
-        ns_tile<4, kNsMaxSpecies, OpT, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m4, smech);
+        ns_tile<4, NS, OpT, NTH, TE, LP, NR>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m4, smech);
       } else if constexpr (MMAX >= 5) {
         // N_p = 4 keeps FP64 operators in a mixed batch: FP32 rounding would exceed a tenth of the
         // discretisation error there
-        ns_tile<5, kNsMaxSpecies, double, kThreadsBatch, TE, kBatchLanesPerPoint>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m5, smech);
+        ns_tile<5, NS, double, NTH, TE, LP, NR>(a, ws, w0, wout, stage, stage == 2, rk, nullptr, tl.y, par, L.m5, smech);
       }
     }
   }

@@ -12,6 +12,7 @@ namespace adg {
 constexpr int kNsMaxSpecies = 9;      // the batched kernels, and single problems with Ns <= 9
 constexpr int kNsWideSpecies = 16;    // single problems with 9 < Ns <= 16
 constexpr int kNsMaxReactions = 32;
+constexpr int kNsBatchReactions = 24;   // reactions of a batched mechanism (rate storage of the batched kernel)
 inline int ns_capacity(int n_species) { return n_species <= kNsMaxSpecies ? kNsMaxSpecies : kNsWideSpecies; }
 
 // Mechanism in device memory, read with wave-uniform indices (scalar loads), for kernels of

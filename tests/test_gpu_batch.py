@@ -324,3 +324,19 @@ def test_batch_autotune_keeps_the_state(adg, orc, mech):
         o.step(6)
         assert float(np.max(var_errors(b.state(sl), o.state()))) < 1e-10
     b.close()
+
+
+@pytest.mark.parametrize("choice", [0, 1])
+def test_every_batched_decomposition_matches_the_oracle(adg, orc, mech, choice):
+    """The batched kernel's work decompositions (tiles of 8 or 4 elements), forced, against the
+    oracle."""
+    cases = mixed_cases(mech)[:4]
+    b = make_batch(adg, cases)
+    slots = [b.add(c, w) for c, w in cases]
+    b.set_decomposition(choice)
+    b.step(6)
+    for (c, w), sl in zip(cases, slots):
+        o = orc.OracleSolver(c, w, 7)
+        o.step(6)
+        check(b.state(sl), o.state(), c, 1e-10, f"decomposition {choice}")
+    b.close()
