@@ -66,6 +66,11 @@ struct Tables {
   double WG[kMaxQ][kMaxM];  // w_q P_j'(xi_q)
   double WB[kMaxQ][kMaxM];  // w_q P_j(xi_q)
   double Dm[kMaxM][kMaxM];  // int P_j' P_k dxi (LDG volume term)
+  // the LDG gradient at a point of row r (nodes r < M, then xi = +1, xi = -1) is
+  // (GA_r w*_R - GB_r w*_L - sum_k GD_rk w_k)/dx:  GA_r = sum_j (2j+1) P_j(xi_r),
+  // GB_r = sum_j (-1)^j (2j+1) P_j(xi_r), GD_rk = sum_j (2j+1) P_j(xi_r) Dm_jk
+  double GD[kMaxQ + 2][kMaxM];
+  double GA[kMaxQ + 2], GB[kMaxQ + 2];
 };
 
 struct OneStep {

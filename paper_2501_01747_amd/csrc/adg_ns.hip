@@ -78,34 +78,50 @@ struct NsLds {
   static constexpr int V = 3 + NS, Q = M;
   static constexpr int NH = TE + 4;   // tile + 2 halo elements per side; local l <-> element e0 - 2 + l
   static constexpr int NF = TE + 3;   // faces e0-1 .. e0+TE+1; local fl <-> face e0 - 1 + fl
-  static constexpr int NQ = TE + 2;   // gradients of elements e0-1 .. e0+TE; local lq <-> element e0 - 1 + lq
   static constexpr int NN = TE * Q;   // quadrature nodes of the tile; node p <-> element p / Q, node p % Q
+  static constexpr int NP = NN + 2 * (TE + 1);   // points: the nodes, then the face traces
   static constexpr int NR = NRC;   // reaction capacity of the rate storage
   // rows padded to an odd number of doubles: the lanes of a point group read or write one
   // row each (their species) at the same column, and rows an even number of doubles apart
   // would put several of them on the same LDS banks
-  static constexpr int NHP = NH | 1, NQP = NQ | 1, NNP = NN | 1;
+  static constexpr int NHP = NH | 1, NNP = NN | 1, NPP = NP | 1;
   double sW[V * M][NHP];
   double sTm[V][NHP], sTp[V][NHP];
   double sG[V][NNP];
-  double sS[NS][NNP];
-  double sT[NN];
-  double sConc[NS][NNP], sGRT[NS][NNP];
-  // the reaction rates of the chemistry phase reuse the storage of the central traces and
-  // LDG gradients, which are dead once the point phase has ended
+  // the central traces are last read by the point phase (synchronous gradient traces); the
+  // species production takes their place
   union {
     struct {
       double sWc[V][NF], sWa[V][NF];
-      double sQ[V * M][NQP];
-    } early;
+    } c;
+    double sS[NS][NNP];
+  } u0;
+  // the species sums of the mixture energy polynomial are read by the mixture chain before the
+  // concentrations and Gibbs energies are formed
+  union {
+    double sMix[8][NPP];   // sums over species of Y_i/rho-weighted coefficients; row 7: e*
+    struct {
+      double sConc[NS][NNP], sGRT[NS][NNP];
+    } g;
+  } u1;
+  // values and gradients at the points and the per-point results of the mixture chain are dead
+  // once the point phase has ended: the reaction rates of the chemistry phase take their place
+  union {
+    struct {
+      double sX[V][NNP];    // values at the nodes (those at the face traces are sTm / sTp)
+      double sDx[V][NPP];   // gradients at the points
+      double sRinv[NPP], sU[NPP], sRhoD[NPP], sKc[NPP];   // 1/rho, u, rho D, kappa / c_v
+    } p;
     double sRate[NR][NN];
   } u;
   double sGf[2][V][TE + 1], sGs[2][V][TE + 1];
   double sLam[2][TE + 1];
-  static constexpr int NP = NN + 2 * (TE + 1);   // points: the nodes, then the face traces
-  double sLnT[NN], sInvT[NN];
+  double sTT[NPP], sLnT[NPP], sInvT[NPP];
   double sF[V][TE + 1], sFat[V][TE + 1];
-  double sB[Q][M], sWG[Q][M], sWB[Q][M], sD[M][M];   // tables, indexed at run time
+  // tables, indexed at run time: nodal values, volume and source projections, gradients at the
+  // points (rows: the nodes, then xi = +1 and xi = -1)
+  double sB[Q][M], sWG[Q][M], sWB[Q][M];
+  double sGD[Q + 2][M], sGA[Q + 2], sGB[Q + 2];
   int sI[NF], sK[NF];
 };
 
@@ -134,19 +150,25 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
                                         NsLds<M, NS, TE, NRC> &Ls, NsMechT<NS> &smech) {
   constexpr int V = 3 + NS, Q = M;
   using Lds = NsLds<M, NS, TE, NRC>;
-  constexpr int NH = Lds::NH, NF = Lds::NF, NQ = Lds::NQ, NN = Lds::NN;
+  constexpr int NH = Lds::NH, NF = Lds::NF, NN = Lds::NN;
   constexpr int NT = 2 * (TE + 1);  // face traces; trace pp <-> face e0 + pp/2, side pp%2
   auto &sW = Ls.sW;
   auto &sTm = Ls.sTm;
   auto &sTp = Ls.sTp;
-  auto &sWc = Ls.u.early.sWc;
-  auto &sWa = Ls.u.early.sWa;
-  auto &sQ = Ls.u.early.sQ;
+  auto &sWc = Ls.u0.c.sWc;
+  auto &sWa = Ls.u0.c.sWa;
+  auto &sS = Ls.u0.sS;
+  auto &sX = Ls.u.p.sX;
+  auto &sDx = Ls.u.p.sDx;
+  auto &sRinv = Ls.u.p.sRinv;
+  auto &sU = Ls.u.p.sU;
+  auto &sRhoD = Ls.u.p.sRhoD;
+  auto &sKc = Ls.u.p.sKc;
+  auto &sTT = Ls.sTT;
   auto &sG = Ls.sG;
-  auto &sS = Ls.sS;
-  auto &sT = Ls.sT;
-  auto &sConc = Ls.sConc;
-  auto &sGRT = Ls.sGRT;
+  auto &sMix = Ls.u1.sMix;
+  auto &sConc = Ls.u1.g.sConc;
+  auto &sGRT = Ls.u1.g.sGRT;
   auto &sRate = Ls.u.sRate;
   auto &sGf = Ls.sGf;
   auto &sGs = Ls.sGs;
@@ -158,7 +180,9 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   auto &sB = Ls.sB;
   auto &sWG = Ls.sWG;
   auto &sWB = Ls.sWB;
-  auto &sD = Ls.sD;
+  auto &sGD = Ls.sGD;
+  auto &sGA = Ls.sGA;
+  auto &sGB = Ls.sGB;
   auto &sI = Ls.sI;
   auto &sK = Ls.sK;
   constexpr int NP = Lds::NP;
@@ -243,18 +267,63 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       sI[t] = fi;
       sK[t] = fi >= 0 ? eff_delay(a.dl, n, fi) : 0;
     }
-    for (int idx = t; idx < Q * M; idx += NTH) {
+    for (int idx = t; idx < (Q + 2) * M; idx += NTH) {
       const int qn = idx / M, j = idx % M;
-      sB[qn][j] = a.tb.B[qn][j];
-      sWG[qn][j] = a.tb.WG[qn][j];
-      sWB[qn][j] = a.tb.WB[qn][j];
-      if (qn < M) sD[qn][j] = a.tb.Dm[qn][j];
+      if (qn < Q) {
+        sB[qn][j] = a.tb.B[qn][j];
+        sWG[qn][j] = a.tb.WG[qn][j];
+        sWB[qn][j] = a.tb.WB[qn][j];
+      }
+      sGD[qn][j] = a.tb.GD[qn][j];
+      if (j == 0) {
+        sGA[qn] = a.tb.GA[qn];
+        sGB[qn] = a.tb.GB[qn];
+      }
     }
   }
   __syncthreads();
   const int nr = mk->nr;
 
-  // 1. traces of w; meanwhile the AT combinations of past levels (Eq. (7)) of the central
+  // face trace point p >= NN: face e0 + ff, side (0: the element left of the face, at its
+  // xi = +1) and the side es whose element is evaluated (at a transmissive end the ghost side
+  // takes the interior's trace and gradient trace)
+  auto trace_side = [&](int p, int &ff, int &side, int &es) {
+    const int pp = p - NN;
+    ff = pp >> 1;
+    side = pp & 1;
+    es = side;
+    if (!periodic) {
+      if (e0 + ff == 0 && side == 0) es = 1;
+      else if (e0 + ff == E && side == 1) es = 0;
+    }
+  };
+  // gradient slot lq (elements e0 - 1 + lq; faces lq and lq + 1) of the element evaluated at
+  // point p, and the row r of p in the point tables
+  auto point_slot = [&](int p, int &lq, int &r) {
+    if (p < NN) {
+      lq = p / Q + 1;
+      r = p % Q;
+    } else {
+      int ff, side, es;
+      trace_side(p, ff, side, es);
+      lq = ff + es;
+      r = Q + es;
+    }
+  };
+
+  // the values of the variables at point p: the nodal values, or the traces of the side
+  // evaluated; variable v is at [v * stride] of the returned row
+  auto values = [&](int p, int &stride) -> const double * {
+    if (p < NN) {
+      stride = Lds::NNP;
+      return &sX[0][p];
+    }
+    int ff, side, es;
+    trace_side(p, ff, side, es);
+    stride = Lds::NHP;
+    return es ? &sTm[0][ff + 1 + es] : &sTp[0][ff + 1 + es];
+  };
+  // 1. traces of w and values at the nodes; meanwhile the AT combinations of past levels (Eq. (7)) of the central
   //    traces and of the fluxes at delayed PE interfaces are gathered from the ring
   for (int idx = t; idx < V * NH; idx += NTH) {
     const int v = idx / NH, l = idx % NH;
@@ -317,6 +386,14 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     sWa[v][fl] = acw;
     if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = acf;
   }
+  for (int idx = t; idx < V * NN; idx += NTH) {
+    const int v = idx / NN, p = idx % NN;
+    const int qn = p % Q, l = p / Q + 2;
+    OpT xo = 0;
+#pragma unroll
+    for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)sB[qn][j] * (OpT)sW[v * M + j][l];
+    sX[v][p] = kMixed ? sW[v * M][l] + (double)xo : (double)xo;
+  }
   __syncthreads();
 
   // 2. central traces; face fl sits between local elements fl (left) and fl + 1 (right).
@@ -331,36 +408,143 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     sWc[v][fl] = wc;
     if (i < 0 || sK[fl] == 0) sWa[v][fl] = wc;
   }
-  __syncthreads();
-
-  // 3. LDG gradient q_j = (2j+1)/dx [w*_R - (-1)^j w*_L - sum_k D_jk w_k] of the element
-  //    with gradient slot lq (left face lq, right face lq + 1)
-  for (int idx = t; idx < V * M * NQ; idx += NTH) {
-    const int c = idx / NQ, lq = idx % NQ;
-    const int v = c / M, j = c % M;
-    OpT vol = 0;
-    if constexpr (kMixed) {
-      // D_j0 = 1 - (-1)^j: the mean cancels against the face terms
-      const double m0 = sW[v * M][lq + 1];
-#pragma unroll
-      for (int k = 1; k < M; ++k) vol += (OpT)sD[j][k] * (OpT)sW[v * M + k][lq + 1];
-      const double dl = sWa[v][lq] - m0, dr = sWa[v][lq + 1] - m0;
-      sQ[c][lq] = (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl) - (double)vol);
+  //    Beside them, the species sums of the mixture chain, one lane per (point, sum): the
+  //    internal energy e(T) = sum_i Y_i R_i [T (a_i0 - 1 + T (a_i1/2 + ...)) + a_i5] is one
+  //    quintic in T whose coefficients are rho^-1 sum_i rho_i R_i (a_i0 - 1), ..., and
+  //    R = rho^-1 sum_i rho_i R_i; row 7 holds 1/rho, u and e* = E/rho - u^2/2.
+  for (int idx = t; idx < 8 * NP; idx += NTH) {
+    const int q = idx / NP, p = idx % NP;
+    int vs;
+    const double *vrow = values(p, vs);
+    if (q == 7) {
+      const double rho_inv = 1.0 / vrow[0];
+      const double u = vrow[vs] * rho_inv;
+      sRinv[p] = rho_inv;
+      sU[p] = u;
+      sMix[7][p] = vrow[2 * vs] * rho_inv - 0.5 * u * u;
     } else {
+      double sum = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) vol += (OpT)sD[j][k] * (OpT)sW[v * M + k][lq + 1];
-      const OpT wl = (OpT)((j & 1) ? -sWa[v][lq] : sWa[v][lq]);
-      sQ[c][lq] = (double)((OpT)((2 * j + 1) * a.inv_dx) * ((OpT)sWa[v][lq + 1] - wl - vol));
+      for (int i = 0; i < NS; ++i) sum += vrow[(3 + i) * vs] * mk->ek[i][q];
+      sMix[q][p] = sum;
     }
   }
   __syncthreads();
 
-  // 4. point physics, one group of LP lanes per point (the quadrature nodes of the tile, then
-  //    both traces of faces e0 .. e0+TE).  Every lane of a group forms rho, rho u, rho E and their
-  //    gradients; lane k owns the species k, k+LP, ....  Species sums (mixture energy polynomial,
-  //    gas constant, diffusive enthalpy terms) are reduced over the group; the temperature Newton,
-  //    pressure, sound speed and viscosity are evaluated on every lane of the group alike.
-  //    At the nodes the lanes also form the Gibbs energies and concentrations of their species.
+  // 3. gradients at the points.  The LDG gradient of the element with gradient slot lq (left
+  //    face lq, right face lq + 1) has modes q_j = (2j+1)/dx [w*_R - (-1)^j w*_L - sum_k D_jk w_k];
+  //    its value at a point of row r (node r < Q, the right end xi = +1 for r = Q, the left end
+  //    for r = Q + 1) is sum_j P_j(xi_r) q_j = (A_r w*_R - B_r w*_L - sum_k G_rk w_k)/dx, with the
+  //    tabulated A_r = sum_j (2j+1) P_j(xi_r), B_r = sum_j (-1)^j (2j+1) P_j(xi_r) and
+  //    G_rk = sum_j (2j+1) P_j(xi_r) D_jk.  Since D_j0 = 1 - (-1)^j, A_r - B_r = G_r0 and the mean
+  //    cancels: the mixed path forms the face terms against it in FP64 and the rest in FP32.
+  for (int idx = t; idx < V * NP; idx += NTH) {
+    const int v = idx / NP, p = idx % NP;
+    int lq, r;
+    point_slot(p, lq, r);
+    double d;
+    if constexpr (kMixed) {
+      const double m0 = sW[v * M][lq + 1];
+      OpT vol = 0;
+#pragma unroll
+      for (int k = 1; k < M; ++k) vol += (OpT)sGD[r][k] * (OpT)sW[v * M + k][lq + 1];
+      d = a.inv_dx * (sGA[r] * (sWa[v][lq + 1] - m0) - sGB[r] * (sWa[v][lq] - m0) - (double)vol);
+    } else {
+      double vol = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) vol += sGD[r][k] * sW[v * M + k][lq + 1];
+      d = a.inv_dx * (sGA[r] * sWa[v][lq + 1] - sGB[r] * sWa[v][lq] - vol);
+    }
+    sDx[v][p] = d;
+  }
+  __syncthreads();
+
+  // 4. point physics (FP64).  Points: the quadrature nodes of the tile, then both traces of the
+  //    faces e0 .. e0+TE.  First one lane per point forms the mixture chain (species sums of
+  //    the energy polynomial, temperature Newton, pressure, sound speed, transport
+  //    coefficients, the convective and non-species diffusive fluxes); then a group of LP lanes
+  //    per point shares the species (diffusive species and enthalpy fluxes, Gibbs energies and
+  //    concentrations at the nodes), reducing the two species sums of the heat flux over the
+  //    group.
+  //    At a PE interface the synchronous gradient trace adds to the point's gradient the
+  //    difference that the synchronous central traces (instead of the AT ones) make to it.
+  auto pe_corr = [&](int v, int lq, int r) -> double {
+    const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
+    return a.inv_dx * (sGA[r] * dr - sGB[r] * dl);
+  };
+  if (t < NP) {
+    const int p = t;
+    const bool node = p < NN;
+    int lq, r;
+    point_slot(p, lq, r);
+    int ff = 0, side = 0, es = 0;
+    if (!node) trace_side(p, ff, side, es);
+    const bool valid = periodic || (node ? p / Q < nloc : e0 + ff <= E);
+    const bool pe = !node && sI[ff + 1] >= 0;
+    int vs;
+    const double *vrow = values(p, vs);
+    const double wr = vrow[0], wm = vrow[vs], we = vrow[2 * vs];
+    const double rho_inv = sRinv[p], u = sU[p], estar = sMix[7][p];
+    double c[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c[q] = sMix[q][p] * rho_inv;
+    const double Rmix = sMix[6][p] * rho_inv;
+    double T, cv;
+    const bool conv = newton_T(c, mk->T_guess, estar, T, cv);
+    const double lnT = log(T);   // shared by the viscosity law and the Gibbs energies
+    const double cp = cv + Rmix;
+    const double pr = wr * Rmix * T;
+    const double rcv = 1.0 / cv;
+    const double snd = sqrt(cp * rcv * pr * rho_inv);
+    if (valid) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
+    double g1 = wm * u + pr, g2 = u * (we + pr);
+    double gs1 = g1, gs2 = g2;
+    double rhoD = 0.0, kc = 0.0;
+    if (a.viscous) {
+      // f^d of Eq. (2)-(3) without its species sums: tau = 4/3 mu u_x and the heat flux
+      // -kappa T_x with T_x = (e_x - sum_i e_i dY_i/dx)/c_v; the species terms (unit Lewis
+      // number, J_i = -rho D dY_i/dx, rho D = mu/Pr) are added by the species lanes
+      const double mu = mk->mu_ref * exp(mk->mu_exp * (lnT - mk->ln_T_ref));
+      const double kappa = mu * cp * mk->inv_prandtl;
+      rhoD = mu * mk->inv_prandtl;
+      kc = kappa * rcv;
+      const double En = we * rho_inv;
+      auto partial = [&](double d0, double d1, double d2, double &h1, double &h2) {
+        const double u_x = (d1 - u * d0) * rho_inv;
+        const double e_x = (d2 - En * d0) * rho_inv - u * u_x;
+        const double tau = (4.0 / 3.0) * mu * u_x;
+        h1 -= tau;
+        h2 -= tau * u + kc * e_x;
+      };
+      partial(sDx[0][p], sDx[1][p], sDx[2][p], g1, g2);
+      if (pe)
+        partial(sDx[0][p] + pe_corr(0, lq, r), sDx[1][p] + pe_corr(1, lq, r), sDx[2][p] + pe_corr(2, lq, r), gs1,
+                gs2);
+    }
+    if (valid) {
+      if (node) {
+        sG[0][p] = wm;
+        sG[1][p] = g1;
+        sG[2][p] = g2;
+      } else {
+        sGf[side][0][ff] = wm;
+        sGf[side][1][ff] = g1;
+        sGf[side][2][ff] = g2;
+        sLam[side][ff] = fabs(u) + snd;
+        if (pe) {
+          sGs[side][0][ff] = wm;
+          sGs[side][1][ff] = gs1;
+          sGs[side][2][ff] = gs2;
+        }
+      }
+      sRhoD[p] = rhoD;
+      sKc[p] = kc;
+      sTT[p] = T;
+      sLnT[p] = lnT;
+      sInvT[p] = 1.0 / T;
+    }
+  }
+  __syncthreads();
   {
     constexpr int kSlots = NP <= 32 ? 32 : 64;   // point slots per workgroup
     constexpr int LP = LPP > 0 ? LPP : NTH / kSlots;   // lanes per point
@@ -370,182 +554,73 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     if ((t & ~63) / LP < NP) {
       const int k = t % LP;
       const int p = min(t / LP, NP - 1);          // spare groups redo the last point and write nothing
-      bool writer = t / LP < NP;
       const bool node = p < NN;
-      int qn = 0, ff = 0, side = 0, es = 0, l, lq;
-      if (node) {
-        qn = p % Q;
-        l = p / Q + 2;
-        lq = p / Q + 1;
-      } else {
-        const int pp = p - NN;
-        ff = pp >> 1;                             // face e0 + ff
-        side = pp & 1;                            // 0: the element left of the face (its xi = +1)
-        es = side;                                // the side whose element is evaluated
-        if (!periodic) {                          // a transmissive end: the ghost side takes the
-          if (e0 + ff == 0 && side == 0) es = 1;  // interior's trace and gradient trace
-          else if (e0 + ff == E && side == 1) es = 0;
-        }
-        l = ff + 1 + es;
-        lq = ff + es;                             // gradient slot; its faces are lq and lq + 1
-      }
-      // points of a transmissive mesh past its last element carry no state: nothing is stored
-      // for them and they do not enter the error flag
-      writer = writer && (periodic || (node ? p / Q < nloc : e0 + ff <= E));
+      int lq, r;
+      point_slot(p, lq, r);
+      int ff = 0, side = 0, es = 0;
+      if (!node) trace_side(p, ff, side, es);
+      const bool writer = t / LP < NP && (periodic || (node ? p / Q < nloc : e0 + ff <= E));
       const bool pe = !node && sI[ff + 1] >= 0;
-      // value, gradient and synchronous gradient (PE-interface traces) of variable v
-      auto eval = [&](int v, double &x, double &d, double &ds) {
-        if (node) {
-          OpT xo = 0, dO = 0;
+      const double rho_inv = sRinv[p], u = sU[p], T = sTT[p];
+      int vs;
+      const double *vrow = values(p, vs);
+      double gy[NO], gsy[NO], hT[NO], wy[NO];
 #pragma unroll
-          for (int j = kMixed ? 1 : 0; j < M; ++j) {
-            xo += (OpT)sB[qn][j] * (OpT)sW[v * M + j][l];
-            dO += (OpT)sB[qn][j] * (OpT)sQ[v * M + j][lq];
-          }
-          x = kMixed ? sW[v * M][l] + (double)xo : (double)xo;
-          d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
-          ds = d;
-        } else {
-          const OpT sgn = es ? (OpT)-1 : (OpT)1;   // P_j(+-1) = (+-1)^j
-          OpT dO = 0, pj = kMixed ? sgn : (OpT)1;
-#pragma unroll
-          for (int j = kMixed ? 1 : 0; j < M; ++j) {
-            dO += pj * (OpT)sQ[v * M + j][lq];
-            pj *= sgn;
-          }
-          x = es ? sTm[v][l] : sTp[v][l];
-          d = kMixed ? sQ[v * M][lq] + (double)dO : (double)dO;
-          ds = d;
-          if (pe) {
-            // synchronous gradient trace at a PE interface: undo the AT central traces of the element's faces
-            const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
-            double corr = 0.0, pk = 1.0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              corr += pk * (2 * j + 1) * a.inv_dx * (dr - ((j & 1) ? -dl : dl));
-              pk *= es ? -1.0 : 1.0;
-            }
-            ds = d + corr;
-          }
+      for (int m = 0; m < NO; ++m) {
+        const int i = k + LP * m;
+        wy[m] = i < NS ? vrow[(3 + i) * vs] : 0.0;
+        gy[m] = gsy[m] = wy[m] * u;
+        hT[m] = 0.0;
+        if (i < NS) {
+          const double *ai = mk->a[i];
+          const double *h2i = mk->h2[i];
+          hT[m] = T * (ai[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3])))) + ai[5];  // h_i/R_i
         }
-      };
-      double wr, dr0, sr0, wm, dm, sm, we, de, se;
-      eval(0, wr, dr0, sr0);
-      eval(1, wm, dm, sm);
-      eval(2, we, de, se);
-      double wy[NO], dy[NO], sy[NO];
-#pragma unroll
-      for (int m = 0; m < NO; ++m) {
-        const int i = k + LP * m;
-        if (i < NS) eval(3 + i, wy[m], dy[m], sy[m]);
-        else wy[m] = dy[m] = sy[m] = 0.0;
       }
-      const double rho_inv = 1.0 / wr;
-      const double u = wm * rho_inv;
-      const double estar = we * rho_inv - 0.5 * u * u;
-      double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Rmix = 0.0;
-#pragma unroll
-      for (int m = 0; m < NO; ++m) {
-        const int i = k + LP * m;
-        if (i >= NS) continue;
-        const double yr = (wy[m] * rho_inv) * mk->Ri[i];
-        c[0] += yr * (mk->a[i][0] - 1.0);
-        c[1] += yr * mk->h2[i][0];
-        c[2] += yr * mk->h2[i][1];
-        c[3] += yr * mk->h2[i][2];
-        c[4] += yr * mk->h2[i][3];
-        c[5] += yr * mk->a[i][5];
-        Rmix += yr;
-      }
-#pragma unroll
-      for (int q = 0; q < 6; ++q) c[q] = group_sum<LP>(c[q]);
-      Rmix = group_sum<LP>(Rmix);
-      double T, cv;
-      const bool conv = newton_T(c, mk->T_guess, estar, T, cv);
-      const double lnT = log(T);   // shared by the viscosity law and the Gibbs energies
-      const double cp = cv + Rmix;
-      const double pr = wr * Rmix * T;
-      const double snd = sqrt(cp / cv * pr * rho_inv);
-      if (writer) ok = conv && pr > 0.0 && isfinite(pr) && wr > 0.0 && ok;
-      double g0 = wm, g1 = wm * u + pr, g2 = u * (we + pr);
-      double gs1 = g1, gs2 = g2;
-      double gy[NO], gsy[NO];
-#pragma unroll
-      for (int m = 0; m < NO; ++m) gy[m] = gsy[m] = wy[m] * u;
       if (a.viscous) {
-        const double mu = mk->mu_ref * exp(mk->mu_exp * (lnT - mk->ln_T_ref));
-        const double kappa = mu * cp * mk->inv_prandtl;
-        const double rhoD = mu * mk->inv_prandtl;
-        const double En = we * rho_inv;
-        // f^d of Eq. (2)-(3) for one gradient: tau = 4/3 mu u_x, heat flux -k T_x + sum_i h_i J_i,
-        // unit Lewis number J_i = -rho D dY_i/dx with rho D = mu/Pr
-        auto diffusive = [&](double d0, double d1, double d2, const double (&dyy)[NO], double (&gyy)[NO],
-                             double &h1, double &h2) {
-          const double u_x = (d1 - u * d0) * rho_inv;
-          const double e_x = (d2 - En * d0) * rho_inv - u * u_x;
+        const double rhoD = sRhoD[p], kc = sKc[p];
+        auto species = [&](double d0, bool sync, double (&gyy)[NO]) -> double {
           double sum_eY = 0.0, sum_hJ = 0.0;
 #pragma unroll
           for (int m = 0; m < NO; ++m) {
             const int i = k + LP * m;
             if (i >= NS) continue;
-            const double *ai = mk->a[i];
-            const double *h2i = mk->h2[i];
-            const double hT = T * (ai[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3])))) + ai[5];  // h_i/R_i
-            const double Yx = (dyy[m] - (wy[m] * rho_inv) * d0) * rho_inv;
-            sum_eY += mk->Ri[i] * (hT - T) * Yx;
+            const double dy = sDx[3 + i][p] + (sync ? pe_corr(3 + i, lq, r) : 0.0);
+            const double Yx = (dy - (wy[m] * rho_inv) * d0) * rho_inv;
+            sum_eY += mk->Ri[i] * (hT[m] - T) * Yx;
             const double J = -rhoD * Yx;
-            sum_hJ += mk->Ri[i] * hT * J;
+            sum_hJ += mk->Ri[i] * hT[m] * J;
             gyy[m] += J;                  // f^d_i = -J_i
           }
-          sum_eY = group_sum<LP>(sum_eY);
-          sum_hJ = group_sum<LP>(sum_hJ);
-          const double T_x = (e_x - sum_eY) / cv;
-          const double tau = (4.0 / 3.0) * mu * u_x;
-          const double qh = -kappa * T_x + sum_hJ;
-          h1 -= tau;
-          h2 -= tau * u - qh;
+          // heat flux -kappa T_x + sum_i h_i J_i: the part left out of the mixture chain
+          return kc * group_sum<LP>(sum_eY) + group_sum<LP>(sum_hJ);
         };
-        diffusive(dr0, dm, de, dy, gy, g1, g2);
-        if (pe) diffusive(sr0, sm, se, sy, gsy, gs1, gs2);
+        const double q = species(sDx[0][p], false, gy);
+        const double qs = pe ? species(sDx[0][p] + pe_corr(0, lq, r), true, gsy) : 0.0;
+        if (writer && k == 0) {
+          if (node) {
+            sG[2][p] += q;
+          } else {
+            sGf[side][2][ff] += q;
+            if (pe) sGs[side][2][ff] += qs;
+          }
+        }
       }
       if (writer) {
         if (node) {
-          if (k == 0) {
-            sG[0][p] = g0;
-            sG[1][p] = g1;
-            sG[2][p] = g2;
-            sT[p] = T;
-          }
-          const double invT = 1.0 / T;
-          if (k == 1) {
-            sLnT[p] = lnT;
-            sInvT[p] = invT;
-          }
+          const double invT = sInvT[p], lnT = sLnT[p];
 #pragma unroll
           for (int m = 0; m < NO; ++m) {
             const int i = k + LP * m;
             if (i >= NS) continue;
             sG[3 + i][p] = gy[m];
             const double *ci = mk->a[i];
-            const double *h2i = mk->h2[i];
             const double *s2i = mk->s2[i];
-            const double hRT = ci[0] + T * (h2i[0] + T * (h2i[1] + T * (h2i[2] + T * h2i[3]))) + ci[5] * invT;
             const double sR = ci[0] * lnT + T * (ci[1] + T * (s2i[0] + T * (s2i[1] + T * s2i[2]))) + ci[6];
-            sGRT[i][p] = hRT - sR;
+            sGRT[i][p] = hT[m] * invT - sR;
             sConc[i][p] = wy[m] * mk->invW[i];
           }
         } else {
-          if (k == 0) {
-            sGf[side][0][ff] = g0;
-            sGf[side][1][ff] = g1;
-            sGf[side][2][ff] = g2;
-            sLam[side][ff] = fabs(u) + snd;
-            if (pe) {
-              sGs[side][0][ff] = g0;
-              sGs[side][1][ff] = gs1;
-              sGs[side][2][ff] = gs2;
-            }
-          }
 #pragma unroll
           for (int m = 0; m < NO; ++m) {
             const int i = k + LP * m;
@@ -833,6 +908,11 @@ adg_status ns_build_mech(const adg_physics *ph, NsMechT<NSC> &hm) {
     hm.s2[i][0] = c[2] / 2.0;
     hm.s2[i][1] = c[3] / 3.0;
     hm.s2[i][2] = c[4] / 4.0;
+    hm.ek[i][0] = hm.Ri[i] * (c[0] - 1.0);
+    for (int q = 0; q < 4; ++q) hm.ek[i][1 + q] = hm.Ri[i] * hm.h2[i][q];
+    hm.ek[i][5] = hm.Ri[i] * c[5];
+    hm.ek[i][6] = hm.Ri[i];
+    hm.ek[i][7] = 0.0;
   }
   for (int r = 0; r < hm.nr; ++r) {
     if (!(m->A[r] > 0.0)) return ADG_ERR_ARG;

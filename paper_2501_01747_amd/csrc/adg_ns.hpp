@@ -33,6 +33,9 @@ struct NsMechT {
   double a[NSC][7];
   double h2[NSC][4];      // a1/2, a2/3, a3/4, a4/5
   double s2[NSC][3];      // a2/2, a3/3, a4/4
+  // R_i times the coefficients of the mixture energy quintic (cv/R - 1 form) and R_i:
+  // R_i (a0 - 1), R_i a1/2, R_i a2/3, R_i a3/4, R_i a4/5, R_i a5, R_i, 0
+  double ek[NSC][8];
   double lnA[kNsMaxReactions], b[kNsMaxReactions], EaR[kNsMaxReactions];
   int dnu[kNsMaxReactions];
   // compact per-reaction form for one lane per (point, reaction): the species

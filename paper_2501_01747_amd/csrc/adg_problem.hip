@@ -73,6 +73,23 @@ void build_tables(int M, Tables &tb) {
       }
       tb.Dm[j][k] = s;
     }
+  for (int r = 0; r < M + 2; ++r) {
+    double Pr[kMaxM];
+    for (int j = 0; j < M; ++j)
+      Pr[j] = r < M ? tb.B[r][j] : r == M ? 1.0 : (j & 1 ? -1.0 : 1.0);   // P_j(+1) = 1, P_j(-1) = (-1)^j
+    double ga = 0.0, gb = 0.0;
+    for (int j = 0; j < M; ++j) {
+      ga += (2 * j + 1) * Pr[j];
+      gb += (j & 1 ? -1.0 : 1.0) * (2 * j + 1) * Pr[j];
+    }
+    tb.GA[r] = ga;
+    tb.GB[r] = gb;
+    for (int k = 0; k < M; ++k) {
+      double g = 0.0;
+      for (int j = 0; j < M; ++j) g += (2 * j + 1) * Pr[j] * tb.Dm[j][k];
+      tb.GD[r][k] = g;
+    }
+  }
 }
 
 // Smoothness quadratic form sum_s 2^(2s-1) int P_a^(s) P_b^(s) (Legendre
