@@ -53,9 +53,11 @@ __device__ __forceinline__ int eff_delay(const DelayParams &d, long long n, int 
     unsigned long long ctr = (unsigned long long)n * (unsigned long long)d.nif + (unsigned long long)i;
     unsigned long long z = splitmix64(d.seed ^ (ctr * 0x9E3779B97F4A7C15ull));
     double u = (double)(z >> 11) * 0x1.0p-53;
-    k = d.L - 1;
-    for (int j = 0; j < d.L; ++j)
-      if (u < d.cum[j]) { k = j; break; }
+    // the first j with u < cum[j] (cum is non-decreasing), at most L - 1: the number of
+    // j < L - 1 with cum[j] <= u, counted without a data-dependent loop
+    k = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxL - 1; ++j) k += (j < d.L - 1 && u >= d.cum[j]) ? 1 : 0;
   } else if (d.mode == 3) {
     k = d.sched[(long long)step_mod(n, d.sched_steps) * d.nif + i];
   }

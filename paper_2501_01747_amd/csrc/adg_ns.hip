@@ -118,10 +118,9 @@ struct NsLds {
   double sLam[2][TE + 1];
   double sTT[NPP], sLnT[NPP], sInvT[NPP];
   double sF[V][TE + 1], sFat[V][TE + 1];
-  // tables, indexed at run time: nodal values, volume and source projections, gradients at the
-  // points (rows: the nodes, then xi = +1 and xi = -1)
-  double sB[Q][M], sWG[Q][M], sWB[Q][M];
-  double sGD[Q + 2][M], sGA[Q + 2], sGB[Q + 2];
+  // operator tables, indexed at run time (copied whole): nodal values, volume and source
+  // projections, gradients at the points (rows: the nodes, then xi = +1 and xi = -1)
+  Tables sTb;
   int sI[NF], sK[NF];
 };
 
@@ -177,12 +176,12 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   auto &sInvT = Ls.sInvT;
   auto &sF = Ls.sF;
   auto &sFat = Ls.sFat;
-  auto &sB = Ls.sB;
-  auto &sWG = Ls.sWG;
-  auto &sWB = Ls.sWB;
-  auto &sGD = Ls.sGD;
-  auto &sGA = Ls.sGA;
-  auto &sGB = Ls.sGB;
+  auto &sB = Ls.sTb.B;
+  auto &sWG = Ls.sTb.WG;
+  auto &sWB = Ls.sTb.WB;
+  auto &sGD = Ls.sTb.GD;
+  auto &sGA = Ls.sTb.GA;
+  auto &sGB = Ls.sTb.GB;
   auto &sI = Ls.sI;
   auto &sK = Ls.sK;
   constexpr int NP = Lds::NP;
@@ -191,8 +190,6 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const int t = threadIdx.x;
   const int E = a.E;
   const int nloc = min(TE, E - e0);
-  const long long n = a.step[par];
-  const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
   const NsMechT<NS> *__restrict__ mk = &smech;
   // variables stored per element in HBM and in the ring (the capacity NS may pad species)
   const int Vg = 3 + a.ns, VMg = Vg * M;
@@ -200,27 +197,37 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const int q_at = a.dl.q;
   bool ok = true;
 
-  // 0. mechanism, state of the tile and its halo, tables, PE-interface data of the faces.
-  //    Every global load is issued before the first LDS store, so the phase costs about one
-  //    memory latency.
+  // 0. mechanism, operator tables, state of the tile and its halo, PE-interface data of the
+  //    faces.  Every global load is issued first, and nothing before them depends on a loaded
+  //    value (the step counter included), so the phase costs about one memory latency.
   constexpr int kOut = (V * M * TE + NTH - 1) / NTH;
   // the second operand of the RK combination (w^n, or the 2N register) of the outputs
   // this thread writes in the last phase
   const bool use_prev = rk.two_n ? rk.ca != 0.0 : rk.ca != 0.0 || rk.cb != 1.0;
   const double *prev = rk.two_n ? kbuf : w0;
   double w0pre[kOut];
+  long long n;
   {
     constexpr int nwords = (int)(sizeof(NsMechT<NS>) / 8);
     constexpr int kMw = (nwords + NTH - 1) / NTH;
+    constexpr int twords = (int)(sizeof(Tables) / 8);
+    constexpr int kTw = (twords + NTH - 1) / NTH;
     constexpr int kSw = (V * M * NH + NTH - 1) / NTH;
     const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.mech);
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(&smech);
-    unsigned long long mw[kMw];
+    const unsigned long long *tsrc = reinterpret_cast<const unsigned long long *>(&a.tb);
+    unsigned long long *tdst = reinterpret_cast<unsigned long long *>(&Ls.sTb);
+    unsigned long long mw[kMw], tw[kTw];
     double sw[kSw];
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
       const int idx = t + m * NTH;
       mw[m] = idx < nwords ? src[idx] : 0ull;
+    }
+#pragma unroll
+    for (int m = 0; m < kTw; ++m) {
+      const int idx = t + m * NTH;
+      tw[m] = idx < twords ? tsrc[idx] : 0ull;
     }
 #pragma unroll
     for (int m = 0; m < kSw; ++m) {
@@ -253,10 +260,16 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       w0pre[m] = 0.0;
       if (use_prev && idx < V * M * TE && el < nloc && c < VMg) w0pre[m] = prev[sidx(e0 + el, c, VMg)];
     }
+    n = a.step[par];
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
       const int idx = t + m * NTH;
       if (idx < nwords) dst[idx] = mw[m];
+    }
+#pragma unroll
+    for (int m = 0; m < kTw; ++m) {
+      const int idx = t + m * NTH;
+      if (idx < twords) tdst[idx] = tw[m];
     }
 #pragma unroll
     for (int m = 0; m < kSw; ++m) {
@@ -267,20 +280,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       sI[t] = fi;
       sK[t] = fi >= 0 ? eff_delay(a.dl, n, fi) : 0;
     }
-    for (int idx = t; idx < (Q + 2) * M; idx += NTH) {
-      const int qn = idx / M, j = idx % M;
-      if (qn < Q) {
-        sB[qn][j] = a.tb.B[qn][j];
-        sWG[qn][j] = a.tb.WG[qn][j];
-        sWB[qn][j] = a.tb.WB[qn][j];
-      }
-      sGD[qn][j] = a.tb.GD[qn][j];
-      if (j == 0) {
-        sGA[qn] = a.tb.GA[qn];
-        sGB[qn] = a.tb.GB[qn];
-      }
-    }
   }
+  const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
   __syncthreads();
   const int nr = mk->nr;
 
