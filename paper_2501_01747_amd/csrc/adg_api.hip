@@ -86,6 +86,17 @@ adg_status hip_fail(adg_solver *s, hipError_t e, const char *where) {
 // pair around each launch for adg_profile.
 typedef void (*TimerFn)(adg_solver *, int cls, bool begin);
 
+// Carried AT combinations of the launch of `stage` in the step at parity s->par: launch number
+// n S + stage of the run (n mod 2 = s->par: both start at zero) reads buffer (n S + stage) mod 2
+// and leaves its successor's values in the other one.  After a reset no delay is positive before
+// step q, so no launch reads a buffer before one has been written for it.
+void set_at_buffers(const adg_solver *s, NsArgs &a, int stage) {
+  if (!s->P.at) return;
+  const int b = (s->par * s->P.lay.S + stage) & 1;
+  a.at_in = s->P.at + (size_t)b * s->P.at_stride;
+  a.at_out = s->P.at + (size_t)(1 - b) * s->P.at_stride;
+}
+
 // The state buffer and step counter parity after one time step from (cur, par).
 void next_alignment(const adg_solver *s, int &cur, int &par) {
   const int S = s->P.lay.S;
@@ -139,6 +150,7 @@ adg_status enqueue_step(adg_solver *s, hipStream_t st, TimerFn timer) {
       a.rk = r;
       a.advance = last;
       a.par = s->par;
+      set_at_buffers(s, a, stage);
       if (timer) timer(s, 0, true);
       HIP_TRY(s, launch_ns_stage(M, s->ns_cfg, a, s->P.disc.precision == ADG_MIXED_FP32, st));
       if (timer) timer(s, 0, false);
@@ -415,6 +427,7 @@ adg_status adg_autotune(adg_solver *s, int32_t n_reps, int32_t *choice) {
   a.stage = 0;
   a.advance = 0;
   a.par = s->par;
+  set_at_buffers(s, a, 0);   // writes only the successor's buffer, which the next step rewrites
   // every candidate warmed up first, then timed in three interleaved rounds; each keeps
   // its fastest round (clock ramp-up and other transients then bias no candidate)
   double t[kNsConfigs];

@@ -286,7 +286,7 @@ size_t adg_batch_header_bytes(int32_t max_instances, int64_t max_elements) {
 
 size_t adg_batch_instance_bytes(const adg_physics *phys, const adg_discretization *disc, const adg_async *as) {
   Layout L;
-  if (!make_layout(phys, disc, as, L, nullptr)) return 0;
+  if (!make_layout(phys, disc, as, L, nullptr, true)) return 0;
   return align256(L.total);
 }
 
@@ -330,7 +330,7 @@ adg_status adg_batch_add(adg_batch *b, const adg_physics *phys, const adg_discre
   *slot_out = -1;
   Layout L;
   std::string why;
-  if (!make_layout(phys, disc, as, L, &why)) return bfail(b, ADG_ERR_ARG, why);
+  if (!make_layout(phys, disc, as, L, &why, true)) return bfail(b, ADG_ERR_ARG, why);
   if (count != (int64_t)L.E * L.V * L.M) return bfail(b, ADG_ERR_ARG, "state size mismatch");
   if (where != ADG_HOST && where != ADG_DEVICE) return bfail(b, ADG_ERR_ARG, "where must be ADG_HOST or ADG_DEVICE");
   if (disc->rk != ADG_SSPRK3) return bfail(b, ADG_ERR_UNSUPPORTED, "batches run SSP-RK3 only");

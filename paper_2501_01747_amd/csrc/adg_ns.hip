@@ -124,6 +124,28 @@ struct NsLds {
   int sI[NF], sK[NF];
 };
 
+// AT combination (Eq. (7)) of the central trace and the flux of variable v at interface i from
+// the levels n-k .. n-k-q+1 of stage st: levels 0..3 given (w, f; a level past q holds level
+// n-k and has weight 0), later ones (q > 4) read here one at a time.  The carried and the
+// in-launch combinations both come from here, so they round alike.
+__device__ __forceinline__ void at_combine(const NsArgs &a, int q, int k, int nmod, int st, int i, int v,
+                                           const double (&w)[4], const double (&f)[4], double &acw, double &acf) {
+  acw = 0.0;
+  acf = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double c = j < q ? at_weight(q, k, j) : 0.0;
+    acw += c * w[j];
+    acf += c * f[j];
+  }
+  for (int j = 4; j < q; ++j) {
+    const double c = at_weight(q, k, j);
+    const double *rec = ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), st, a.dl.nif, i);
+    acw += c * rec[a.ring.off_Wc + v];
+    acf += c * rec[a.ring.off_F + v];
+  }
+}
+
 // One tile of one stage (all phases).  OpT is the arithmetic type of the modal
 // operators (interpolation to nodes and traces, LDG gradient, volume integral):
 // double for the plain path, float for the mixed-precision path.  Point physics
@@ -207,6 +229,10 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const double *prev = rk.two_n ? kbuf : w0;
   double w0pre[kOut];
   long long n;
+  // the history gather of this lane (at most one item per lane): variable t / NF at face t % NF;
+  // its loads are issued in the load phase, their AT combination formed in the next
+  static_assert(V * NF <= NTH, "one history gather item per lane");
+  double g_w[4], g_f[4];
   {
     constexpr int nwords = (int)(sizeof(NsMechT<NS>) / 8);
     constexpr int kMw = (nwords + NTH - 1) / NTH;
@@ -219,6 +245,26 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     unsigned long long *tdst = reinterpret_cast<unsigned long long *>(&Ls.sTb);
     unsigned long long mw[kMw], tw[kTw];
     double sw[kSw];
+    // the interface of the gather item's face: loaded first, so the history loads that depend
+    // on it need not wait for the state
+    const int gv = t / NF, gfl = t % NF;
+    int gfi = -1;
+    if (t < V * NF && gv < Vg) {
+      int f = e0 - 1 + gfl;
+      if (periodic) {
+        while (f < 0) f += E;
+        while (f >= E) f -= E;
+      }
+      if (a.at_in) {
+        // carried from the previous launch: no dependence on the interface index
+        if (f >= 0 && f <= E) {
+          g_w[0] = a.at_in[(size_t)f * 2 * Vg + gv];
+          g_f[0] = a.at_in[(size_t)f * 2 * Vg + Vg + gv];
+        }
+      } else {
+        gfi = f >= 0 && f <= E ? a.face_if[f] : -1;
+      }
+    }
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
       const int idx = t + m * NTH;
@@ -261,6 +307,20 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       if (use_prev && idx < V * M * TE && el < nloc && c < VMg) w0pre[m] = prev[sidx(e0 + el, c, VMg)];
     }
     n = a.step[par];
+    // levels 0..3 of the gather item (a level past q reads level n-k with weight 0); they land
+    // while the LDS stores, the barrier and the traces proceed
+    if (gfi >= 0) {
+      const int k = eff_delay(a.dl, n, gfi);
+      if (k > 0) {
+        const int nm = step_mod(n, a.ring.D);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double *rec = ring_at(a.ring, ring_slot(nm, k + (j < q_at ? j : 0), a.ring.D), stage, a.dl.nif, gfi);
+          g_w[j] = rec[a.ring.off_Wc + gv];
+          g_f[j] = rec[a.ring.off_F + gv];
+        }
+      }
+    }
 #pragma unroll
     for (int m = 0; m < kMw; ++m) {
       const int idx = t + m * NTH;
@@ -324,8 +384,9 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     stride = Lds::NHP;
     return es ? &sTm[0][ff + 1 + es] : &sTp[0][ff + 1 + es];
   };
-  // 1. traces of w and values at the nodes; meanwhile the AT combinations of past levels (Eq. (7)) of the central
-  //    traces and of the fluxes at delayed PE interfaces are gathered from the ring
+  // 1. traces of w and values at the nodes; then the AT combinations of past levels (Eq. (7)) of
+  //    the central traces and of the fluxes at delayed PE interfaces, from the history gathered
+  //    by the load phase
   for (int idx = t; idx < V * NH; idx += NTH) {
     const int v = idx / NH, l = idx % NH;
     // transmissive ends: the ghost element beyond a boundary face carries the interior trace
@@ -358,35 +419,6 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     sTm[v][l] = tm;
     sTp[v][l] = tp;
   }
-  for (int idx = t; idx < V * NF; idx += NTH) {
-    const int v = idx / NF, fl = idx % NF;
-    const int i = sI[fl], k = sK[fl];
-    if (i < 0 || k == 0) continue;
-    double acw = 0.0, acf = 0.0;
-    if (v >= Vg) {   // padded species: nothing in the ring
-      sWa[v][fl] = 0.0;
-      if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = 0.0;
-      continue;
-    }
-    // levels 0..3 loaded together (a level past q reads level n-k with weight 0), later
-    // ones (q > 4) one at a time
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bool in = j < q_at;
-      const double c = in ? at_weight(q_at, k, j) : 0.0;
-      const double *rec = ring_at(a.ring, ring_slot(nmod, k + (in ? j : 0), a.ring.D), stage, a.dl.nif, i);
-      acw += c * rec[a.ring.off_Wc + v];
-      acf += c * rec[a.ring.off_F + v];
-    }
-    for (int j = 4; j < q_at; ++j) {
-      const double c = at_weight(q_at, k, j);
-      const double *rec = ring_at(a.ring, ring_slot(nmod, k + j, a.ring.D), stage, a.dl.nif, i);
-      acw += c * rec[a.ring.off_Wc + v];
-      acf += c * rec[a.ring.off_F + v];
-    }
-    sWa[v][fl] = acw;
-    if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = acf;
-  }
   for (int idx = t; idx < V * NN; idx += NTH) {
     const int v = idx / NN, p = idx % NN;
     const int qn = p % Q, l = p / Q + 2;
@@ -394,6 +426,25 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 #pragma unroll
     for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)sB[qn][j] * (OpT)sW[v * M + j][l];
     sX[v][p] = kMixed ? sW[v * M][l] + (double)xo : (double)xo;
+  }
+  // the AT combinations of the gathered levels, last: their loads have had the longest to land
+  if (t < V * NF) {
+    const int v = t / NF, fl = t % NF;
+    const int i = sI[fl], k = sK[fl];
+    if (i >= 0 && k > 0) {
+      if (v >= Vg) {   // padded species: nothing in the ring
+        sWa[v][fl] = 0.0;
+        if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = 0.0;
+      } else if (a.at_in) {
+        sWa[v][fl] = g_w[0];
+        if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = g_f[0];
+      } else {
+        double acw, acf;
+        at_combine(a, q_at, k, nmod, stage, i, v, g_w, g_f, acw, acf);
+        sWa[v][fl] = acw;
+        if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = acf;
+      }
+    }
   }
   __syncthreads();
 
@@ -473,6 +524,36 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const double dl = sWc[v][lq] - sWa[v][lq], dr = sWc[v][lq + 1] - sWa[v][lq + 1];
     return a.inv_dx * (sGA[r] * dr - sGB[r] * dl);
   };
+  static_assert(NTH - 64 >= V * TE, "a lane of the later wavefronts per (variable, owned face)");
+  if (t >= 64 && a.at_out) {
+    // the wavefronts the mixture chain leaves idle form the next launch's AT combinations at the
+    // PE interfaces this tile owns (faces e0 .. e0+nloc-1): stage + 1 of this step, or stage 0
+    // of the next; their levels all precede what this launch writes
+    const int idx = t - 64;
+    const int v = idx / TE, fo = idx % TE;
+    const int i = sI[fo + 1];
+    if (v < Vg && fo < nloc && i >= 0) {
+      const bool last = stage == a.nst - 1;
+      const long long n2 = n + (last ? 1 : 0);
+      const int s2 = last ? 0 : stage + 1;
+      const int k2 = eff_delay(a.dl, n2, i);
+      if (k2 > 0) {
+        const int nm2 = step_mod(n2, a.ring.D);
+        double w[4], f[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double *rec = ring_at(a.ring, ring_slot(nm2, k2 + (j < q_at ? j : 0), a.ring.D), s2, a.dl.nif, i);
+          w[j] = rec[a.ring.off_Wc + v];
+          f[j] = rec[a.ring.off_F + v];
+        }
+        double acw, acf;
+        at_combine(a, q_at, k2, nm2, s2, i, v, w, f, acw, acf);
+        const size_t base = (size_t)(e0 + fo) * 2 * Vg;
+        a.at_out[base + v] = acw;
+        a.at_out[base + Vg + v] = acf;
+      }
+    }
+  }
   if (t < NP) {
     const int p = t;
     const bool node = p < NN;
@@ -864,6 +945,9 @@ adg_status ns_setup(NsArgs &a, const adg_physics *ph, const adg_discretization *
   if (rc != ADG_OK) return rc;
   a.ns = ns;
   a.periodic = periodic ? 1 : 0;
+  a.at_in = nullptr;
+  a.at_out = nullptr;
+  a.nst = 3;
   a.face_if = face_if;
   a.step = step;
   a.err = err;

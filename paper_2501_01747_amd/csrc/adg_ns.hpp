@@ -70,6 +70,13 @@ struct NsArgs {
   int *err;
   long long target;     // batched launches skip the instance once its step reaches it
   const void *mech;     // NsMechT<capacity> of the kernel that runs the problem
+  // AT combinations carried between launches (single problems; nullptr: gathered in the launch).
+  // Per face f: [f * 2 Vg, +Vg) the AT central traces, [+Vg, +2 Vg) the AT fluxes, Vg = 3 + ns.
+  // at_in holds this launch's values (written by the previous launch), at_out receives the next
+  // launch's (stage + 1 of this step, or stage 0 of the next; nst stages per step).
+  const double *at_in;
+  double *at_out;
+  int nst;
   int E;
   int stage;
   RkStage rk;

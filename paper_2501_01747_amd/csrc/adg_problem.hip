@@ -134,7 +134,7 @@ void build_limiter_tables(int M, LimiterArgs &la) {
 }
 
 bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_async *as, Layout &L,
-                 std::string *why) {
+                 std::string *why, bool batched) {
   auto bad = [&](const char *m) { if (why) *why = m; return false; };
   if (!ph || !d || !as) return bad("null argument");
   if (d->order_p < 1 || d->order_p > 4) return bad("order_p must be 1..4");
@@ -215,6 +215,9 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   L.ring = off;   off += align256(sizeof(double) * (size_t)L.D * L.S * (L.nif > 0 ? L.nif : 1) * L.rec);
   L.sched = off;  off += as->mode == ADG_SCHEDULE ? align256((size_t)as->schedule_steps * (L.nif > 0 ? L.nif : 1)) : 0;
   L.mech = off;   off += ph->model == ADG_DETAILED ? align256(ns_mech_bytes(ph->n_species)) : 0;
+  // the AT combinations carried from launch to launch (two buffers of (E + 1) faces x 2 Vg)
+  L.carry_at = !batched && ph->model == ADG_DETAILED && L.nif > 0;
+  L.at = off;     off += L.carry_at ? 2 * align256(sizeof(double) * (size_t)(L.E + 1) * 2 * (3 + ph->n_species)) : 0;
   L.total = off;
   return true;
 }
@@ -256,6 +259,10 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
   P.err = (int *)(base + L.counters + 64);
   P.flag_count = (unsigned long long *)(base + L.counters + 128);
   P.ring = (double *)(base + L.ring);
+  if (L.carry_at) {
+    P.at = (double *)(base + L.at);
+    P.at_stride = align256(sizeof(double) * (size_t)(L.E + 1) * 2 * (3 + phys->n_species)) / sizeof(double);
+  }
 
   const bool periodic = disc->bc == ADG_PERIODIC;
   std::vector<int> fif(L.E + 1, -1);
@@ -336,6 +343,9 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
     P.na.kbuf = P.W[2];
     P.na.rk = rk_stage(disc->rk, 0);
     P.na.target = kNoTarget;
+    P.na.nst = L.S;
+    P.na.at_in = nullptr;
+    P.na.at_out = nullptr;
   }
   return ADG_OK;
 }

@@ -17,11 +17,12 @@ constexpr long long kNoTarget = 0x7fffffffffffffffLL;
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t state, flags, face_if, counters, ring, sched, mech, total;
+  size_t state, flags, face_if, counters, ring, sched, mech, at, total;
   int nbuf;             // state-sized buffers (3; 4 for a 2N scheme with the limiter)
   int nif, nfaces, D, rec, q, V, M, E;
   int S;                // RK stages per step
   int off_F, off_Wc, off_U;
+  bool carry_at;        // AT combinations carried between launches (single detailed problems with PE interfaces)
 };
 
 struct Problem {
@@ -37,14 +38,17 @@ struct Problem {
   int *err = nullptr;
   unsigned long long *flag_count = nullptr;
   double *ring = nullptr;
+  double *at = nullptr;        // detailed model with PE interfaces: two per-face AT buffers
+  size_t at_stride = 0;        // doubles per buffer
   EulerArgs ea{};
   LimiterArgs la{};
   NsArgs na{};
 };
 
 // Validates a problem and computes the layout of its device region (bytes in L.total).
+// batched: the layout of a batch instance (no AT carry buffers: the batched kernel gathers).
 bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_async *as, Layout &L,
-                 std::string *why);
+                 std::string *why, bool batched = false);
 // ADG_ERR_UNSUPPORTED for precisions a single problem cannot run (MIXED_BF16; MIXED_FP32 with
 // the one-step model), with the reason in *why.
 adg_status check_precision(const adg_physics *ph, const adg_discretization *d, std::string *why);
