@@ -741,10 +741,16 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const int nitems = nr * NN;
     for (int idx = t; idx < nitems; idx += 2 * NTH) {
       const bool two = idx + NTH < nitems;
-      const int idx2 = two ? idx + NTH : idx;
-      const double ra = rate(idx), rb = rate(idx2);
-      sRate[idx / NN][idx % NN] = ra;
-      if (two) sRate[idx2 / NN][idx2 % NN] = rb;
+      // a wavefront none of whose lanes holds a second item forms one rate per lane
+      const bool wave_two = (idx & ~63) + NTH < nitems;
+      if (wave_two) {
+        const int idx2 = two ? idx + NTH : idx;
+        const double ra = rate(idx), rb = rate(idx2);
+        sRate[idx / NN][idx % NN] = ra;
+        if (two) sRate[idx2 / NN][idx2 % NN] = rb;
+      } else {
+        sRate[idx / NN][idx % NN] = rate(idx);
+      }
     }
   }
 
@@ -879,7 +885,9 @@ union NsBatchLds<5, TE> {
 // skipped by all of its workgroups (its first tile carries the count over to
 // the other parity at the last stage).
 // At most 128 VGPRs (four wavefronts per SIMD): with four tiles' LDS per CU, more registers would
-// leave only three of them resident (measured: 24 % slower at 132 VGPRs).
+// leave only three of them resident (measured: 24 % slower at 132 VGPRs).  The LDS of tiles of up
+// to N_p = 3 likewise stays within a quarter of the CU's 160 KiB.
+static_assert(sizeof(NsBatchLds<4, 8>) + sizeof(NsMech) <= 40960, "four batched tiles of N_p <= 3 per CU");
 template <typename OpT, int MMAX, int TE>
 __global__ __launch_bounds__(kThreadsBatch, 4) void ns_batch_kernel(const NsArgs *__restrict__ insts,
                                                             const int2 *__restrict__ tiles, int stage, int par) {

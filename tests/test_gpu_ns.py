@@ -193,6 +193,35 @@ def test_odd_graph_length(adg, mech):
             np.testing.assert_array_equal(w, ref)
 
 
+@pytest.mark.parametrize("rk", ["ssprk3", "rk2", "lserk4"])
+def test_carried_at_after_restart(adg, mech, rk):
+    """The AT combinations a launch leaves for the next one: a solver stepped, set back to the
+    initial state (stale carried values in its buffers) and stepped again, with an autotune in
+    between (its first-stage launches write the next launch's buffer), equals a fresh solver bit
+    for bit, with long SAA delays and AT order 3 so the carried values are read from step 3 on.
+    The decomposition is set back to the default after the autotune: another one may reduce the
+    species sums in another order."""
+    case, w0 = gen.case_c1(E=48, order_p=2, n_pe=6, mech=mech, Lx=0.01 * 48 / 2048, at_order=3,
+                           pmf=(0.1, 0.3, 0.3, 0.3))
+    case["disc"]["rk"] = rk
+    fresh = adg.Solver(case)
+    fresh.set_state(w0)
+    fresh.step(12)
+    ref = fresh.state()
+    fresh.close()
+    s = adg.Solver(case)
+    s.set_state(w0)
+    s.step(9)
+    s.set_state(w0)
+    s.step(5)
+    s.autotune(2)
+    s.set_kernel_config(0)
+    s.step(7)
+    np.testing.assert_array_equal(s.state(), ref)
+    assert s.step_count() == 12
+    s.close()
+
+
 SPECIES_SETS = {
     5: ["A2", "B2", "A", "AB", "Z"],
     12: ["A2", "B2", "A", "B", "AB", "A2B", "AB2", "A2B2", "A3", "B3", "A3B", "Z"],
