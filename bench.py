@@ -362,11 +362,14 @@ def hbm_points(steps: int = 20):
     the limiter, the C2 physics at E = 2^21 with it), each with its roofline against 8 TB/s: mean
     launch time from HIP events over graph-replayed steps on the solver's stream."""
     out = {}
-    for key, res, kernel in (("c0_physics_E4194304", sweep_euler([2**22], steps)[0], "euler_stage_kernel"),
-                             ("c2_physics_E2097152", sweep_limiter([2**21], steps)[0], "euler_lim_kernel")):
+    for key, res, kernel, tkey in (("c0_physics_E4194304", sweep_euler([2**22], steps)[0], "euler_stage_kernel",
+                                    "c0_4194304"),
+                                   ("c2_physics_E2097152", sweep_limiter([2**21], steps)[0], "euler_lim_kernel",
+                                    "c2_2097152")):
         out[key] = {"n_elem": res["n_elem"], "dof": res["dof"], "launch_ms": res["stage_ms"],
                     "roofline": {"bound": "hbm", "kernel": kernel, "achieved": res["GBps"], "peak": HBM_PEAK_GBS,
-                                 "unit": "GB/s", "frac": res["frac_hbm"], "bytes_per_launch": res["bytes"]}}
+                                 "unit": "GB/s", "frac": res["frac_hbm"], "bytes_per_launch": res["bytes"],
+                                 "traffic": read_traffic(tkey, ["adg_euler.hip", "adg_device.hpp"])}}
     return out
 
 
