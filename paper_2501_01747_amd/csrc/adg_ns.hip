@@ -464,25 +464,48 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     sWc[v][fl] = wc;
     if (i < 0 || sK[fl] == 0) sWa[v][fl] = wc;
   }
-  //    Beside them, the species sums of the mixture chain, one lane per (point, sum): the
-  //    internal energy e(T) = sum_i Y_i R_i [T (a_i0 - 1 + T (a_i1/2 + ...)) + a_i5] is one
-  //    quintic in T whose coefficients are rho^-1 sum_i rho_i R_i (a_i0 - 1), ..., and
-  //    R = rho^-1 sum_i rho_i R_i; row 7 holds 1/rho, u and e* = E/rho - u^2/2.
-  for (int idx = t; idx < 8 * NP; idx += NTH) {
-    const int q = idx / NP, p = idx % NP;
-    int vs;
-    const double *vrow = values(p, vs);
-    if (q == 7) {
-      const double rho_inv = 1.0 / vrow[0];
-      const double u = vrow[vs] * rho_inv;
-      sRinv[p] = rho_inv;
-      sU[p] = u;
-      sMix[7][p] = vrow[2 * vs] * rho_inv - 0.5 * u * u;
-    } else {
-      double sum = 0.0;
+  //    Beside them, the species sums of the mixture chain: the internal energy
+  //    e(T) = sum_i Y_i R_i [T (a_i0 - 1 + T (a_i1/2 + ...)) + a_i5] is one quintic in T whose
+  //    coefficients are rho^-1 sum_i rho_i R_i (a_i0 - 1), ..., and R = rho^-1 sum_i rho_i R_i
+  //    (rows 0..6); row 7 holds e* = E/rho - u^2/2 (with 1/rho and u beside it).  One lane per
+  //    (point, row) when the workgroup has a lane for each; else one per (point, rows g and
+  //    g + 4), reading the point's species once for both.
+  auto mixture_row7 = [&](int p, const double *vrow, int vs) {
+    const double rho_inv = 1.0 / vrow[0];
+    const double u = vrow[vs] * rho_inv;
+    sRinv[p] = rho_inv;
+    sU[p] = u;
+    sMix[7][p] = vrow[2 * vs] * rho_inv - 0.5 * u * u;
+  };
+  if constexpr (8 * NP <= NTH) {
+    if (t < 8 * NP) {
+      const int q = t / NP, p = t % NP;
+      int vs;
+      const double *vrow = values(p, vs);
+      if (q == 7) {
+        mixture_row7(p, vrow, vs);
+      } else {
+        double sum = 0.0;
 #pragma unroll
-      for (int i = 0; i < NS; ++i) sum += vrow[(3 + i) * vs] * mk->ek[i][q];
-      sMix[q][p] = sum;
+        for (int i = 0; i < NS; ++i) sum += vrow[(3 + i) * vs] * mk->ek[i][q];
+        sMix[q][p] = sum;
+      }
+    }
+  } else {
+    for (int idx = t; idx < 4 * NP; idx += NTH) {
+      const int g = idx / NP, p = idx % NP;
+      int vs;
+      const double *vrow = values(p, vs);
+      double lo = 0.0, hi = 0.0;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const double x = vrow[(3 + i) * vs];
+        lo += x * mk->ek[i][g];
+        if (g < 3) hi += x * mk->ek[i][g + 4];
+      }
+      sMix[g][p] = lo;
+      if (g < 3) sMix[g + 4][p] = hi;
+      else mixture_row7(p, vrow, vs);
     }
   }
   __syncthreads();
@@ -494,24 +517,39 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   //    tabulated A_r = sum_j (2j+1) P_j(xi_r), B_r = sum_j (-1)^j (2j+1) P_j(xi_r) and
   //    G_rk = sum_j (2j+1) P_j(xi_r) D_jk.  Since D_j0 = 1 - (-1)^j, A_r - B_r = G_r0 and the mean
   //    cancels: the mixed path forms the face terms against it in FP64 and the rest in FP32.
-  for (int idx = t; idx < V * NP; idx += NTH) {
-    const int v = idx / NP, p = idx % NP;
-    int lq, r;
-    point_slot(p, lq, r);
-    double d;
-    if constexpr (kMixed) {
-      const double m0 = sW[v * M][lq + 1];
-      OpT vol = 0;
+  //    A lane forms the gradients of VPL variables (v, v + VH, ...) at its point, reading the
+  //    point's table row once: two when one variable per lane would take more than one pass.
+  {
+    constexpr int VPL = V * NP > NTH ? 2 : 1;
+    constexpr int VH = (V + VPL - 1) / VPL;
+    for (int idx = t; idx < VH * NP; idx += NTH) {
+      const int h = idx / NP, p = idx % NP;
+      int lq, r;
+      point_slot(p, lq, r);
+      double gd[M];
 #pragma unroll
-      for (int k = 1; k < M; ++k) vol += (OpT)sGD[r][k] * (OpT)sW[v * M + k][lq + 1];
-      d = a.inv_dx * (sGA[r] * (sWa[v][lq + 1] - m0) - sGB[r] * (sWa[v][lq] - m0) - (double)vol);
-    } else {
-      double vol = 0.0;
+      for (int k = 0; k < M; ++k) gd[k] = sGD[r][k];
+      const double ga = sGA[r], gb = sGB[r];
 #pragma unroll
-      for (int k = 0; k < M; ++k) vol += sGD[r][k] * sW[v * M + k][lq + 1];
-      d = a.inv_dx * (sGA[r] * sWa[v][lq + 1] - sGB[r] * sWa[v][lq] - vol);
+      for (int u = 0; u < VPL; ++u) {
+        const int v = h + u * VH;
+        if (v >= V) break;
+        double d;
+        if constexpr (kMixed) {
+          const double m0 = sW[v * M][lq + 1];
+          OpT vol = 0;
+#pragma unroll
+          for (int k = 1; k < M; ++k) vol += (OpT)gd[k] * (OpT)sW[v * M + k][lq + 1];
+          d = a.inv_dx * (ga * (sWa[v][lq + 1] - m0) - gb * (sWa[v][lq] - m0) - (double)vol);
+        } else {
+          double vol = 0.0;
+#pragma unroll
+          for (int k = 0; k < M; ++k) vol += gd[k] * sW[v * M + k][lq + 1];
+          d = a.inv_dx * (ga * sWa[v][lq + 1] - gb * sWa[v][lq] - vol);
+        }
+        sDx[v][p] = d;
+      }
     }
-    sDx[v][p] = d;
   }
   __syncthreads();
 
