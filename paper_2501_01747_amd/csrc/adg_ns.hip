@@ -262,8 +262,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       if (a.at_in) {
         // carried from the previous launch: no dependence on the interface index
         if (f >= 0 && f <= E) {
-          g_w[0] = a.at_in[(size_t)f * 2 * Vg + gv];
-          g_f[0] = a.at_in[(size_t)f * 2 * Vg + Vg + gv];
+          g_w[0] = a.at_in[(size_t)f * (2 * Vg + 1) + gv];
+          g_f[0] = a.at_in[(size_t)f * (2 * Vg + 1) + Vg + gv];
         }
       } else {
         gfi = f >= 0 && f <= E ? a.face_if[f] : -1;
@@ -295,6 +295,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       }
     }
     int fi = -1;
+    double kc = 0.0;   // the carried delay of the face
     if (t < NF) {
       int f = e0 - 1 + t;
       if (periodic) {
@@ -302,6 +303,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
         while (f >= E) f -= E;
       }
       fi = f >= 0 && f <= E ? a.face_if[f] : -1;
+      if (a.at_in && f >= 0 && f <= E) kc = a.at_in[(size_t)f * (2 * Vg + 1) + 2 * Vg];
     }
 #pragma unroll
     for (int m = 0; m < kOut; ++m) {
@@ -342,7 +344,9 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     }
     if (t < NF) {
       sI[t] = fi;
-      sK[t] = fi >= 0 ? eff_delay(a.dl, n, fi) : 0;
+      // carried: the previous launch drew it (a step before q, which has no predecessor after a
+      // reset, has only zero delays)
+      sK[t] = fi < 0 ? 0 : a.at_in ? (n >= q_at ? (int)kc : 0) : eff_delay(a.dl, n, fi);
     }
   }
   const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
@@ -579,6 +583,8 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const long long n2 = n + (last ? 1 : 0);
       const int s2 = last ? 0 : stage + 1;
       const int k2 = eff_delay(a.dl, n2, i);
+      const size_t base = (size_t)(e0 + fo) * (2 * Vg + 1);
+      if (v == 0) a.at_out[base + 2 * Vg] = (double)k2;
       if (k2 > 0) {
         const int nm2 = step_mod(n2, a.ring.D);
         double w[4], f[4];
@@ -590,7 +596,6 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
         }
         double acw, acf;
         at_combine(a, q_at, k2, nm2, s2, i, v, w, f, acw, acf);
-        const size_t base = (size_t)(e0 + fo) * 2 * Vg;
         a.at_out[base + v] = acw;
         a.at_out[base + Vg + v] = acf;
       }

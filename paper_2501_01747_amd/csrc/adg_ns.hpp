@@ -71,9 +71,10 @@ struct NsArgs {
   long long target;     // batched launches skip the instance once its step reaches it
   const void *mech;     // NsMechT<capacity> of the kernel that runs the problem
   // AT combinations carried between launches (single problems; nullptr: gathered in the launch).
-  // Per face f: [f * 2 Vg, +Vg) the AT central traces, [+Vg, +2 Vg) the AT fluxes, Vg = 3 + ns.
-  // at_in holds this launch's values (written by the previous launch), at_out receives the next
-  // launch's (stage + 1 of this step, or stage 0 of the next; nst stages per step).
+  // Record of face f at f * (2 Vg + 1), Vg = 3 + ns: [0, Vg) the AT central traces, [Vg, 2 Vg)
+  // the AT fluxes, [2 Vg] the delay (PE-interface faces).  at_in holds this launch's values
+  // (written by the previous launch), at_out receives the next launch's (stage + 1 of this
+  // step, or stage 0 of the next; nst stages per step).
   const double *at_in;
   double *at_out;
   int nst;

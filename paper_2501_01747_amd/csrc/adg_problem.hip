@@ -217,7 +217,7 @@ bool make_layout(const adg_physics *ph, const adg_discretization *d, const adg_a
   L.mech = off;   off += ph->model == ADG_DETAILED ? align256(ns_mech_bytes(ph->n_species)) : 0;
   // the AT combinations carried from launch to launch (two buffers of (E + 1) faces x 2 Vg)
   L.carry_at = !batched && ph->model == ADG_DETAILED && L.nif > 0;
-  L.at = off;     off += L.carry_at ? 2 * align256(sizeof(double) * (size_t)(L.E + 1) * 2 * (3 + ph->n_species)) : 0;
+  L.at = off;     off += L.carry_at ? 2 * align256(sizeof(double) * (size_t)(L.E + 1) * (2 * (3 + ph->n_species) + 1)) : 0;
   L.total = off;
   return true;
 }
@@ -261,7 +261,7 @@ adg_status setup_problem(const adg_physics *phys, const adg_discretization *disc
   P.ring = (double *)(base + L.ring);
   if (L.carry_at) {
     P.at = (double *)(base + L.at);
-    P.at_stride = align256(sizeof(double) * (size_t)(L.E + 1) * 2 * (3 + phys->n_species)) / sizeof(double);
+    P.at_stride = align256(sizeof(double) * (size_t)(L.E + 1) * (2 * (3 + phys->n_species) + 1)) / sizeof(double);
   }
 
   const bool periodic = disc->bc == ADG_PERIODIC;
