@@ -302,7 +302,8 @@ def bench_batched(steps: int, warmup: int, graph: int, precision: str = "mixed",
 C4_RATE = 16.0   # 0.7 x 22.94 requests/s measured with --calibrate --requests 300
 
 
-def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, precision: str):
+def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, precision: str,
+                group_streams: int | None = None):
     """Served stream of n_req requests (half ignition, half reacting shock; E log-uniform in
     [256, 65536], N_p in {1..4}, 100-2000 steps) arriving as a Poisson process at `rate`
     requests/s (all at t = 0 when rate is None: the saturation measurement)."""
@@ -318,6 +319,8 @@ def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, preci
     reqs = [Request(r["rid"], r["case"], r["w0"], r["steps"], r["arrival"]) for r in raw]
     t_gen = time.perf_counter() - t_gen
     b = adg.Batch(slots, 1 << 27, int(heap_gib * 2**30), precision=precision)
+    if group_streams:
+        b.set_group_streams(group_streams)
     srv = Server(b, chunk=chunk)
     torch.cuda.synchronize()
     res = srv.run(reqs)
@@ -456,6 +459,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision measurement")
     ap.add_argument("--batch-steps", type=int, default=60, help="timed steps of the batched workload")
     ap.add_argument("--precision", default="mixed", help="batched workload precision: mixed | fp64")
+    ap.add_argument("--group-streams", type=int, default=None,
+                    help="served stream: streams a stage's group launches are spread over (1..4; default 4)")
     ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
     ap.add_argument("--rate", type=float, default=None, help="served stream: arrival rate (requests/s)")
     ap.add_argument("--calibrate", action="store_true", help="served stream: saturation run (all arrive at t=0)")
@@ -494,9 +499,9 @@ def main():
         if rate is None and not args.calibrate:
             raise SystemExit("no arrival rate: run with --calibrate first or pass --rate")
         out = bench_serve(args.requests, rate, args.serve_heap_gib, args.serve_slots, args.serve_chunk,
-                          args.precision)
+                          args.precision, args.group_streams)
         out.update({"metric": METRIC, "workload": "c4_served_stream", "n_gpus": 1, "data": "synthetic",
-                    "saturation_run": bool(args.calibrate)})
+                    "saturation_run": bool(args.calibrate), "group_streams": args.group_streams or 4})
         if args.calibrate:
             out["calibrated_rate_req_per_s"] = 0.7 * out["requests_per_s"]
         print(json.dumps(out), flush=True)

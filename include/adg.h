@@ -353,6 +353,17 @@ adg_status adg_batch_autotune(adg_batch *b, int32_t n_reps, int32_t *choice);
    step on.  Results do not depend on it beyond the order of floating-point sums. */
 adg_status adg_batch_set_kernel_config(adg_batch *b, int32_t config);
 
+/* Spread each RK stage's launches (one per group: the detailed-chemistry
+   instances, and one per (order, flux, limiter) class of one-step instances)
+   over `streams` streams (1..4; ADG_ERR_ARG otherwise): the batch's stream and
+   up to three more of the default priority, created by the library on first
+   use and joined back into the batch's stream before the next stage.  Groups
+   touch disjoint instances, so results do not depend on it; with several
+   groups the smaller launches overlap the larger ones instead of waiting for
+   them.  Default 4; 1 launches everything on the batch's stream.  A captured
+   graph is re-captured at the next step. */
+adg_status adg_batch_set_group_streams(adg_batch *b, int32_t streams);
+
 /* Number of admitted instances. */
 int32_t adg_batch_active(const adg_batch *b);
 

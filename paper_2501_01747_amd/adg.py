@@ -109,6 +109,7 @@ _sig = {
     "adg_batch_profile": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_int64), C.c_int32]),
     "adg_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int32, _P(C.c_int32)]),
     "adg_batch_set_kernel_config": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "adg_batch_set_group_streams": (C.c_int32, [C.c_void_p, C.c_int32]),
     "adg_batch_active": (C.c_int32, [C.c_void_p]),
     "adg_batch_free_bytes": (C.c_int64, [C.c_void_p]),
     "adg_batch_destroy": (None, [C.c_void_p]),
@@ -409,6 +410,10 @@ class Batch:
     def set_decomposition(self, config: int):
         """Use the batched kernel's work decomposition `config` (autotune's numbering)."""
         self._check(adg_batch_set_kernel_config(self.h, int(config)))
+
+    def set_group_streams(self, streams: int):
+        """Spread each stage's group launches over `streams` streams (1..4)."""
+        self._check(adg_batch_set_group_streams(self.h, int(streams)))
 
     def profile(self, n_steps: int) -> dict:
         k = len(BATCH_PROFILE_CLASSES)

@@ -42,6 +42,8 @@ struct Slot {
 // then read the same few kilobytes, which stay in every L2).
 constexpr int kBatchMechs = 16;
 
+constexpr int kGroupStreams = 4;
+
 struct Group {
   int kind;  // 0 detailed stage, 1 one-step stage
   int M, flux;
@@ -85,6 +87,12 @@ struct adg_batch {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
+  // launches of a stage's groups spread over the batch's stream and up to kGroupStreams - 1
+  // extra streams (default priority), joined before the next stage; 1 = all on one stream
+  int group_streams = kGroupStreams;
+  hipStream_t aux[kGroupStreams - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kGroupStreams - 1] = {};
   std::vector<hipEvent_t> prof_events;
   std::vector<int> prof_class;
   std::string msg;
@@ -192,9 +200,33 @@ void rebuild_tiles(adg_batch *b) {
                   [&](const Slot &s) { return euler_blocks(s.P.lay.E, lim != 0); });
 }
 
+// The extra streams and events of concurrent group launches, created on first use.
+adg_status ensure_group_streams(adg_batch *b) {
+  if (b->fork) return ADG_OK;
+  for (int k = 0; k < kGroupStreams - 1; ++k) {
+    BHIP(b, hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking));
+    BHIP(b, hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+  }
+  BHIP(b, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  return ADG_OK;
+}
+
 adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
+  // a stage's groups touch disjoint instances: with several groups they may run side by side
+  // (group k on stream k mod S, the first on st), every stream joined back before the next stage
+  const int nstreams = timed ? 1 : std::min<int>(b->group_streams, (int)b->groups.size());
+  if (nstreams > 1) {
+    adg_status rc = ensure_group_streams(b);
+    if (rc != ADG_OK) return rc;
+  }
   for (int stage = 0; stage < 3; ++stage) {
-    for (const Group &g : b->groups) {
+    if (nstreams > 1) {
+      BHIP(b, hipEventRecord(b->fork, st));
+      for (int k = 1; k < nstreams; ++k) BHIP(b, hipStreamWaitEvent(b->aux[k - 1], b->fork, 0));
+    }
+    for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+      const Group &g = b->groups[gi];
+      const hipStream_t gs = nstreams > 1 && gi % nstreams ? b->aux[gi % nstreams - 1] : st;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {
         BHIP(b, hipEventCreate(&e0));
@@ -202,9 +234,9 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
       }
       if (g.kind == 0) {
         BHIP(b, launch_ns_batch(b->d_ns, b->d_tiles + g.off, g.n, stage, b->par, b->precision == ADG_MIXED_FP32,
-                                g.M, b->tile_elems, st));
+                                g.M, b->tile_elems, gs));
       } else {
-        BHIP(b, launch_euler_batch(g.M, g.flux, g.lim, b->d_eu, b->d_tiles + g.off, g.n, stage, b->par, st));
+        BHIP(b, launch_euler_batch(g.M, g.flux, g.lim, b->d_eu, b->d_tiles + g.off, g.n, stage, b->par, gs));
       }
       if (timed) {
         BHIP(b, hipEventCreate(&e1));
@@ -212,6 +244,12 @@ adg_status enqueue_batch_step(adg_batch *b, hipStream_t st, bool timed) {
         b->prof_events.push_back(e0);
         b->prof_events.push_back(e1);
         b->prof_class.push_back(g.kind);
+      }
+    }
+    if (nstreams > 1) {
+      for (int k = 1; k < nstreams; ++k) {
+        BHIP(b, hipEventRecord(b->join[k - 1], b->aux[k - 1]));
+        BHIP(b, hipStreamWaitEvent(st, b->join[k - 1], 0));
       }
     }
   }
@@ -618,7 +656,25 @@ void adg_batch_destroy(adg_batch *b) {
   (void)hipStreamSynchronize(b->stream);
   destroy_batch_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (int k = 0; k < kGroupStreams - 1; ++k) {
+    if (b->aux[k]) {
+      (void)hipStreamSynchronize(b->aux[k]);
+      (void)hipStreamDestroy(b->aux[k]);
+    }
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
+}
+
+adg_status adg_batch_set_group_streams(adg_batch *b, int32_t streams) {
+  if (!b) return ADG_ERR_ARG;
+  if (streams < 1 || streams > kGroupStreams) return bfail(b, ADG_ERR_ARG, "group streams out of range");
+  if (streams != b->group_streams) {
+    b->group_streams = streams;
+    destroy_batch_graph(b);   // captured with the old spread
+  }
+  return ADG_OK;
 }
 
 const char *adg_batch_last_error(const adg_batch *b) { return b ? b->msg.c_str() : "null batch"; }

@@ -124,6 +124,27 @@ def test_alone_equals_in_the_mix(adg, mech, precision):
     np.testing.assert_array_equal(wa, wm)
 
 
+@pytest.mark.parametrize("graph", [0, 3])
+def test_group_streams_do_not_change_results(adg, mech, graph):
+    """A batch of detailed and one-step instances (several one-step classes) stepped with every
+    stage's group launches on one stream and spread over four: the same states bit for bit, with
+    plain steps and with captured graphs (7 steps: two replays of 3 and one plain step)."""
+    cases = mixed_cases(mech) + onestep_cases()
+    states = []
+    for streams in (1, 4):
+        b = make_batch(adg, cases, "fp64")
+        b.set_group_streams(streams)
+        if graph:
+            b.set_graph(graph)
+        slots = [b.add(*c) for c in cases]
+        b.step(7)
+        states.append([b.state(sl) for sl in slots])
+        b.close()
+    print(f"[group streams] graph {graph}: {len(cases)} instances", flush=True)
+    for a, c in zip(*states):
+        np.testing.assert_array_equal(a, c)
+
+
 def restrict_to_coarse(w_fine, order_p):
     """L2 projection of a piecewise polynomial on 2E elements onto E elements (modal, P_j(1) = 1)."""
     from numpy.polynomial import legendre as npleg
