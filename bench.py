@@ -303,7 +303,7 @@ C4_RATE = 16.0   # 0.7 x 22.94 requests/s measured with --calibrate --requests 3
 
 
 def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, precision: str,
-                group_streams: int | None = None):
+                group_streams: int | None = None, graph_steps: int = 0):
     """Served stream of n_req requests (half ignition, half reacting shock; E log-uniform in
     [256, 65536], N_p in {1..4}, 100-2000 steps) arriving as a Poisson process at `rate`
     requests/s (all at t = 0 when rate is None: the saturation measurement)."""
@@ -321,7 +321,7 @@ def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, preci
     b = adg.Batch(slots, 1 << 27, int(heap_gib * 2**30), precision=precision)
     if group_streams:
         b.set_group_streams(group_streams)
-    srv = Server(b, chunk=chunk)
+    srv = Server(b, chunk=chunk, graph_steps=graph_steps)
     torch.cuda.synchronize()
     res = srv.run(reqs)
     b.close()
@@ -339,7 +339,8 @@ def bench_serve(n_req: int, rate, heap_gib: float, slots: int, chunk: int, preci
                              "p99_latency_s": float(np.percentile(lat, 99))}
     out.update({"failed_by_kind_order": fails, "latency_by_kind": by_kind, "rate_req_per_s": rate, "heap_gib": heap_gib, "slots": slots, "chunk": chunk,
                 "precision": precision, "rounds": srv.rounds, "max_active": srv.max_active,
-                "input_generation_s": t_gen, "loop_seconds": srv.time_in})
+                "input_generation_s": t_gen, "loop_seconds": srv.time_in, "graph_steps": graph_steps,
+                "group_streams": group_streams or 4})
     return out
 
 
@@ -378,10 +379,10 @@ def hbm_points(steps: int = 20):
 
 def served_short(n_req: int, rate: float, precision: str):
     """A short served stream (n_req requests at the fixed arrival rate) for the default line."""
-    out = bench_serve(n_req, rate, 16.0, 1024, 10, precision)
+    out = bench_serve(n_req, rate, 16.0, 1024, 10, precision, graph_steps=2)
     keep = ("requests", "completed_ok", "failed", "p50_latency_s", "p99_latency_s", "mean_latency_s", "mean_queue_s",
             "makespan_s", "requests_per_s", "dof_updates_per_s", "latency_by_kind", "rate_req_per_s", "max_active",
-            "rounds", "precision", "loop_seconds")
+            "rounds", "precision", "loop_seconds", "graph_steps", "group_streams")
     return {k: out[k] for k in keep}
 
 
@@ -459,6 +460,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision measurement")
     ap.add_argument("--batch-steps", type=int, default=60, help="timed steps of the batched workload")
     ap.add_argument("--precision", default="mixed", help="batched workload precision: mixed | fp64")
+    ap.add_argument("--serve-graph", type=int, default=2,
+                    help="served stream: steps per captured batch graph (0: plain launches)")
     ap.add_argument("--group-streams", type=int, default=None,
                     help="served stream: streams a stage's group launches are spread over (1..4; default 4)")
     ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
@@ -499,9 +502,9 @@ def main():
         if rate is None and not args.calibrate:
             raise SystemExit("no arrival rate: run with --calibrate first or pass --rate")
         out = bench_serve(args.requests, rate, args.serve_heap_gib, args.serve_slots, args.serve_chunk,
-                          args.precision, args.group_streams)
+                          args.precision, args.group_streams, args.serve_graph)
         out.update({"metric": METRIC, "workload": "c4_served_stream", "n_gpus": 1, "data": "synthetic",
-                    "saturation_run": bool(args.calibrate), "group_streams": args.group_streams or 4})
+                    "saturation_run": bool(args.calibrate)})
         if args.calibrate:
             out["calibrated_rate_req_per_s"] = 0.7 * out["requests_per_s"]
         print(json.dumps(out), flush=True)

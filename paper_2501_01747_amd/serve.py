@@ -62,8 +62,13 @@ class Server:
     interface); `clock` returns seconds; `sleep` waits."""
 
     def __init__(self, batch, chunk: int = 10, keep_states: bool = False, clock=time.perf_counter,
-                 sleep=time.sleep, nomem_code: int = -2):
+                 sleep=time.sleep, nomem_code: int = -2, graph_steps: int = 0):
         self.batch = batch
+        # graph_steps > 0: the batch replays captured graphs of that many steps (captured again
+        # only when the composition changes: most rounds keep the previous round's), so a round
+        # costs a few graph launches instead of every launch and stream join of its steps
+        if graph_steps > 0:
+            batch.set_graph(graph_steps)
         self.chunk = int(chunk)
         self.keep_states = keep_states
         self.clock = clock

@@ -29,19 +29,21 @@ def small_stream(n=16, rate=None):
     return reqs
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_served_equals_alone(adg, precision):
+@pytest.mark.parametrize("precision,graph_steps", [("mixed", 0), ("fp64", 0), ("mixed", 2)])
+def test_served_equals_alone(adg, precision, graph_steps):
+    """With graph_steps = 2 the rounds replay captured two-step graphs of the batch, captured
+    again whenever an admission or a retirement changes its composition."""
     from paper_2501_01747_amd.serve import Server, summarize
 
     reqs = small_stream()
     foot = [adg.Batch.instance_bytes(r.case) for r in reqs]
     # every request arrives at t = 0 and there is room for about a third of them at once
     b = adg.Batch(8, 1 << 20, sum(foot) // 3, precision=precision)
-    srv = Server(b, chunk=6, keep_states=True)
+    srv = Server(b, chunk=6, keep_states=True, graph_steps=graph_steps)
     res = srv.run(reqs)
     b.close()
     s = summarize(res)
-    print(f"[serve] {precision} {s} rounds={srv.rounds} max_active={srv.max_active}", flush=True)
+    print(f"[serve] {precision} graph {graph_steps} {s} rounds={srv.rounds} max_active={srv.max_active}", flush=True)
     assert s["failed"] == 0 and 1 < srv.max_active < len(reqs)
     assert any(r.admitted > r.arrival for r in res[3:])           # all arrive at once: some wait for space
     for q, r in zip(reqs, res):
