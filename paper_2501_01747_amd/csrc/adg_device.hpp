@@ -44,7 +44,13 @@ __device__ __forceinline__ int step_mod(long long n, int d) {
 }
 
 // Delay at PE interface i for time step n (Sec. 4), clamped so that all q
-// levels n-k .. n-k-q+1 exist.
+// levels n-k .. n-k-q+1 exist.  BRANCH_FREE: the SAA bin is counted over all
+// kMaxL - 1 bin edges with the loads of every edge issued together (the
+// detailed-chemistry load phase, where the draw sits between the loads and the
+// barrier); otherwise the bins are searched in order (the one-step kernels,
+// where most draws end at the first edges).  Both give the same bin: the first
+// j with u < cum[j] (cum is non-decreasing), at most L - 1.
+template <bool BRANCH_FREE = false>
 __device__ __forceinline__ int eff_delay(const DelayParams &d, long long n, int i) {
   int k = 0;
   if (d.mode == 1) {
@@ -53,11 +59,14 @@ __device__ __forceinline__ int eff_delay(const DelayParams &d, long long n, int 
     unsigned long long ctr = (unsigned long long)n * (unsigned long long)d.nif + (unsigned long long)i;
     unsigned long long z = splitmix64(d.seed ^ (ctr * 0x9E3779B97F4A7C15ull));
     double u = (double)(z >> 11) * 0x1.0p-53;
-    // the first j with u < cum[j] (cum is non-decreasing), at most L - 1: the number of
-    // j < L - 1 with cum[j] <= u, counted without a data-dependent loop
-    k = 0;
+    if constexpr (BRANCH_FREE) {
 #pragma unroll
-    for (int j = 0; j < kMaxL - 1; ++j) k += (j < d.L - 1 && u >= d.cum[j]) ? 1 : 0;
+      for (int j = 0; j < kMaxL - 1; ++j) k += (j < d.L - 1 && u >= d.cum[j]) ? 1 : 0;
+    } else {
+      k = d.L - 1;
+      for (int j = 0; j < d.L; ++j)
+        if (u < d.cum[j]) { k = j; break; }
+    }
   } else if (d.mode == 3) {
     k = d.sched[(long long)step_mod(n, d.sched_steps) * d.nif + i];
   }

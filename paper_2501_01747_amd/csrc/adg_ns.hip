@@ -316,7 +316,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     // levels 0..3 of the gather item (a level past q reads level n-k with weight 0); they land
     // while the LDS stores, the barrier and the traces proceed
     if (gfi >= 0) {
-      const int k = eff_delay(a.dl, n, gfi);
+      const int k = eff_delay<true>(a.dl, n, gfi);
       if (k > 0) {
         const int nm = step_mod(n, a.ring.D);
 #pragma unroll
@@ -346,7 +346,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       sI[t] = fi;
       // carried: the previous launch drew it (a step before q, which has no predecessor after a
       // reset, has only zero delays)
-      sK[t] = fi < 0 ? 0 : a.at_in ? (n >= q_at ? (int)kc : 0) : eff_delay(a.dl, n, fi);
+      sK[t] = fi < 0 ? 0 : a.at_in ? (n >= q_at ? (int)kc : 0) : eff_delay<true>(a.dl, n, fi);
     }
   }
   const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
@@ -582,7 +582,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const bool last = stage == a.nst - 1;
       const long long n2 = n + (last ? 1 : 0);
       const int s2 = last ? 0 : stage + 1;
-      const int k2 = eff_delay(a.dl, n2, i);
+      const int k2 = eff_delay<true>(a.dl, n2, i);
       const size_t base = (size_t)(e0 + fo) * (2 * Vg + 1);
       if (v == 0) a.at_out[base + 2 * Vg] = (double)k2;
       if (k2 > 0) {
