@@ -418,6 +418,52 @@ def sweep_euler(sizes, steps=20):
     return out
 
 
+def sweep_ns(sizes, steps=20):
+    """Size sweep of the single-problem detailed-chemistry stage kernel: the ignition workload's
+    physics at its element width (1 cm / 2048) and PE density (one PE per 128 elements), E
+    elements (the 2048-element state repeated, a periodic domain of E/2048 cm), N_p = 3; per
+    size the decomposition the autotuner keeps, the mean launch time (HIP events over
+    graph-replayed steps) and the algorithmic FP64 rate against the 78.6 TFLOP/s peak."""
+    import numpy as np
+    import torch
+
+    from paper_2501_01747_amd import adg
+    from workloads import gen
+
+    mech = gen.c1_mechanism()
+    _, base = gen.case_c1(mech=mech)
+    out = []
+    for E in sizes:
+        if E >= 2048:
+            case, _ = gen.case_c1(E=2048, mech=mech, n_pe=16)
+            case["disc"]["n_elem"] = E
+            case["disc"]["x_right"] = case["disc"]["x_left"] + 0.01 * E / 2048
+            case["async"]["n_pe"] = E // 128
+            w0 = np.ascontiguousarray(np.tile(base, (E // 2048, 1, 1)))
+        else:
+            case, w0 = gen.case_c1(E=E, Lx=0.01 * E / 2048, n_pe=max(1, E // 128), mech=mech)
+        s = adg.Solver(case)
+        s.set_state(w0)
+        cfg = s.autotune()
+        s.set_state(w0)
+        ms = region_stage_ms(s, steps)
+        flops = detailed_stage_flops(case)
+        try:
+            s.sync()              # raises if the run latched a state error
+            state_ok = True
+        except Exception:
+            state_ok = False
+        out.append({"n_elem": E, "dof": gen.dof(case), "n_pe": case["async"]["n_pe"], "kernel_config": cfg,
+                    "stage_ms": ms, "TFLOPs": flops / (ms * 1e-3) / 1e12,
+                    "frac_fp64": flops / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                    "steps": s.step_count(), "state_ok": state_ok})
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        print(json.dumps(out[-1]), flush=True)
+    return out
+
+
 def sweep_limiter(sizes, steps=20):
     """Size sweep of the one-step stage kernel with the limiter inside (the detonation
     workload's physics at its resolution dx = 1/32, N_p = 3, HLLC, KXRCF + AT-WENO, 64 PEs):
@@ -452,6 +498,8 @@ def main():
     ap.add_argument("--graph", type=int, default=50, help="time steps per captured HIP graph (0 = plain launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured copy / FP64 ceilings")
+    ap.add_argument("--sweep-ns", action="store_true",
+                    help="print the single-problem detailed-chemistry stage-kernel size sweep instead of the benchmark line")
     ap.add_argument("--sweep-euler", action="store_true",
                     help="print the one-step stage-kernel size sweeps (without and with the limiter) instead of the benchmark line")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -511,6 +559,10 @@ def main():
         return
     if args.pmc_probe:
         pmc_probe(args)
+        return
+    if args.sweep_ns:
+        print(json.dumps({"sweep": "ns_stage_kernel", "results": sweep_ns([2**p for p in range(11, 21, 1)])}),
+              flush=True)
         return
     if args.sweep_euler:
         print(json.dumps({"sweep": "euler_stage_kernel", "results": sweep_euler([2**p for p in range(10, 24, 1)])}),
