@@ -224,8 +224,10 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   bool ok = true;
 
   // 0. mechanism, operator tables, state of the tile and its halo, PE-interface data of the
-  //    faces.  Every global load is issued first, and nothing before them depends on a loaded
-  //    value (the step counter included), so the phase costs about one memory latency.
+  //    faces, then the traces, the nodal values and the AT combinations of past levels
+  //    (Eq. (7)) formed from the loaded registers.  Every global load is issued first, and
+  //    nothing before them depends on a loaded value (the step counter included), so the
+  //    phase costs about one memory latency plus the arithmetic of its lanes.
   constexpr int kOut = (V * M * TE + NTH - 1) / NTH;
   // the second operand of the RK combination (w^n, or the 2N register) of the outputs
   // this thread writes in the last phase
@@ -233,27 +235,29 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const double *prev = rk.two_n ? kbuf : w0;
   double w0pre[kOut];
   long long n;
-  // the history gather of this lane (at most one item per lane): variable t / NF at face t % NF;
-  // its loads are issued in the load phase, their AT combination formed in the next
+  // the element item of this lane (at most one per lane): variable t / NH of local element
+  // t % NH (element e0 - 2 + t % NH); it loads the element's modes and forms its traces and,
+  // inside the tile, its nodal values
+  static_assert(V * NH <= NTH, "one element item per lane");
+  // the history gather of this lane (at most one item per lane): variable t / NF at face t % NF
   static_assert(V * NF <= NTH, "one history gather item per lane");
-  double g_w[4], g_f[4];
   {
     constexpr int nwords = (int)(sizeof(NsMechT<NS>) / 8);
     constexpr int kMw = (nwords + NTH - 1) / NTH;
     constexpr int twords = (int)(sizeof(Tables) / 8);
     constexpr int kTw = (twords + NTH - 1) / NTH;
-    constexpr int kSw = (V * M * NH + NTH - 1) / NTH;
     const unsigned long long *src = reinterpret_cast<const unsigned long long *>(a.mech);
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(&smech);
     const unsigned long long *tsrc = reinterpret_cast<const unsigned long long *>(&a.tb);
     unsigned long long *tdst = reinterpret_cast<unsigned long long *>(&Ls.sTb);
     unsigned long long mw[kMw], tw[kTw];
-    double sw[kSw];
     // the interface of the gather item's face: loaded first, so the history loads that depend
     // on it need not wait for the state
     const int gv = t / NF, gfl = t % NF;
-    int gfi = -1;
-    if (t < V * NF && gv < Vg) {
+    const bool gather = t < V * NF && gv < Vg;
+    int gfi = -1, gk = 0;
+    double g_w[4], g_f[4];
+    if (gather) {
       int f = e0 - 1 + gfl;
       if (periodic) {
         while (f < 0) f += E;
@@ -279,20 +283,25 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const int idx = t + m * NTH;
       tw[m] = idx < twords ? tsrc[idx] : 0ull;
     }
+    // the element item: at a transmissive end the ghost element beyond a boundary face carries
+    // the interior trace at that face on both of its sides (ghost trace = interior trace), so
+    // its lane loads the interior element; elements further out are never read
+    const int ev = t / NH, el = t % NH;
+    int ghost = 0, esrc = e0 - 2 + el;
+    if (!periodic) {
+      if (esrc < 0) { ghost = esrc == -1 ? 1 : 3; esrc += 1; }
+      else if (esrc >= E) { ghost = esrc == E ? 2 : 3; esrc -= 1; }
+    } else {
+      // within a few periods of [0, E)
+      while (esrc < 0) esrc += E;
+      while (esrc >= E) esrc -= E;
+    }
+    double wl[M];
 #pragma unroll
-    for (int m = 0; m < kSw; ++m) {
-      const int idx = t + m * NTH;
-      sw[m] = 0.0;
-      if (idx < V * M * NH) {
-        const int c = idx / NH, l = idx % NH;
-        int e = e0 - 2 + l;   // periodic: within a few periods of [0, E)
-        if (periodic) {
-          while (e < 0) e += E;
-          while (e >= E) e -= E;
-        }
-        // padded species, and elements past a transmissive end, stay zero
-        if (c < VMg && e >= 0 && e < E) sw[m] = ws[sidx(e, c, VMg)];
-      }
+    for (int j = 0; j < M; ++j) {
+      wl[j] = 0.0;
+      // padded species stay zero
+      if (t < V * NH && ev < Vg && ghost != 3) wl[j] = ws[sidx(esrc, ev * M + j, VMg)];
     }
     int fi = -1;
     double kc = 0.0;   // the carried delay of the face
@@ -308,20 +317,20 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 #pragma unroll
     for (int m = 0; m < kOut; ++m) {
       const int idx = t + m * NTH;
-      const int c = idx / TE, el = idx % TE;
+      const int c = idx / TE, el2 = idx % TE;
       w0pre[m] = 0.0;
-      if (use_prev && idx < V * M * TE && el < nloc && c < VMg) w0pre[m] = prev[sidx(e0 + el, c, VMg)];
+      if (use_prev && idx < V * M * TE && el2 < nloc && c < VMg) w0pre[m] = prev[sidx(e0 + el2, c, VMg)];
     }
     n = a.step[par];
     // levels 0..3 of the gather item (a level past q reads level n-k with weight 0); they land
-    // while the LDS stores, the barrier and the traces proceed
+    // while the element items form their traces and nodal values
     if (gfi >= 0) {
-      const int k = eff_delay<true>(a.dl, n, gfi);
-      if (k > 0) {
+      gk = eff_delay<true>(a.dl, n, gfi);
+      if (gk > 0) {
         const int nm = step_mod(n, a.ring.D);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const double *rec = ring_at(a.ring, ring_slot(nm, k + (j < q_at ? j : 0), a.ring.D), stage, a.dl.nif, gfi);
+          const double *rec = ring_at(a.ring, ring_slot(nm, gk + (j < q_at ? j : 0), a.ring.D), stage, a.dl.nif, gfi);
           g_w[j] = rec[a.ring.off_Wc + gv];
           g_f[j] = rec[a.ring.off_F + gv];
         }
@@ -337,16 +346,66 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const int idx = t + m * NTH;
       if (idx < twords) tdst[idx] = tw[m];
     }
-#pragma unroll
-    for (int m = 0; m < kSw; ++m) {
-      const int idx = t + m * NTH;
-      if (idx < V * M * NH) sW[idx / NH][idx % NH] = sw[m];
-    }
     if (t < NF) {
       sI[t] = fi;
       // carried: the previous launch drew it (a step before q, which has no predecessor after a
       // reset, has only zero delays)
       sK[t] = fi < 0 ? 0 : a.at_in ? (n >= q_at ? (int)kc : 0) : eff_delay<true>(a.dl, n, fi);
+    }
+    // traces of w and values at the nodes of the element item
+    if (t < V * NH) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) sW[ev * M + j][el] = ghost ? 0.0 : wl[j];
+      OpT sm = 0, sp = 0;
+#pragma unroll
+      for (int j = kMixed ? 1 : 0; j < M; ++j) {
+        const OpT c = (OpT)wl[j];
+        sp += c;
+        sm += (j & 1) ? -c : c;
+      }
+      double tm, tp;
+      if constexpr (kMixed) {
+        tm = wl[0] + (double)sm;
+        tp = wl[0] + (double)sp;
+      } else {
+        tm = (double)sm;
+        tp = (double)sp;
+      }
+      if (ghost == 1) tp = tm;
+      else if (ghost == 2) tm = tp;
+      else if (ghost == 3) tm = tp = 0.0;
+      sTm[ev][el] = tm;
+      sTp[ev][el] = tp;
+      if (el >= 2 && el < TE + 2) {
+#pragma unroll
+        for (int qn = 0; qn < Q; ++qn) {
+          OpT xo = 0;
+#pragma unroll
+          for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)a.tb.B[qn][j] * (OpT)wl[j];
+          sX[ev][(el - 2) * Q + qn] = kMixed ? wl[0] + (double)xo : (double)xo;
+        }
+      }
+    }
+    // the AT combinations of the gathered levels, last: their loads have had the longest to
+    // land.  A face that turns out not to be delayed has its entry replaced by the synchronous
+    // central trace in the next phase, and its AT flux is not read.
+    if (t < V * NF) {
+      const int fl = gfl;
+      if (gv >= Vg) {   // padded species: nothing in the ring
+        sWa[gv][fl] = 0.0;
+        if (fl >= 1 && fl <= TE + 1) sFat[gv][fl - 1] = 0.0;
+      } else if (a.at_in) {
+        int f = e0 - 1 + fl;
+        if (periodic || (f >= 0 && f <= E)) {
+          sWa[gv][fl] = g_w[0];
+          if (fl >= 1 && fl <= TE + 1) sFat[gv][fl - 1] = g_f[0];
+        }
+      } else if (gfi >= 0 && gk > 0) {
+        double acw, acf;
+        at_combine(a, q_at, gk, step_mod(n, a.ring.D), stage, gfi, gv, g_w, g_f, acw, acf);
+        sWa[gv][fl] = acw;
+        if (fl >= 1 && fl <= TE + 1) sFat[gv][fl - 1] = acf;
+      }
     }
   }
   const int nmod = step_mod(n, a.ring.D);   // the current level's ring slot
@@ -392,70 +451,6 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     stride = Lds::NHP;
     return es ? &sTm[0][ff + 1 + es] : &sTp[0][ff + 1 + es];
   };
-  // 1. traces of w and values at the nodes; then the AT combinations of past levels (Eq. (7)) of
-  //    the central traces and of the fluxes at delayed PE interfaces, from the history gathered
-  //    by the load phase
-  for (int idx = t; idx < V * NH; idx += NTH) {
-    const int v = idx / NH, l = idx % NH;
-    // transmissive ends: the ghost element beyond a boundary face carries the interior trace
-    // at that face on both of its sides (ghost trace = interior trace); elements further out
-    // are never read
-    int src = l, ghost = 0;
-    if (!periodic) {
-      const int e = e0 - 2 + l;
-      if (e < 0) { ghost = e == -1 ? 1 : 3; src = l + 1; }
-      else if (e >= E) { ghost = e == E ? 2 : 3; src = l - 1; }
-    }
-    OpT sm = 0, sp = 0;
-#pragma unroll
-    for (int j = kMixed ? 1 : 0; j < M; ++j) {
-      const OpT c = (OpT)sW[v * M + j][src];
-      sp += c;
-      sm += (j & 1) ? -c : c;
-    }
-    double tm, tp;
-    if constexpr (kMixed) {
-      tm = sW[v * M][src] + (double)sm;
-      tp = sW[v * M][src] + (double)sp;
-    } else {
-      tm = (double)sm;
-      tp = (double)sp;
-    }
-    if (ghost == 1) tp = tm;
-    else if (ghost == 2) tm = tp;
-    else if (ghost == 3) tm = tp = 0.0;
-    sTm[v][l] = tm;
-    sTp[v][l] = tp;
-  }
-  for (int idx = t; idx < V * NN; idx += NTH) {
-    const int v = idx / NN, p = idx % NN;
-    const int qn = p % Q, l = p / Q + 2;
-    OpT xo = 0;
-#pragma unroll
-    for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)sB[qn][j] * (OpT)sW[v * M + j][l];
-    sX[v][p] = kMixed ? sW[v * M][l] + (double)xo : (double)xo;
-  }
-  // the AT combinations of the gathered levels, last: their loads have had the longest to land
-  if (t < V * NF) {
-    const int v = t / NF, fl = t % NF;
-    const int i = sI[fl], k = sK[fl];
-    if (i >= 0 && k > 0) {
-      if (v >= Vg) {   // padded species: nothing in the ring
-        sWa[v][fl] = 0.0;
-        if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = 0.0;
-      } else if (a.at_in) {
-        sWa[v][fl] = g_w[0];
-        if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = g_f[0];
-      } else {
-        double acw, acf;
-        at_combine(a, q_at, k, nmod, stage, i, v, g_w, g_f, acw, acf);
-        sWa[v][fl] = acw;
-        if (fl >= 1 && fl <= TE + 1) sFat[v][fl - 1] = acf;
-      }
-    }
-  }
-  __syncthreads();
-
   // 2. central traces; face fl sits between local elements fl (left) and fl + 1 (right).
   //    The synchronous value of a PE interface is published for this level.
   for (int idx = t; idx < V * NF; idx += NTH) {
