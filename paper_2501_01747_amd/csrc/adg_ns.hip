@@ -224,10 +224,10 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   bool ok = true;
 
   // 0. mechanism, operator tables, state of the tile and its halo, PE-interface data of the
-  //    faces, then the traces, the nodal values and the AT combinations of past levels
-  //    (Eq. (7)) formed from the loaded registers.  Every global load is issued first, and
-  //    nothing before them depends on a loaded value (the step counter included), so the
-  //    phase costs about one memory latency plus the arithmetic of its lanes.
+  //    faces, then the traces, the nodal values, the central traces and the AT combinations of
+  //    past levels (Eq. (7)) formed from the loaded registers.  Every global load is issued
+  //    first, and nothing before them depends on a loaded value (the step counter included),
+  //    so the phase costs about one memory latency plus the arithmetic of its lanes.
   constexpr int kOut = (V * M * TE + NTH - 1) / NTH;
   // the second operand of the RK combination (w^n, or the 2N register) of the outputs
   // this thread writes in the last phase
@@ -235,12 +235,15 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   const double *prev = rk.two_n ? kbuf : w0;
   double w0pre[kOut];
   long long n;
-  // the element item of this lane (at most one per lane): variable t / NH of local element
-  // t % NH (element e0 - 2 + t % NH); it loads the element's modes and forms its traces and,
-  // inside the tile, its nodal values
-  static_assert(V * NH <= NTH, "one element item per lane");
-  // the history gather of this lane (at most one item per lane): variable t / NF at face t % NF
-  static_assert(V * NF <= NTH, "one history gather item per lane");
+  // element items: lane jw of wavefront w < kEW holds variable w * VPW + jw / NH at local
+  // element el = jw % NH (element e0 - 2 + el), so the NH elements of a variable sit in
+  // consecutive lanes of one wavefront.  It loads the element's modes, forms its traces and,
+  // inside the tile, its nodal values, and owns the face right of it (face fl = el, between
+  // local elements el and el + 1, for el < NF): the next lane's left trace completes the
+  // central trace, and the item gathers the face's past levels.
+  constexpr int VPW = 64 / NH;   // variables per wavefront
+  constexpr int kEW = (V + VPW - 1) / VPW;
+  static_assert(kEW * 64 <= NTH, "one element item per lane");
   {
     constexpr int nwords = (int)(sizeof(NsMechT<NS>) / 8);
     constexpr int kMw = (nwords + NTH - 1) / NTH;
@@ -251,26 +254,31 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     const unsigned long long *tsrc = reinterpret_cast<const unsigned long long *>(&a.tb);
     unsigned long long *tdst = reinterpret_cast<unsigned long long *>(&Ls.sTb);
     unsigned long long mw[kMw], tw[kTw];
-    // the interface of the gather item's face: loaded first, so the history loads that depend
-    // on it need not wait for the state
-    const int gv = t / NF, gfl = t % NF;
-    const bool gather = t < V * NF && gv < Vg;
+    const int jw = t & 63;
+    const int ev = (t >> 6) * VPW + jw / NH, el = jw % NH;
+    const bool eitem = t < kEW * 64 && jw < VPW * NH && ev < V;
+    const bool real = eitem && ev < Vg;   // a stored variable (padded species stay zero)
+    const bool hasface = eitem && el < NF;
+    // the interface of the item's face: loaded first, so the history loads that depend on it
+    // need not wait for the state
     int gfi = -1, gk = 0;
+    double gkc = 0.0;
     double g_w[4], g_f[4];
-    if (gather) {
-      int f = e0 - 1 + gfl;
+    if (hasface && real) {
+      int f = e0 - 1 + el;
       if (periodic) {
         while (f < 0) f += E;
         while (f >= E) f -= E;
       }
-      if (a.at_in) {
-        // carried from the previous launch: no dependence on the interface index
-        if (f >= 0 && f <= E) {
-          g_w[0] = a.at_in[(size_t)f * (2 * Vg + 1) + gv];
-          g_f[0] = a.at_in[(size_t)f * (2 * Vg + 1) + Vg + gv];
+      if (f >= 0 && f <= E) {
+        gfi = a.face_if[f];
+        if (a.at_in) {
+          // carried from the previous launch: no dependence on the interface index
+          const double *rec = a.at_in + (size_t)f * (2 * Vg + 1);
+          g_w[0] = rec[ev];
+          g_f[0] = rec[Vg + ev];
+          gkc = rec[2 * Vg];
         }
-      } else {
-        gfi = f >= 0 && f <= E ? a.face_if[f] : -1;
       }
     }
 #pragma unroll
@@ -283,10 +291,9 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       const int idx = t + m * NTH;
       tw[m] = idx < twords ? tsrc[idx] : 0ull;
     }
-    // the element item: at a transmissive end the ghost element beyond a boundary face carries
-    // the interior trace at that face on both of its sides (ghost trace = interior trace), so
-    // its lane loads the interior element; elements further out are never read
-    const int ev = t / NH, el = t % NH;
+    // at a transmissive end the ghost element beyond a boundary face carries the interior trace
+    // at that face on both of its sides (ghost trace = interior trace), so its lane loads the
+    // interior element; elements further out are never read
     int ghost = 0, esrc = e0 - 2 + el;
     if (!periodic) {
       if (esrc < 0) { ghost = esrc == -1 ? 1 : 3; esrc += 1; }
@@ -300,8 +307,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       wl[j] = 0.0;
-      // padded species stay zero
-      if (t < V * NH && ev < Vg && ghost != 3) wl[j] = ws[sidx(esrc, ev * M + j, VMg)];
+      if (real && ghost != 3) wl[j] = ws[sidx(esrc, ev * M + j, VMg)];
     }
     int fi = -1;
     double kc = 0.0;   // the carried delay of the face
@@ -322,17 +328,26 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       if (use_prev && idx < V * M * TE && el2 < nloc && c < VMg) w0pre[m] = prev[sidx(e0 + el2, c, VMg)];
     }
     n = a.step[par];
-    // levels 0..3 of the gather item (a level past q reads level n-k with weight 0); they land
-    // while the element items form their traces and nodal values
+    const int nm = step_mod(n, a.ring.D);   // the current level's ring slot
+    // the carried delays are first used here, after every load has been issued (left to itself
+    // the compiler converts them to int right after their loads, which waits for those loads
+    // before the rest are issued)
+    asm volatile("" : "+v"(gkc), "+v"(kc));
+    // levels 0..3 of the item's face (a level past q reads level n-k with weight 0); they land
+    // while the items form their traces and nodal values.  Carried: the previous launch drew
+    // the delay (a step before q, which has no predecessor after a reset, has only zero delays).
     if (gfi >= 0) {
-      gk = eff_delay<true>(a.dl, n, gfi);
-      if (gk > 0) {
-        const int nm = step_mod(n, a.ring.D);
+      if (a.at_in) {
+        gk = n >= q_at ? (int)gkc : 0;
+      } else {
+        gk = eff_delay<true>(a.dl, n, gfi);
+        if (gk > 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double *rec = ring_at(a.ring, ring_slot(nm, gk + (j < q_at ? j : 0), a.ring.D), stage, a.dl.nif, gfi);
-          g_w[j] = rec[a.ring.off_Wc + gv];
-          g_f[j] = rec[a.ring.off_F + gv];
+          for (int j = 0; j < 4; ++j) {
+            const double *rec = ring_at(a.ring, ring_slot(nm, gk + (j < q_at ? j : 0), a.ring.D), stage, a.dl.nif, gfi);
+            g_w[j] = rec[a.ring.off_Wc + ev];
+            g_f[j] = rec[a.ring.off_F + ev];
+          }
         }
       }
     }
@@ -348,14 +363,11 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     }
     if (t < NF) {
       sI[t] = fi;
-      // carried: the previous launch drew it (a step before q, which has no predecessor after a
-      // reset, has only zero delays)
       sK[t] = fi < 0 ? 0 : a.at_in ? (n >= q_at ? (int)kc : 0) : eff_delay<true>(a.dl, n, fi);
     }
-    // traces of w and values at the nodes of the element item
-    if (t < V * NH) {
-#pragma unroll
-      for (int j = 0; j < M; ++j) sW[ev * M + j][el] = ghost ? 0.0 : wl[j];
+    // traces, nodal values and central traces of the element items: every lane of their
+    // wavefronts takes part in the lane move (lanes without an item hold zeros)
+    if (t < kEW * 64) {
       OpT sm = 0, sp = 0;
 #pragma unroll
       for (int j = kMixed ? 1 : 0; j < M; ++j) {
@@ -374,37 +386,47 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       if (ghost == 1) tp = tm;
       else if (ghost == 2) tm = tp;
       else if (ghost == 3) tm = tp = 0.0;
-      sTm[ev][el] = tm;
-      sTp[ev][el] = tp;
-      if (el >= 2 && el < TE + 2) {
+      const double tm_right = dpp_move<kDppFromNext>(tm);   // left trace of element el + 1
+      if (eitem) {
 #pragma unroll
-        for (int qn = 0; qn < Q; ++qn) {
-          OpT xo = 0;
+        for (int j = 0; j < M; ++j) sW[ev * M + j][el] = ghost ? 0.0 : wl[j];
+        sTm[ev][el] = tm;
+        sTp[ev][el] = tp;
+        if (el >= 2 && el < TE + 2) {
 #pragma unroll
-          for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)a.tb.B[qn][j] * (OpT)wl[j];
-          sX[ev][(el - 2) * Q + qn] = kMixed ? wl[0] + (double)xo : (double)xo;
+          for (int qn = 0; qn < Q; ++qn) {
+            OpT xo = 0;
+#pragma unroll
+            for (int j = kMixed ? 1 : 0; j < M; ++j) xo += (OpT)a.tb.B[qn][j] * (OpT)wl[j];
+            sX[ev][(el - 2) * Q + qn] = kMixed ? wl[0] + (double)xo : (double)xo;
+          }
         }
       }
-    }
-    // the AT combinations of the gathered levels, last: their loads have had the longest to
-    // land.  A face that turns out not to be delayed has its entry replaced by the synchronous
-    // central trace in the next phase, and its AT flux is not read.
-    if (t < V * NF) {
-      const int fl = gfl;
-      if (gv >= Vg) {   // padded species: nothing in the ring
-        sWa[gv][fl] = 0.0;
-        if (fl >= 1 && fl <= TE + 1) sFat[gv][fl - 1] = 0.0;
-      } else if (a.at_in) {
-        int f = e0 - 1 + fl;
-        if (periodic || (f >= 0 && f <= E)) {
-          sWa[gv][fl] = g_w[0];
-          if (fl >= 1 && fl <= TE + 1) sFat[gv][fl - 1] = g_f[0];
+      if (hasface) {
+        // central trace; the synchronous one of a PE interface is published for this level
+        // (faces e0 .. e0+nloc-1 are owned by this tile).  The AT combination of the face's
+        // gathered levels takes its place at a delayed PE interface.
+        const double wc = kMixed ? 0.5 * (tp + tm_right) : (double)((OpT)0.5 * ((OpT)tp + (OpT)tm_right));
+        sWc[ev][el] = wc;
+        double wa = wc;
+        if (!real) {   // padded species: nothing in the ring
+          wa = 0.0;
+          if (el >= 1 && el <= TE + 1) sFat[ev][el - 1] = 0.0;
+        } else if (gfi >= 0) {
+          if (el >= 1 && el <= nloc) ring_at(a.ring, nm, stage, a.dl.nif, gfi)[a.ring.off_Wc + ev] = wc;
+          if (gk > 0) {
+            double acw, acf;
+            if (a.at_in) {
+              acw = g_w[0];
+              acf = g_f[0];
+            } else {
+              at_combine(a, q_at, gk, nm, stage, gfi, ev, g_w, g_f, acw, acf);
+            }
+            wa = acw;
+            if (el >= 1 && el <= TE + 1) sFat[ev][el - 1] = acf;
+          }
         }
-      } else if (gfi >= 0 && gk > 0) {
-        double acw, acf;
-        at_combine(a, q_at, gk, step_mod(n, a.ring.D), stage, gfi, gv, g_w, g_f, acw, acf);
-        sWa[gv][fl] = acw;
-        if (fl >= 1 && fl <= TE + 1) sFat[gv][fl - 1] = acf;
+        sWa[ev][el] = wa;
       }
     }
   }
@@ -451,19 +473,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     stride = Lds::NHP;
     return es ? &sTm[0][ff + 1 + es] : &sTp[0][ff + 1 + es];
   };
-  // 2. central traces; face fl sits between local elements fl (left) and fl + 1 (right).
-  //    The synchronous value of a PE interface is published for this level.
-  for (int idx = t; idx < V * NF; idx += NTH) {
-    const int v = idx / NF, fl = idx % NF;
-    const double wc = kMixed ? 0.5 * (sTp[v][fl] + sTm[v][fl + 1])
-                             : (double)((OpT)0.5 * ((OpT)sTp[v][fl] + (OpT)sTm[v][fl + 1]));
-    const int i = sI[fl];
-    if (i >= 0 && fl >= 1 && fl <= nloc && v < Vg)   // faces e0 .. e0+nloc-1 are owned by this tile
-      ring_at(a.ring, nmod, stage, a.dl.nif, i)[a.ring.off_Wc + v] = wc;
-    sWc[v][fl] = wc;
-    if (i < 0 || sK[fl] == 0) sWa[v][fl] = wc;
-  }
-  //    Beside them, the species sums of the mixture chain: the internal energy
+  // 2. the species sums of the mixture chain: the internal energy
   //    e(T) = sum_i Y_i R_i [T (a_i0 - 1 + T (a_i1/2 + ...)) + a_i5] is one quintic in T whose
   //    coefficients are rho^-1 sum_i rho_i R_i (a_i0 - 1), ..., and R = rho^-1 sum_i rho_i R_i
   //    (rows 0..6); row 7 holds e* = E/rho - u^2/2 (with 1/rho and u beside it).  One lane per
