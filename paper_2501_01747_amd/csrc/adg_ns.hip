@@ -517,10 +517,11 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
       else mixture_row7(p, vrow, vs);
     }
   }
-  __syncthreads();
 
-  // 3. gradients at the points.  The LDG gradient of the element with gradient slot lq (left
-  //    face lq, right face lq + 1) has modes q_j = (2j+1)/dx [w*_R - (-1)^j w*_L - sum_k D_jk w_k];
+  // 3. gradients at the points, in the same phase as the species sums: both read only what the
+  //    load phase wrote, and neither reads what the other writes.  The LDG gradient of the
+  //    element with gradient slot lq (left face lq, right face lq + 1) has modes
+  //    q_j = (2j+1)/dx [w*_R - (-1)^j w*_L - sum_k D_jk w_k];
   //    its value at a point of row r (node r < Q, the right end xi = +1 for r = Q, the left end
   //    for r = Q + 1) is sum_j P_j(xi_r) q_j = (A_r w*_R - B_r w*_L - sum_k G_rk w_k)/dx, with the
   //    tabulated A_r = sum_j (2j+1) P_j(xi_r), B_r = sum_j (-1)^j (2j+1) P_j(xi_r) and
