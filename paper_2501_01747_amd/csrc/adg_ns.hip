@@ -476,9 +476,18 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   // 2. the species sums of the mixture chain: the internal energy
   //    e(T) = sum_i Y_i R_i [T (a_i0 - 1 + T (a_i1/2 + ...)) + a_i5] is one quintic in T whose
   //    coefficients are rho^-1 sum_i rho_i R_i (a_i0 - 1), ..., and R = rho^-1 sum_i rho_i R_i
-  //    (rows 0..6); row 7 holds e* = E/rho - u^2/2 (with 1/rho and u beside it).  One lane per
-  //    (point, row) when the workgroup has a lane for each; else one per (point, rows g and
-  //    g + 4), reading the point's species once for both.
+  //    (rows 0..6); row 7 holds e* = E/rho - u^2/2 (with 1/rho and u beside it).  The sums take
+  //    the first lanes and the gradients of the next step the last ones, laid out so that where
+  //    the workgroup has the lanes no lane forms both: one lane per (point, row) (layout 0);
+  //    one per (point, rows g and g + 4) for g < 3, one per (point, row 3) and one per
+  //    (point, row 7) (layout 1); else one per (point, rows g and g + 4), the g = 3 lane also
+  //    forming row 7 (layout 2).  A lane reads the point's species once for its rows.
+  constexpr int VH1 = V, VH2 = (V + 1) / 2, VH3 = (V + 2) / 3;
+  constexpr bool kFit0 = 8 * NP + VH1 * NP <= NTH;
+  constexpr int kFit1 = 5 * NP + VH1 * NP <= NTH ? 1 : 5 * NP + VH2 * NP <= NTH ? 2 : 5 * NP + VH3 * NP <= NTH ? 3 : 0;
+  constexpr int kMixLayout = kFit0 ? 0 : kFit1 ? 1 : 8 * NP <= NTH ? 0 : 2;
+  // variables per lane of the gradients
+  constexpr int VPL = kFit0 ? 1 : kFit1 ? kFit1 : V * NP > NTH ? 2 : 1;
   auto mixture_row7 = [&](int p, const double *vrow, int vs) {
     const double rho_inv = 1.0 / vrow[0];
     const double u = vrow[vs] * rho_inv;
@@ -486,7 +495,7 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
     sU[p] = u;
     sMix[7][p] = vrow[2 * vs] * rho_inv - 0.5 * u * u;
   };
-  if constexpr (8 * NP <= NTH) {
+  if constexpr (kMixLayout == 0) {
     if (t < 8 * NP) {
       const int q = t / NP, p = t % NP;
       int vs;
@@ -498,6 +507,25 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
 #pragma unroll
         for (int i = 0; i < NS; ++i) sum += vrow[(3 + i) * vs] * mk->ek[i][q];
         sMix[q][p] = sum;
+      }
+    }
+  } else if constexpr (kMixLayout == 1) {
+    if (t < 5 * NP) {
+      const int g = t / NP, p = t % NP;
+      int vs;
+      const double *vrow = values(p, vs);
+      if (g == 4) {
+        mixture_row7(p, vrow, vs);
+      } else {
+        double lo = 0.0, hi = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const double x = vrow[(3 + i) * vs];
+          lo += x * mk->ek[i][g];
+          if (g < 3) hi += x * mk->ek[i][g + 4];
+        }
+        sMix[g][p] = lo;
+        if (g < 3) sMix[g + 4][p] = hi;
       }
     }
   } else {
@@ -528,11 +556,12 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   //    G_rk = sum_j (2j+1) P_j(xi_r) D_jk.  Since D_j0 = 1 - (-1)^j, A_r - B_r = G_r0 and the mean
   //    cancels: the mixed path forms the face terms against it in FP64 and the rest in FP32.
   //    A lane forms the gradients of VPL variables (v, v + VH, ...) at its point, reading the
-  //    point's table row once: two when one variable per lane would take more than one pass.
+  //    point's table row once; where the lanes suffice for both the items are taken from the
+  //    last lane down, clear of the sums.
   {
-    constexpr int VPL = V * NP > NTH ? 2 : 1;
     constexpr int VH = (V + VPL - 1) / VPL;
-    for (int idx = t; idx < VH * NP; idx += NTH) {
+    constexpr bool kFromTop = kFit0 || kFit1 != 0;
+    for (int idx = kFromTop ? NTH - 1 - t : t; idx < VH * NP; idx += NTH) {
       const int h = idx / NP, p = idx % NP;
       int lq, r;
       point_slot(p, lq, r);
