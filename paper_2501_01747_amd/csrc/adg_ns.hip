@@ -30,7 +30,6 @@ namespace adg {
 
 constexpr int kThreadsBatch = 256;   // batched kernel: more resident workgroups per CU
 constexpr int kBatchLanesPerPoint = 4;   // batched kernel: lanes per point of the point phase
-constexpr int kThreadsSingle = 512;  // one problem: more lanes per tile, shorter phases
 
 // Sum over the LP lanes of a point group (every lane receives the same value:
 // the pairwise sums are formed in the same order on every lane).  Groups of up to
@@ -176,7 +175,6 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   constexpr int V = 3 + NS, Q = M;
   using Lds = NsLds<M, NS, TE, NRC>;
   constexpr int NH = Lds::NH, NF = Lds::NF, NN = Lds::NN;
-  constexpr int NT = 2 * (TE + 1);  // face traces; trace pp <-> face e0 + pp/2, side pp%2
   auto &sW = Ls.sW;
   auto &sTm = Ls.sTm;
   auto &sTp = Ls.sTp;
@@ -202,7 +200,6 @@ __device__ __forceinline__ void ns_tile(const NsArgs &a, const double *__restric
   auto &sInvT = Ls.sInvT;
   auto &sF = Ls.sF;
   auto &sFat = Ls.sFat;
-  auto &sB = Ls.sTb.B;
   auto &sWG = Ls.sTb.WG;
   auto &sWB = Ls.sTb.WB;
   auto &sGD = Ls.sTb.GD;
