@@ -50,9 +50,10 @@ def compare(adg, orc, case, w0, steps, every, tol=1e-10):
     return worst
 
 
-@pytest.mark.parametrize("E,P", [(1, 1), (5, 2), (8, 3), (13, 4), (64, 8), (100, 7)])
+@pytest.mark.parametrize("E,P", [(1, 1), (5, 2), (8, 3), (13, 4), (64, 8), (100, 7), (24, 24)])
 def test_small_sizes(adg, orc, mech, E, P):
-    """Tiles of 8 elements: a single element, fewer elements than a halo, a ragged tail."""
+    """Tiles of 8 elements: a single element, fewer elements than a halo, a ragged tail, and one
+    element per PE (every face a PE interface)."""
     case, w0 = gen.case_c1(E=E, n_pe=P, mech=mech, Lx=0.01 * E / 64)
     compare(adg, orc, case, w0, 12, every=4)
 
