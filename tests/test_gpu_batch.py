@@ -36,10 +36,10 @@ def ns_case(mech, E, P, n_pe, mode, seed):
 
 def mixed_cases(mech):
     """Detailed-chemistry instances of every order, delay model, ragged tile tail and PE count
-    (N_p = 4 under SAA: AT combinations of q = 5 levels gathered from the ring), periodic and
-    transmissive."""
+    (N_p = 4 under SAA: AT combinations of q = 5 levels gathered from the ring; one element per PE:
+    every face gathers), periodic and transmissive."""
     spec = [(40, 1, 3, "saa", 11), (64, 2, 4, "caa", 12), (29, 3, 5, "saa", 13), (48, 4, 2, "sync", 14),
-            (100, 3, 7, "saa", 15), (8, 2, 1, "saa", 16), (56, 4, 3, "saa", 17)]
+            (100, 3, 7, "saa", 15), (8, 2, 1, "saa", 16), (56, 4, 3, "saa", 17), (16, 3, 16, "saa", 20)]
     cases = [ns_case(mech, *s) for s in spec]
     # transmissive ends: at both ends of a longer mesh, and both in one tile of a mesh shorter
     # than a tile
